@@ -1,0 +1,194 @@
+"""Benchmark: segment-group updates per second of the planar-MOC power iteration on one
+MI355X, plus time to a 1e-6 residual, beside the FP64 CPU oracle.
+
+A step is one power iteration of the whole path: source update, transport sweep (the
+dominant kernel), scalar-flux finalisation, FP64 eigenvalue update, normalisation and
+residual. The workload is the 51 x 51 pin lattice (about 1.2M triangular regions,
+7 groups, 128 azimuthal x 3 polar directions, 0.01 cm spacing, vacuum on two sides),
+synthetic seeded inputs. `value` = U / (wall time per step), U = 2 P G S segment-group
+updates per sweep.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and derived ALU peak
+HBM_PEAK_GBS = 8000.0
+N_CU, CLOCK_GHZ = 256, 2.4
+FP32_NONPACKED_TFLOPS = N_CU * 64 * 2 * CLOCK_GHZ / 1000.0      # FMA = 2 flops, no packed FP32
+FLOPS_PER_UPDATE = 7     # tau mul, 1 - e^-tau (1), psi - q, * F, psi -= d, tally fma (2)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=3, help="problem recipe (3 = 51x51 lattice)")
+    ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--exp-mode", default="poly")
+    return ap.parse_args()
+
+
+def time_iterations(s, steps, warmup):
+    import torch
+    s.run_iterations(warmup)
+    torch.cuda.synchronize()
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = s.run_iterations(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile()
+    s.set_profiling(False)
+    return (t1 - t0) * 1e3 / steps, prof, r
+
+
+def algorithmic_bytes(info, precision):
+    """Bytes one sweep launch must move at minimum: the segment stream once
+    (length + region id), Sigma_t and qhat read once, the tally read-modify-written once,
+    boundary fluxes read and written once."""
+    R, G, P, T, S = (info["n_regions"], info["n_groups"], info["n_polar"], info["n_tracks"],
+                     info["n_segments"])
+    rb = 8 if precision == "f64" else 4
+    seg = S * (rb + 4)
+    xs = 2 * R * G * rb
+    tally = 2 * R * G * 8
+    psi = 2 * T * 2 * P * G * rb
+    return seg + xs + tally + psi
+
+
+def cpu_baseline(workload):
+    """The FP64 oracle, single-threaded, timed on a bounded sample of the workload: the
+    same pin-cell template, track spacing and quadrature on a 6 x 6 pin window."""
+    import numpy as np
+    from oracle.oracle import Oracle
+    from paper_2607_01591_amd import problems as P
+    if workload == 3:
+        prob = P.square_lattice(6, 6, seed=3, m=5, n_fuel_rings=5, n_mod_rings=7, n_azim=128,
+                                spacing=0.01, bc=(1, 0, 1, 0), name="cfg3_window6x6")
+        sample = "one FP64 oracle sweep of a 6x6-pin window of the 51x51 lattice (same template, A=128, P=3, 0.01 cm)"
+    else:
+        prob = P.config(workload)
+        sample = f"one FP64 oracle sweep of workload {workload}"
+    o = Oracle.from_problem(prob)
+    src = np.ones((o.R, o.G))
+    o.sweep(src)                      # warm caches
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        o.sweep(src)
+        n += 1
+        if time.perf_counter() - t0 > 8.0:
+            break
+    dt = (time.perf_counter() - t0) / n
+    U = 2 * o.P * o.G * o.S
+    return {"value": U / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; {n} sweeps, U={U:.3e} per sweep, {dt:.2f} s per sweep"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2607_01591_amd import moc
+    from paper_2607_01591_amd import problems as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"generating workload {args.workload}")
+    prob = P.config(args.workload)
+    log("creating FP32 context (host tracking + upload)")
+    s32 = moc.Solver(prob, precision="f32", exp_mode=args.exp_mode, check_every=1 << 30)
+    info = s32.info
+    log(f"R={info['n_regions']} T={info['n_tracks']} S={info['n_segments']} U={info['n_updates']} "
+        f"setup {info['setup_ms']:.0f} ms, device {info['device_bytes'] / 2**30:.2f} GiB")
+    ms, prof, r = time_iterations(s32, args.steps, args.warmup)
+    U = info["n_updates"]
+    sweep_ms = prof["sweep_ms"] / max(1, prof["sweeps"])
+    log(f"FP32: {ms:.3f} ms/iteration, sweep kernel {sweep_ms:.3f} ms avg over {prof['sweeps']}, "
+        f"k={r['k']:.6f}")
+    value = U / (ms * 1e-3)
+    achieved = U * FLOPS_PER_UPDATE / (sweep_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_NONPACKED_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_NONPACKED_TFLOPS, "traffic": None,
+                "kernel": "k_sweep<float,3,7,POLY>", "kernel_ms": sweep_ms,
+                "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": U}
+    alg_bytes = algorithmic_bytes(info, "f32")
+    hbm = {"algorithmic_bytes": alg_bytes, "achieved_GBs": alg_bytes / (sweep_ms * 1e-3) / 1e9,
+           "frac_of_8TBs": alg_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del s32
+    torch.cuda.empty_cache()
+
+    fp64 = None
+    if not args.no_f64:
+        log("creating FP64 context")
+        s64 = moc.Solver(prob, precision="f64", check_every=1 << 30)
+        ms64, prof64, r64 = time_iterations(s64, max(3, args.steps // 4), 1)
+        sw64 = prof64["sweep_ms"] / max(1, prof64["sweeps"])
+        fp64 = {"updates_per_s": U / (ms64 * 1e-3), "ms_per_step": ms64, "sweep_kernel_ms": sw64}
+        log(f"FP64: {ms64:.3f} ms/iteration, sweep kernel {sw64:.3f} ms")
+        del s64
+        torch.cuda.empty_cache()
+
+    solve = None
+    if not args.no_solve:
+        log("cold solve to 1e-6 on a 17x17 lattice (held-out seed 200000)")
+        p5 = P.config(5, seed=200000)
+        s5 = moc.Solver(p5, precision="f32", max_iter=20000)
+        r5 = s5.solve(1e-6)
+        solve = {"workload": "17x17 lattice seed 200000, FP32 sweep", "cold_iterations": r5["iterations"],
+                 "cold_wall_ms": r5["wall_ms"], "converged": r5["converged"], "k": r5["k"],
+                 "warm": None}
+        log(f"cold solve: {r5['iterations']} iterations, {r5['wall_ms']:.0f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the FP64 CPU oracle on a bounded sample")
+        cpu = cpu_baseline(args.workload)
+        log(f"oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} core")
+
+    out = {
+        "metric": "segment-group updates/s (FP32 sweep power iteration)",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{prob.name}: {info['n_regions']} regions, {info['n_groups']} groups, "
+                               f"A={prob.n_azim} x P={prob.n_polar}, spacing {prob.spacing} cm",
+                   "regions": info["n_regions"], "groups": info["n_groups"], "tracks": info["n_tracks"],
+                   "segments": info["n_segments"], "updates_per_sweep": U},
+        "roofline": roofline,
+        "hbm_view": hbm,
+        "fp64": fp64,
+        "time_to_tol": solve,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

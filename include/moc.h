@@ -1,0 +1,230 @@
+/*
+ * moc.h -- C ABI of libmoc: flat-source planar Method of Characteristics on
+ * unstructured 2D triangular meshes, for AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the steady multigroup k-eigenvalue (or fixed-source) transport
+ * equation with isotropic scattering (paper Sec. 2, Eq. MGNTE and Eq. MGNTE_element)
+ * by the planar method of characteristics (Sec. 2.1): every mesh region is a flat-
+ * source region, straight cyclic tracks are laid on the bounding box of the domain
+ * and intersected with the mesh (Sec. 3.1), and along each segment the angular flux
+ * is attenuated by Eq. MOC_sol; the scalar flux is the angular integral of the
+ * segment-averaged flux.
+ *
+ * Conventions (all entry points):
+ *   - Every function returns MOC_OK (0) or an error code; nothing throws across the
+ *     boundary. moc_last_error() describes the last failure.
+ *   - "host" pointers are ordinary CPU memory; they are only read during the call and
+ *     may be freed by the caller on return (the library copies what it keeps).
+ *   - "device" pointers are caller-owned HIP device allocations on the context's
+ *     device, contiguous, in the layout stated; the library never frees them.
+ *   - Region-indexed arrays [R][G] are in the caller's region numbering
+ *     (row-major, group fastest). Groups are numbered from fastest (0) to slowest.
+ *   - Scattering matrices are sigma_s[m][g_from][g_to].
+ *   - Calls on one context must be serialised by the caller; separate contexts are
+ *     independent. A context is bound to the HIP device named in its options.
+ */
+#ifndef MOC_H
+#define MOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MOC_OK 0
+#define MOC_EINVAL 1   /* invalid argument: bad topology, Sigma_t <= 0, null pointer ... */
+#define MOC_ENOMEM 2   /* host or device allocation failed */
+#define MOC_EHIP 3     /* a HIP runtime call or kernel launch failed */
+#define MOC_ENOCONV 4  /* moc_solve reached max_iter; the result is still filled in */
+#define MOC_ESTATE 5   /* call not valid in the context's current state */
+
+/* boundary conditions, per domain side */
+#define MOC_BC_VACUUM 0
+#define MOC_BC_REFLECTIVE 1
+
+/* domain shapes */
+#define MOC_DOMAIN_BOX 0      /* axis-aligned rectangle box[0..3] = x0, y0, x1, y1 */
+#define MOC_DOMAIN_HEXAGON 1  /* regular hexagon centred in box, flats parallel to x */
+
+/* sweep precision */
+#define MOC_PREC_F32 0   /* FP32 sweep; FP64 source, eigenvalue, norms and tallies */
+#define MOC_PREC_F64 1   /* FP64 everywhere (same kernels instantiated in double) */
+
+/* evaluation of 1 - exp(-tau) in the FP32 sweep (the FP64 sweep always uses expm1) */
+#define MOC_EXP_POLY 0   /* hardware exp2 for large tau, Taylor polynomial for small tau */
+#define MOC_EXP_TABLE 1  /* linear interpolation in a table of (1 - e^-x)/x */
+#define MOC_EXP_LIBM 2   /* device libm expm1f */
+
+/* moc_result.flags */
+#define MOC_FLAG_FELL_BACK_TO_COLD 1  /* the initial guess was rejected; cold start used */
+#define MOC_FLAG_FIXED_SOURCE 2       /* an external source was set: source iteration */
+
+typedef struct moc_ctx moc_ctx;
+
+/* Mesh: triangles are the elements; a region (flat-source region, Sec. 2.1) is a set
+ * of triangles (one triangle per region is the usual case). */
+typedef struct {
+    int32_t n_vertices;
+    const double *xy;              /* host [n_vertices][2] */
+    int32_t n_triangles;
+    const int32_t *tri;            /* host [n_triangles][3], counter-clockwise */
+    const int32_t *tri_region;     /* host [n_triangles], values in [0, n_regions) */
+    int32_t n_regions;
+    const int32_t *region_material;/* host [n_regions], values in [0, n_materials) */
+    int32_t domain;                /* MOC_DOMAIN_* */
+    double box[4];                 /* bounding box x0, y0, x1, y1 of the domain */
+    double hex_apothem;            /* hexagon: centre-to-flat distance */
+    int32_t bc[6];                 /* box: x = x0, x = x1, y = y0, y = y1; hexagon: 6 sides */
+} moc_mesh;
+
+/* Tracking parameters (Sec. 3.1, modular rays on the whole-domain bounding box). */
+typedef struct {
+    int32_t n_azim;         /* azimuthal directions over [0, 2 pi), a positive multiple of 4 */
+    int32_t n_polar;        /* polar angles per hemisphere, 1..4 */
+    double spacing;         /* nominal track spacing in cm (the corrected spacing is <= it) */
+    const double *polar_mu; /* host [n_polar] polar cosines, or NULL for half-range Gauss-Legendre */
+    const double *polar_w;  /* host [n_polar] weights summing to 1 (required with polar_mu) */
+} moc_tracks;
+
+/* Multigroup macroscopic cross sections per material (Eq. MGNTE, isotropic part). */
+typedef struct {
+    int32_t n_materials;
+    int32_t n_groups;
+    const double *sigma_t;    /* host [M][G], each > 0 */
+    const double *sigma_s;    /* host [M][G][G], from -> to */
+    const double *nu_sigma_f; /* host [M][G] */
+    const double *chi;        /* host [M][G] */
+} moc_xs;
+
+typedef struct {
+    int32_t precision;   /* MOC_PREC_* */
+    int32_t exp_mode;    /* MOC_EXP_* (FP32 sweep only) */
+    int32_t max_iter;    /* moc_solve iteration limit (<= 0: 10000) */
+    int32_t device;      /* HIP device ordinal; negative: host-only context (tracking,
+                            volumes, quadrature and info only; device calls return
+                            MOC_ESTATE) */
+    int32_t check_every; /* moc_solve reads (k, residual) back every this many iterations (<= 0: 1) */
+    int32_t n_threads;   /* host threads for tracking (<= 0: all hardware threads) */
+} moc_options;
+
+typedef struct {
+    double k;            /* eigenvalue (1 in fixed-source mode) */
+    int32_t iterations;
+    double residual;     /* ||sqrt(V)(phi_n - phi_n-1)|| / ||sqrt(V) phi_n|| of the last iteration */
+    double dk;           /* |k_n - k_n-1| of the last iteration */
+    double wall_ms;      /* host wall time of the solve */
+    int32_t flags;       /* MOC_FLAG_* */
+} moc_result;
+
+typedef struct {
+    int32_t n_regions, n_groups, n_materials, n_polar, n_angles;
+    int32_t n_tracks;          /* T: tracks that cross the domain */
+    int64_t n_segments;        /* S: 2D segments after merging */
+    int64_t n_updates;         /* U = 2 * P * G * S per sweep */
+    int64_t n_padded_steps;    /* segment slots the sweep walks (incl. padding), per sense */
+    int32_t n_batches;         /* 64-track wavefront batches */
+    double setup_ms;           /* host setup time of moc_create */
+    int64_t device_bytes;      /* device memory held by the context */
+    int32_t precision;
+} moc_info;
+
+/* Device-time profile of the sweep kernel, from HIP events recorded on the stream each
+ * sweep kernel is launched on (enabled by moc_set_profiling). */
+typedef struct {
+    int64_t sweeps;       /* sweep kernel launches timed since profiling was enabled */
+    double sweep_ms;      /* total device time of those launches */
+    double sweep_ms_min;  /* shortest launch */
+    double sweep_ms_max;  /* longest launch */
+} moc_profile;
+
+/* Build a solver context (host setup in C++: mesh half-edge structure, cyclic track
+ * laydown, ray tracing by mesh walk, segment merging, boundary links, track volumes,
+ * device packing). All inputs are copied. Errors: MOC_EINVAL (inconsistent topology,
+ * clockwise triangle, non-manifold edge, a region without triangles, material index
+ * out of range, Sigma_t <= 0, n_azim % 4 != 0, n_polar outside 1..4, reflective hexagon,
+ * mesh not covering the domain), MOC_ENOMEM, MOC_EHIP. */
+int moc_create(const moc_mesh *mesh, const moc_tracks *tracks, const moc_xs *xs,
+               const moc_options *opts, moc_ctx **out);
+
+/* Release the context and every device buffer it owns. NULL is allowed. */
+void moc_destroy(moc_ctx *ctx);
+
+/* One transport sweep (Eq. MOC_sol on every segment, direction, polar angle and group)
+ * for a given isotropic emission density. source_dev: device FP64 [R][G], neutrons per
+ * cm^3 per s over all directions (the library divides by 4 pi). scalar_flux_out_dev:
+ * device FP64 [R][G] receives phi = 4 pi qhat + T / (Sigma_t V). Enqueued on the HIP
+ * stream `stream` (NULL = the context's own stream); returns without waiting. Reads the
+ * context's incoming boundary angular fluxes and stores the outgoing ones as the next
+ * sweep's incoming fluxes (reflective sides), so consecutive calls iterate. */
+int moc_sweep(moc_ctx *ctx, const double *source_dev, double *scalar_flux_out_dev, void *stream);
+
+/* Power iteration (or source iteration with an external source) to `tol`: stops when
+ * the residual and |dk| are both below tol. Synchronous on the context's stream. Starts
+ * from the initial guess if one is set (once), else from phi = 1, k = 1, psi = 0.
+ * Returns MOC_ENOCONV at max_iter with `out` filled in. */
+int moc_solve(moc_ctx *ctx, double tol, moc_result *out);
+
+/* Exactly n iterations of the moc_solve loop (same start rules) with a single
+ * read-back of (k, residual) at the end, for timing. `out` holds the last iterate's
+ * values. Returns MOC_OK after n iterations. */
+int moc_run_iterations(moc_ctx *ctx, int n, moc_result *out);
+
+/* Initial guess for the next moc_solve: phi0_dev device FP64 [R][G] (required), k0 > 0,
+ * psi_b0_dev device FP64 [T][2][P][G] incoming boundary fluxes in canonical track order
+ * (NULL: psi = phi0 / 4 pi of the region where each track-sense enters). A guess with a
+ * non-finite or negative entry, or all zeros, is not an error: moc_solve then cold-starts
+ * and sets MOC_FLAG_FELL_BACK_TO_COLD. */
+int moc_set_initial_guess(moc_ctx *ctx, const double *phi0_dev, double k0, const double *psi_b0_dev);
+
+/* Copy the current scalar flux (device FP64 [R][G], user region order). */
+int moc_get_flux(moc_ctx *ctx, double *phi_dev, void *stream);
+
+/* Incoming boundary angular fluxes, device FP64 [T][2][P][G]; tracks in canonical order
+ * (angle index ascending, then perpendicular coordinate -sin(phi) x + cos(phi) y
+ * ascending), sense 0 = along (cos phi, sin phi). Get converts from the sweep precision;
+ * set rounds to it. */
+int moc_get_boundary_flux(moc_ctx *ctx, double *psi_dev, void *stream);
+int moc_set_boundary_flux(moc_ctx *ctx, const double *psi_dev, void *stream);
+
+/* Register a device FP64 [T][2][P][G] buffer that every following sweep fills with the
+ * outgoing angular flux of each track-sense (NULL disables). For tests and diagnostics. */
+int moc_set_exit_flux_buffer(moc_ctx *ctx, double *psi_exit_dev);
+
+/* Fixed-source mode: q_dev device FP64 [R][G] external emission density (copied), or
+ * NULL to return to eigenvalue mode. In fixed-source mode moc_solve iterates
+ * s = Sigma_s^T phi + chi F + q with k = 1 and no normalisation. */
+int moc_set_external_source(moc_ctx *ctx, const double *q_dev);
+
+int moc_get_info(const moc_ctx *ctx, moc_info *info);
+
+/* Enable (non-zero) or disable timing of every sweep kernel launch with a pair of HIP
+ * events on its stream; enabling resets the counters. moc_get_profile waits for the
+ * timed launches to finish and reports them. */
+int moc_set_profiling(moc_ctx *ctx, int enable);
+int moc_get_profile(moc_ctx *ctx, moc_profile *out);
+
+/* Track-estimated region volumes V_r (host FP64 [R], user order). */
+int moc_get_volumes(const moc_ctx *ctx, double *V_host);
+
+/* Tracking dump for tests (host arrays sized from moc_get_info): angle [T],
+ * endpoints [T][4] (x0 y0 x1 y1 along sense 0), offsets [T+1], then the merged
+ * segments region [S] (user ids) and length [S] in double, and links [T][2]
+ * (destination track*2+sense, or -1 for vacuum). Any pointer may be NULL. */
+int moc_get_tracks(moc_ctx *ctx, int32_t *angle, double *endpoints, int64_t *offsets,
+                   int32_t *seg_region, double *seg_length, int32_t *links);
+
+/* Quadrature actually used: per track angle phi, delta, weight [n_angles]; polar
+ * mu, weight [n_polar]. Any pointer may be NULL. */
+int moc_get_quadrature(const moc_ctx *ctx, double *phi, double *delta, double *w_azim,
+                       double *mu, double *w_polar);
+
+/* Description of the last error on this context (ctx NULL: the calling thread's last
+ * moc_create failure). Valid until the next call on the same context or thread. */
+const char *moc_last_error(const moc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOC_H */

@@ -1,0 +1,765 @@
+// C ABI of libmoc (declared in include/moc.h): context creation (host setup + device
+// packing), sweep, power/source iteration, state access. No exception crosses the ABI.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <thread>
+
+#include "moc_kernels.h"
+
+using namespace moc;
+
+#define HIP_OK(call)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess) throw Error(MOC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct moc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Mesh mesh;
+    Quadrature quad;
+    Tracks tracks;
+    DevProblem d;
+    std::vector<int> internal_of_user, user_of_internal;
+    std::vector<int> slot_of_canon;
+    std::vector<double> V_user;
+    std::vector<double> sigt_m_host, nsf_m_host;
+    int64_t S = 0, padded_steps = 0;
+    int64_t device_bytes = 0;
+    double setup_ms = 0;
+    int max_iter = 10000, check_every = 1, n_threads = 1;
+    bool host_only = false;   // negative device ordinal: tracking only, no device state
+    int cur_psi = 0, cur_phi = 0;
+    bool fissile = false;
+    bool fixed_source = false;
+    // initial guess
+    bool guess_pending = false;
+    double guess_k = 1.0;
+    bool guess_has_psi = false;
+    double *guess_phi = nullptr;   // internal [R][G]
+    double *exit_canon = nullptr;  // user buffer
+    double *host_scal = nullptr;   // pinned
+    std::vector<void *> allocs;
+    std::string err;
+    // sweep profiling
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_pool;
+    int64_t prof_n = 0;
+    double prof_ms = 0, prof_min = 0, prof_max = 0;
+
+    template <typename T> T *dalloc(size_t n) {
+        if (host_only) return nullptr;
+        void *p = nullptr;
+        const size_t bytes = std::max<size_t>(n * sizeof(T), 16);
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) throw Error(MOC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+        allocs.push_back(p);
+        device_bytes += (int64_t)bytes;
+        return (T *)p;
+    }
+    template <typename T> T *upload(const std::vector<T> &v) {
+        if (host_only) return nullptr;
+        T *p = dalloc<T>(v.size());
+        if (!v.empty()) HIP_OK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return p;
+    }
+    ~moc_ctx() {
+        if (stream) hipStreamSynchronize(stream);
+        for (auto &e : prof_pending) {
+            hipEventSynchronize(e.second);
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        for (auto &e : prof_pool) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        for (void *p : allocs) hipFree(p);
+        if (host_scal) hipHostFree(host_scal);
+        if (stream) hipStreamDestroy(stream);
+    }
+};
+
+static thread_local std::string g_create_error;
+
+template <typename F> static int guarded(moc_ctx *ctx, F &&f) {
+    try {
+        f();
+        if (ctx) ctx->err.clear();
+        return MOC_OK;
+    } catch (const Error &e) {
+        if (ctx) ctx->err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->err = "host allocation failed";
+        return MOC_ENOMEM;
+    } catch (const std::exception &e) {
+        if (ctx) ctx->err = e.what();
+        return MOC_EINVAL;
+    } catch (...) {
+        if (ctx) ctx->err = "unknown error";
+        return MOC_EINVAL;
+    }
+}
+
+static int choose_group_batch(int G) {
+    if (G == 1 || G == 2 || G == 4 || G == 7 || G == 8) return G;
+    if (G == 3) return 4;
+    if (G <= 8) return 8;
+    if (G % 11 == 0) return 11;
+    if (G % 8 == 0) return 8;
+    if (G % 7 == 0) return 7;
+    return 8;
+}
+
+namespace {
+
+struct CountSink : SegmentSink {
+    int64_t n = 0;
+    void emit(int, double) override { ++n; }
+};
+
+template <typename Seg> struct PackSink : SegmentSink {
+    Seg *base = nullptr;  // first entry of the lane in its batch
+    const int *internal_of_user = nullptr;
+    double *V = nullptr;  // thread-local volumes
+    double w = 0;         // w_a * delta_a
+    int64_t k = 0;
+    int first = -1, last = -1;
+    void emit(int r, double len) override {
+        const int ri = internal_of_user[r];
+        Seg &s = base[k * kBatch];
+        s.len = (decltype(s.len))len;
+        s.reg = ri;
+        V[ri] += w * len;
+        if (first < 0) first = ri;
+        last = ri;
+        ++k;
+    }
+};
+
+struct DumpSink : SegmentSink {
+    std::vector<int> reg;
+    std::vector<double> len;
+    void emit(int r, double l) override {
+        reg.push_back(r);
+        len.push_back(l);
+    }
+};
+
+struct SegF {
+    float len;
+    int reg;
+};
+struct alignas(16) SegD {
+    double len;
+    int reg;
+    int pad;
+};
+
+}  // namespace
+
+template <typename Seg>
+static void pack_segments(moc_ctx *c, const std::vector<int> &counts, const std::vector<int64_t> &batch_off,
+                          const std::vector<int> &batch_of_track, std::vector<int> &entry_region, std::vector<double> &V) {
+    const int T = c->tracks.T;
+    const int64_t total = batch_off.empty() ? 0 : batch_off.back();
+    std::vector<Seg> host((size_t)total);
+    std::memset((void *)host.data(), 0, sizeof(Seg) * host.size());
+    const int nth = c->n_threads;
+    std::vector<std::vector<double>> Vt(nth, std::vector<double>(c->mesh.R, 0.0));
+    entry_region.assign(2 * (size_t)c->d.nslots, -1);
+    parallel_for(T, nth, 64, [&](int64_t b, int64_t e, int w) {
+        PackSink<Seg> sink;
+        sink.internal_of_user = c->internal_of_user.data();
+        sink.V = Vt[w].data();
+        for (int64_t t = b; t < e; ++t) {
+            const int slot = c->slot_of_canon[t];
+            const int bt = batch_of_track[t];
+            sink.base = host.data() + batch_off[bt] + (slot - bt * kBatch);
+            sink.k = 0;
+            sink.first = sink.last = -1;
+            const int a = c->tracks.angle[t];
+            sink.w = c->quad.wa[a] * c->quad.delta[a];
+            const int64_t n = trace_track(c->mesh, c->quad, c->tracks, (int)t, sink);
+            if (n != counts[t]) throw Error(MOC_EINVAL, "tracking: non-deterministic segment count");
+            entry_region[slot] = sink.first;                     // sense 0 enters at the first segment
+            entry_region[c->d.nslots + slot] = sink.last;        // sense 1 at the last
+        }
+    });
+    V.assign(c->mesh.R, 0.0);
+    for (int w = 0; w < nth; ++w)
+        for (int r = 0; r < c->mesh.R; ++r) V[r] += Vt[w][r];
+    c->d.segs = c->upload(host);
+}
+
+static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const moc_xs *xs, const moc_options *opt,
+                        moc_ctx *c) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!mesh_in || !tr_in || !xs) throw Error(MOC_EINVAL, "create: null argument");
+    moc_options o{};
+    o.precision = MOC_PREC_F32;
+    o.exp_mode = MOC_EXP_POLY;
+    if (opt) o = *opt;
+    if (o.precision != MOC_PREC_F32 && o.precision != MOC_PREC_F64) throw Error(MOC_EINVAL, "options: bad precision");
+    if (o.exp_mode < MOC_EXP_POLY || o.exp_mode > MOC_EXP_LIBM) throw Error(MOC_EINVAL, "options: bad exp_mode");
+    c->max_iter = o.max_iter > 0 ? o.max_iter : 10000;
+    c->check_every = o.check_every > 0 ? o.check_every : 1;
+    c->n_threads = o.n_threads > 0 ? o.n_threads : std::max(1u, std::thread::hardware_concurrency());
+    c->device = o.device;
+    c->host_only = o.device < 0;
+    if (!c->host_only) {
+        HIP_OK(hipSetDevice(c->device));
+        HIP_OK(hipStreamCreate(&c->stream));
+        HIP_OK(hipHostMalloc((void **)&c->host_scal, kScalCount * sizeof(double)));
+    }
+
+    // ---- cross sections
+    const int M = xs->n_materials, G = xs->n_groups;
+    if (M <= 0 || G <= 0 || !xs->sigma_t || !xs->sigma_s || !xs->nu_sigma_f || !xs->chi)
+        throw Error(MOC_EINVAL, "xs: empty or null arrays");
+    for (int i = 0; i < M * G; ++i)
+        if (!(xs->sigma_t[i] > 0) || !std::isfinite(xs->sigma_t[i])) throw Error(MOC_EINVAL, "xs: Sigma_t must be positive and finite");
+    for (int i = 0; i < M * G * G; ++i)
+        if (!std::isfinite(xs->sigma_s[i])) throw Error(MOC_EINVAL, "xs: non-finite Sigma_s");
+    for (int i = 0; i < M * G; ++i)
+        if (!std::isfinite(xs->nu_sigma_f[i]) || !std::isfinite(xs->chi[i])) throw Error(MOC_EINVAL, "xs: non-finite nuSigma_f or chi");
+    c->sigt_m_host.assign(xs->sigma_t, xs->sigma_t + M * G);
+    c->nsf_m_host.assign(xs->nu_sigma_f, xs->nu_sigma_f + M * G);
+    for (int i = 0; i < M * G; ++i) c->fissile |= xs->nu_sigma_f[i] > 0;
+
+    // ---- geometry and tracks (host)
+    build_mesh(*mesh_in, c->mesh);
+    if (!mesh_in->region_material) throw Error(MOC_EINVAL, "mesh: null region_material");
+    for (int r = 0; r < c->mesh.R; ++r)
+        if (mesh_in->region_material[r] < 0 || mesh_in->region_material[r] >= M)
+            throw Error(MOC_EINVAL, "mesh: material index out of range");
+    build_quadrature(c->mesh, *tr_in, c->quad);
+    lay_tracks(c->mesh, c->quad, c->tracks);
+    link_tracks(c->mesh, c->quad, c->tracks);
+    locality_order(c->mesh, c->internal_of_user, c->user_of_internal);
+
+    DevProblem &d = c->d;
+    const int R = c->mesh.R, T = c->tracks.T, P = c->quad.P;
+    d.R = R;
+    d.G = G;
+    d.M = M;
+    d.P = P;
+    d.NA = c->quad.NA;
+    d.T = T;
+    d.precision = o.precision;
+    d.exp_mode = o.exp_mode;
+    d.gb = choose_group_batch(G);
+    d.n_gb = (G + d.gb - 1) / d.gb;
+    d.Gp = ((d.n_gb * d.gb + 3) / 4) * 4;
+    const bool f64 = o.precision == MOC_PREC_F64;
+    const size_t rs = f64 ? sizeof(double) : sizeof(float);
+
+    // ---- batches: 64 consecutive tracks of one angle per batch
+    std::vector<int> batch_angle, batch_of_track(T);
+    c->slot_of_canon.assign(T, -1);
+    for (int t = 0; t < T;) {
+        const int a = c->tracks.angle[t];
+        int e = t;
+        while (e < T && c->tracks.angle[e] == a) ++e;
+        for (int s = t; s < e; s += kBatch) {
+            const int b = (int)batch_angle.size();
+            batch_angle.push_back(a);
+            for (int k = s; k < std::min(e, s + kBatch); ++k) {
+                batch_of_track[k] = b;
+                c->slot_of_canon[k] = b * kBatch + (k - s);
+            }
+        }
+        t = e;
+    }
+    d.nb = (int)batch_angle.size();
+    d.nslots = d.nb * kBatch;
+    if (d.nb == 0) throw Error(MOC_EINVAL, "tracks: no track crosses the domain");
+    std::vector<int> canon_of_slot(d.nslots, -1);
+    for (int t = 0; t < T; ++t) canon_of_slot[c->slot_of_canon[t]] = t;
+
+    // ---- pass 1: segment counts
+    std::vector<int> counts(T, 0);
+    parallel_for(T, c->n_threads, 64, [&](int64_t b, int64_t e, int) {
+        CountSink cs;
+        for (int64_t t = b; t < e; ++t) {
+            cs.n = 0;
+            counts[t] = (int)trace_track(c->mesh, c->quad, c->tracks, (int)t, cs);
+        }
+    });
+    std::vector<int> batch_n(d.nb, 0);
+    for (int t = 0; t < T; ++t) batch_n[batch_of_track[t]] = std::max(batch_n[batch_of_track[t]], counts[t]);
+    std::vector<int64_t> batch_off(d.nb + 1, 0);
+    for (int b = 0; b < d.nb; ++b) batch_off[b + 1] = batch_off[b] + (int64_t)batch_n[b] * kBatch;
+    c->S = 0;
+    for (int t = 0; t < T; ++t) c->S += counts[t];
+    c->padded_steps = batch_off[d.nb];
+
+    // ---- pass 2: pack segments, volumes, entry regions
+    std::vector<int> entry_region;
+    std::vector<double> V_internal;
+    if (f64)
+        pack_segments<SegD>(c, counts, batch_off, batch_of_track, entry_region, V_internal);
+    else
+        pack_segments<SegF>(c, counts, batch_off, batch_of_track, entry_region, V_internal);
+    for (int r = 0; r < R; ++r)
+        if (!(V_internal[r] > 0))
+            throw Error(MOC_EINVAL, "tracking: region " + std::to_string(c->user_of_internal[r]) +
+                                        " is crossed by no track (refine the track spacing)");
+    c->V_user.assign(R, 0.0);
+    for (int r = 0; r < R; ++r) c->V_user[c->user_of_internal[r]] = V_internal[r];
+    batch_off.pop_back();
+    d.batch_off = c->upload(batch_off);
+    d.batch_n = c->upload(batch_n);
+    d.batch_angle = c->upload(batch_angle);
+    d.entry_region = c->upload(entry_region);
+    d.slot_of_canon = c->upload(c->slot_of_canon);
+    d.canon_of_slot = c->upload(canon_of_slot);
+
+    // links in slot space
+    std::vector<int> link(2 * (size_t)d.nslots, -1);
+    std::vector<unsigned char> fed(2 * (size_t)d.nslots, 0);
+    for (int t = 0; t < T; ++t)
+        for (int s = 0; s < 2; ++s) {
+            const int dst = c->tracks.link[2 * (size_t)t + s];
+            if (dst < 0) continue;
+            const int t2 = dst / 2, s2 = dst % 2;
+            const int j = s2 * d.nslots + c->slot_of_canon[t2];
+            link[(size_t)s * d.nslots + c->slot_of_canon[t]] = j;
+            fed[j] = 1;
+        }
+    d.link = c->upload(link);
+    d.fed = c->upload(fed);
+
+    // ---- per-region and per-material arrays
+    std::vector<int> mat(R);
+    for (int r = 0; r < R; ++r) mat[r] = mesh_in->region_material[c->user_of_internal[r]];
+    d.mat = c->upload(mat);
+    d.user_of = c->upload(c->user_of_internal);
+    d.V = c->upload(V_internal);
+    d.sigt_m = c->upload(c->sigt_m_host);
+    d.sigs_m = c->upload(std::vector<double>(xs->sigma_s, xs->sigma_s + M * G * G));
+    d.nsf_m = c->upload(c->nsf_m_host);
+    d.chi_m = c->upload(std::vector<double>(xs->chi, xs->chi + M * G));
+    if (f64) {
+        std::vector<double> st((size_t)R * d.Gp, 0.0);
+        for (int r = 0; r < R; ++r)
+            for (int g = 0; g < G; ++g) st[(size_t)r * d.Gp + g] = xs->sigma_t[mat[r] * G + g];
+        d.sigt_r = c->upload(st);
+    } else {
+        std::vector<float> st((size_t)R * d.Gp, 0.0f);
+        for (int r = 0; r < R; ++r)
+            for (int g = 0; g < G; ++g) st[(size_t)r * d.Gp + g] = (float)xs->sigma_t[mat[r] * G + g];
+        d.sigt_r = c->upload(st);
+    }
+    d.qhat = c->dalloc<char>((size_t)R * d.Gp * rs);
+    d.tally = c->dalloc<double>((size_t)R * d.Gp);
+    d.phi[0] = c->dalloc<double>((size_t)R * G);
+    d.phi[1] = c->dalloc<double>((size_t)R * G);
+    const size_t npsi = (size_t)2 * P * d.Gp * d.nslots;
+    d.psi[0] = c->dalloc<char>(npsi * rs);
+    d.psi[1] = c->dalloc<char>(npsi * rs);
+    if (!c->host_only) {
+        launch_fill_real(d.psi[0], (int64_t)npsi, d.precision, c->stream);
+        launch_fill_real(d.psi[1], (int64_t)npsi, d.precision, c->stream);
+        launch_fill_real(d.qhat, (int64_t)R * d.Gp, d.precision, c->stream);
+    }
+
+    // tally weights c_ap = 2 pi w_a w_p delta_a sin(theta_p); 1/sin(theta_p)
+    std::vector<double> coef((size_t)d.NA * P), inv_sin(P);
+    for (int a = 0; a < d.NA; ++a)
+        for (int p = 0; p < P; ++p)
+            coef[(size_t)a * P + p] = 2.0 * 3.14159265358979323846 * c->quad.wa[a] * c->quad.wp[p] * c->quad.delta[a] * c->quad.sinp[p];
+    for (int p = 0; p < P; ++p) inv_sin[p] = 1.0 / c->quad.sinp[p];
+    if (f64) {
+        d.coef = c->upload(coef);
+        d.inv_sin = c->upload(inv_sin);
+    } else {
+        d.coef = c->upload(std::vector<float>(coef.begin(), coef.end()));
+        d.inv_sin = c->upload(std::vector<float>(inv_sin.begin(), inv_sin.end()));
+    }
+    std::vector<float> table(kExpTableN);
+    for (int i = 0; i < kExpTableN; ++i) {
+        const double x = (double)i * kExpTableMax / kExpTableN;
+        table[i] = (float)(i == 0 ? 1.0 : -std::expm1(-x) / x);
+    }
+    d.exp_table = c->upload(table);
+    d.partials = c->dalloc<double>(2 * kReduceBlocks);
+    d.scal = c->dalloc<double>(kScalCount);
+    if (!c->host_only) {
+        launch_fill_f64(d.scal, kScalCount, 0.0, c->stream);
+        launch_fill_f64(d.scal, 1, 1.0, c->stream);  // k = 1
+        launch_fill_f64(d.phi[0], (int64_t)R * G, 1.0, c->stream);
+        HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    c->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+static hipStream_t pick(moc_ctx *c, void *s) { return s ? (hipStream_t)s : c->stream; }
+
+static void need_device(const moc_ctx *c) {
+    if (c->host_only) throw Error(MOC_ESTATE, "host-only context (negative device ordinal): no device state");
+}
+
+static void sweep_impl(moc_ctx *c, hipStream_t s) {
+    DevProblem &d = c->d;
+    launch_fill_f64(d.tally, (int64_t)d.R * d.Gp, 0.0, s);
+    SweepArgs a{};
+    a.segs = d.segs;
+    a.batch_off = d.batch_off;
+    a.batch_n = d.batch_n;
+    a.batch_angle = d.batch_angle;
+    a.sigt = d.sigt_r;
+    a.qhat = d.qhat;
+    a.psi_in = d.psi[c->cur_psi];
+    a.psi_out = d.psi[1 - c->cur_psi];
+    a.link = d.link;
+    a.fed = d.fed;
+    a.coef = d.coef;
+    a.inv_sin = d.inv_sin;
+    a.exp_table = d.exp_table;
+    a.tally = d.tally;
+    a.exit_canon = c->exit_canon;
+    a.canon_of_slot = d.canon_of_slot;
+    a.nslots = d.nslots;
+    a.Gp = d.Gp;
+    a.G = d.G;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (c->profiling) {
+        if (c->prof_pool.empty()) {
+            HIP_OK(hipEventCreate(&ev.first));
+            HIP_OK(hipEventCreate(&ev.second));
+        } else {
+            ev = c->prof_pool.back();
+            c->prof_pool.pop_back();
+        }
+        HIP_OK(hipEventRecord(ev.first, s));
+    }
+    launch_sweep(a, d.precision, d.exp_mode, d.nb, d.P, d.gb, d.n_gb, s);
+    if (c->profiling) {
+        HIP_OK(hipEventRecord(ev.second, s));
+        c->prof_pending.push_back(ev);
+    }
+    c->cur_psi = 1 - c->cur_psi;
+}
+
+extern "C" {
+
+int moc_create(const moc_mesh *mesh, const moc_tracks *tracks, const moc_xs *xs, const moc_options *opts, moc_ctx **out) {
+    if (!out) {
+        g_create_error = "create: null output pointer";
+        return MOC_EINVAL;
+    }
+    *out = nullptr;
+    moc_ctx *c = new (std::nothrow) moc_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return MOC_ENOMEM;
+    }
+    const int rc = guarded(c, [&] { create_impl(mesh, tracks, xs, opts, c); });
+    if (rc != MOC_OK) {
+        g_create_error = c->err;
+        delete c;
+        return rc;
+    }
+    g_create_error.clear();
+    *out = c;
+    return MOC_OK;
+}
+
+void moc_destroy(moc_ctx *ctx) { delete ctx; }
+
+int moc_sweep(moc_ctx *c, const double *source_dev, double *phi_out_dev, void *stream) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        if (!source_dev || !phi_out_dev) throw Error(MOC_EINVAL, "sweep: null pointer");
+        need_device(c);
+        HIP_OK(hipSetDevice(c->device));
+        hipStream_t s = pick(c, stream);
+        launch_prep_user(c->d, source_dev, s);
+        sweep_impl(c, s);
+        launch_finalize(c->d, nullptr, phi_out_dev, nullptr, s);
+    });
+}
+
+// Power (eigen) or source (fixed-source) iteration; see moc_solve in moc.h.
+static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc_result *out) {
+    if (!out) throw Error(MOC_EINVAL, "solve: null result");
+    need_device(c);
+    HIP_OK(hipSetDevice(c->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    DevProblem &d = c->d;
+    hipStream_t s = c->stream;
+    const bool eigen = c->fissile && !c->fixed_source;
+    const int64_t nphi = (int64_t)d.R * d.G;
+    const int64_t npsi = (int64_t)2 * d.P * d.Gp * d.nslots;
+    int flags = c->fixed_source ? MOC_FLAG_FIXED_SOURCE : 0;
+    bool use_guess = false;
+    if (c->guess_pending) {
+        c->guess_pending = false;
+        launch_check_guess(c->guess_phi, nphi, d.partials, s);
+        double chk[2];
+        HIP_OK(hipMemcpyAsync(chk, d.partials, sizeof chk, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        use_guess = chk[0] == 0.0 && chk[1] > 0.0 && std::isfinite(c->guess_k) && c->guess_k > 0;
+        if (!use_guess) flags |= MOC_FLAG_FELL_BACK_TO_COLD;
+    }
+    c->cur_phi = 0;
+    double k0 = 1.0;
+    if (use_guess) {
+        HIP_OK(hipMemcpyAsync(d.phi[0], c->guess_phi, nphi * sizeof(double), hipMemcpyDeviceToDevice, s));
+        k0 = c->guess_k;
+        if (!c->guess_has_psi) launch_psi_from_phi(d, d.phi[0], d.psi[c->cur_psi], s);
+    } else {
+        launch_fill_f64(d.phi[0], nphi, 1.0, s);
+        launch_fill_real(d.psi[0], npsi, d.precision, s);
+        launch_fill_real(d.psi[1], npsi, d.precision, s);
+    }
+    c->host_scal[0] = eigen ? k0 : 1.0;
+    HIP_OK(hipMemcpyAsync(d.scal + kScalK, c->host_scal, sizeof(double), hipMemcpyHostToDevice, s));
+    if (eigen) {
+        launch_fission_partials(d, d.phi[0], d.partials, s);
+        launch_eigen_update(d, d.partials, 0, s);
+        launch_scale_f64(d.phi[0], nphi, d.scal + kScalF, s);
+        launch_scale_real(d.psi[c->cur_psi], npsi, d.precision, d.scal + kScalF, s);
+    }
+    int it = 0;
+    bool conv = false;
+    double res = 1.0, dk = 1.0, k = k0;
+    for (it = 1; it <= max_iter; ++it) {
+        double *phi_old = d.phi[c->cur_phi], *phi_new = d.phi[1 - c->cur_phi];
+        launch_source(d, phi_old, s);
+        sweep_impl(c, s);
+        launch_finalize(d, phi_new, nullptr, d.partials, s);
+        launch_eigen_update(d, d.partials, eigen ? 1 : 2, s);
+        launch_norm_residual(d, phi_new, phi_old, d.partials, s);
+        if (eigen) launch_scale_real(d.psi[c->cur_psi], npsi, d.precision, d.scal + kScalF, s);
+        c->cur_phi = 1 - c->cur_phi;
+        if (it % check_every == 0 || it == max_iter) {
+            HIP_OK(hipMemcpyAsync(c->host_scal, d.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            k = c->host_scal[kScalK];
+            res = c->host_scal[kScalRes];
+            dk = c->host_scal[kScalDk];
+            if (!std::isfinite(res) || !std::isfinite(k)) throw Error(MOC_EHIP, "solve: non-finite iterate");
+            if (res < tol && dk < tol) {
+                conv = true;
+                break;
+            }
+        }
+    }
+    out->k = eigen ? k : 1.0;
+    out->iterations = conv ? it : max_iter;
+    out->residual = res;
+    out->dk = dk;
+    out->flags = flags;
+    out->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return conv ? MOC_OK : MOC_ENOCONV;
+}
+
+int moc_solve(moc_ctx *c, double tol, moc_result *out) {
+    if (!c) return MOC_EINVAL;
+    int status = MOC_OK;
+    const int rc = guarded(c, [&] {
+        if (!(tol > 0)) throw Error(MOC_EINVAL, "solve: tol must be positive");
+        status = solve_impl(c, tol, c->max_iter, c->check_every, out);
+    });
+    if (rc != MOC_OK) return rc;
+    if (status != MOC_OK) c->err = "solve: not converged within max_iter";
+    return status;
+}
+
+int moc_run_iterations(moc_ctx *c, int n, moc_result *out) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        if (n <= 0) throw Error(MOC_EINVAL, "run_iterations: n must be positive");
+        solve_impl(c, 0.0, n, n, out);
+    });
+}
+
+int moc_set_initial_guess(moc_ctx *c, const double *phi0_dev, double k0, const double *psi_b0_dev) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        if (!phi0_dev) throw Error(MOC_EINVAL, "initial guess: null phi0");
+        need_device(c);
+        HIP_OK(hipSetDevice(c->device));
+        if (!c->guess_phi) c->guess_phi = c->dalloc<double>((size_t)c->d.R * c->d.G);
+        launch_permute_rows(c->d, phi0_dev, c->guess_phi, 0, c->stream);
+        c->guess_k = k0;
+        c->guess_has_psi = psi_b0_dev != nullptr;
+        if (psi_b0_dev) launch_psi_canon(c->d, const_cast<double *>(psi_b0_dev), c->d.psi[c->cur_psi], 0, c->stream);
+        HIP_OK(hipStreamSynchronize(c->stream));
+        c->guess_pending = true;
+    });
+}
+
+int moc_get_flux(moc_ctx *c, double *phi_dev, void *stream) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        if (!phi_dev) throw Error(MOC_EINVAL, "get_flux: null pointer");
+        need_device(c);
+        HIP_OK(hipSetDevice(c->device));
+        launch_permute_rows(c->d, c->d.phi[c->cur_phi], phi_dev, 1, pick(c, stream));
+    });
+}
+
+int moc_get_boundary_flux(moc_ctx *c, double *psi_dev, void *stream) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        if (!psi_dev) throw Error(MOC_EINVAL, "get_boundary_flux: null pointer");
+        need_device(c);
+        HIP_OK(hipSetDevice(c->device));
+        launch_psi_canon(c->d, psi_dev, c->d.psi[c->cur_psi], 1, pick(c, stream));
+    });
+}
+
+int moc_set_boundary_flux(moc_ctx *c, const double *psi_dev, void *stream) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        if (!psi_dev) throw Error(MOC_EINVAL, "set_boundary_flux: null pointer");
+        need_device(c);
+        HIP_OK(hipSetDevice(c->device));
+        launch_psi_canon(c->d, const_cast<double *>(psi_dev), c->d.psi[c->cur_psi], 0, pick(c, stream));
+    });
+}
+
+int moc_set_exit_flux_buffer(moc_ctx *c, double *psi_exit_dev) {
+    if (!c) return MOC_EINVAL;
+    if (c->host_only) return MOC_ESTATE;
+    c->exit_canon = psi_exit_dev;
+    return MOC_OK;
+}
+
+int moc_set_external_source(moc_ctx *c, const double *q_dev) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        need_device(c);
+        HIP_OK(hipSetDevice(c->device));
+        if (!q_dev) {
+            c->fixed_source = false;
+            c->d.qext = nullptr;
+            return;
+        }
+        double *buf = c->d.qext ? c->d.qext : c->dalloc<double>((size_t)c->d.R * c->d.G);
+        launch_permute_rows(c->d, q_dev, buf, 0, c->stream);
+        HIP_OK(hipStreamSynchronize(c->stream));
+        c->d.qext = buf;
+        c->fixed_source = true;
+    });
+}
+
+int moc_get_info(const moc_ctx *c, moc_info *info) {
+    if (!c || !info) return MOC_EINVAL;
+    info->n_regions = c->d.R;
+    info->n_groups = c->d.G;
+    info->n_materials = c->d.M;
+    info->n_polar = c->d.P;
+    info->n_angles = c->d.NA;
+    info->n_tracks = c->d.T;
+    info->n_segments = c->S;
+    info->n_updates = 2LL * c->d.P * c->d.G * c->S;
+    info->n_padded_steps = c->padded_steps;
+    info->n_batches = c->d.nb;
+    info->setup_ms = c->setup_ms;
+    info->device_bytes = c->device_bytes;
+    info->precision = c->d.precision;
+    return MOC_OK;
+}
+
+static void drain_profile(moc_ctx *c) {
+    for (auto &e : c->prof_pending) {
+        HIP_OK(hipEventSynchronize(e.second));
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, e.first, e.second));
+        c->prof_min = c->prof_n ? std::min(c->prof_min, (double)ms) : ms;
+        c->prof_max = c->prof_n ? std::max(c->prof_max, (double)ms) : ms;
+        c->prof_ms += ms;
+        ++c->prof_n;
+        c->prof_pool.push_back(e);
+    }
+    c->prof_pending.clear();
+}
+
+int moc_set_profiling(moc_ctx *c, int enable) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        need_device(c);
+        drain_profile(c);
+        c->profiling = enable != 0;
+        c->prof_n = 0;
+        c->prof_ms = c->prof_min = c->prof_max = 0;
+    });
+}
+
+int moc_get_profile(moc_ctx *c, moc_profile *out) {
+    if (!c || !out) return MOC_EINVAL;
+    return guarded(c, [&] {
+        need_device(c);
+        drain_profile(c);
+        out->sweeps = c->prof_n;
+        out->sweep_ms = c->prof_ms;
+        out->sweep_ms_min = c->prof_min;
+        out->sweep_ms_max = c->prof_max;
+    });
+}
+
+int moc_get_volumes(const moc_ctx *c, double *V_host) {
+    if (!c || !V_host) return MOC_EINVAL;
+    std::memcpy(V_host, c->V_user.data(), sizeof(double) * c->V_user.size());
+    return MOC_OK;
+}
+
+int moc_get_tracks(moc_ctx *c, int32_t *angle, double *endpoints, int64_t *offsets, int32_t *seg_region, double *seg_length,
+                   int32_t *links) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        const Tracks &t = c->tracks;
+        int64_t off = 0;
+        for (int i = 0; i < t.T; ++i) {
+            if (angle) angle[i] = t.angle[i];
+            if (endpoints) {
+                endpoints[4 * (size_t)i] = t.x0[i];
+                endpoints[4 * (size_t)i + 1] = t.y0[i];
+                endpoints[4 * (size_t)i + 2] = t.x1[i];
+                endpoints[4 * (size_t)i + 3] = t.y1[i];
+            }
+            if (links) {
+                links[2 * (size_t)i] = t.link[2 * (size_t)i];
+                links[2 * (size_t)i + 1] = t.link[2 * (size_t)i + 1];
+            }
+            if (offsets || seg_region || seg_length) {
+                DumpSink ds;
+                trace_track(c->mesh, c->quad, t, i, ds);
+                if (offsets) offsets[i] = off;
+                for (size_t k = 0; k < ds.reg.size(); ++k) {
+                    if (seg_region) seg_region[off + (int64_t)k] = ds.reg[k];
+                    if (seg_length) seg_length[off + (int64_t)k] = ds.len[k];
+                }
+                off += (int64_t)ds.reg.size();
+            }
+        }
+        if (offsets) offsets[t.T] = off;
+    });
+}
+
+int moc_get_quadrature(const moc_ctx *c, double *phi, double *delta, double *w_azim, double *mu, double *w_polar) {
+    if (!c) return MOC_EINVAL;
+    for (int a = 0; a < c->quad.NA; ++a) {
+        if (phi) phi[a] = c->quad.phi[a];
+        if (delta) delta[a] = c->quad.delta[a];
+        if (w_azim) w_azim[a] = c->quad.wa[a];
+    }
+    for (int p = 0; p < c->quad.P; ++p) {
+        if (mu) mu[p] = c->quad.mu[p];
+        if (w_polar) w_polar[p] = c->quad.wp[p];
+    }
+    return MOC_OK;
+}
+
+const char *moc_last_error(const moc_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Device-side state and kernel launchers of libmoc (see moc_kernels.hip for layouts).
+#pragma once
+
+#include "moc_internal.h"
+
+namespace moc {
+
+// indices into the device scalar array
+enum { kScalK = 0, kScalKPrev = 1, kScalF = 2, kScalRes = 3, kScalDk = 4, kScalFsum = 5, kScalCount = 8 };
+
+// table of (1 - e^-x)/x for the FP32 table exponential: kExpTableN points on [0, kExpTableMax]
+constexpr int kExpTableN = 2048;
+constexpr float kExpTableMax = 16.0f;
+
+// fixed number of blocks for the FP64 reductions (partials are summed in block order)
+constexpr int kReduceBlocks = 512;
+
+struct SweepArgs {
+    const void *segs;          // SegF / SegD interleaved per batch
+    const int64_t *batch_off;  // [nb] first segment entry of each batch
+    const int *batch_n;        // [nb] steps of each batch
+    const int *batch_angle;    // [nb]
+    const void *sigt;          // Real [R][Gp]
+    const void *qhat;          // Real [R][Gp]
+    const void *psi_in;        // Real [2][P][Gp][nslots]
+    void *psi_out;
+    const int *link;           // [2][nslots] -> sense' * nslots + slot', or -1
+    const unsigned char *fed;  // [2][nslots] 1 if some link feeds this incoming slot
+    const void *coef;          // Real [NA][P]
+    const void *inv_sin;       // Real [P]
+    const float *exp_table;    // [ExpTable::kN] (FP32 table mode)
+    double *tally;             // [R][Gp]
+    double *exit_canon;        // optional [T][2][P][G]
+    const int *canon_of_slot;  // [nslots] canonical track or -1
+    int nslots, Gp, G;
+};
+
+struct DevProblem {
+    int R = 0, G = 0, Gp = 0, M = 0, P = 0, NA = 0, T = 0;
+    int nb = 0, nslots = 0, gb = 1, n_gb = 1;
+    int precision = MOC_PREC_F32, exp_mode = MOC_EXP_POLY;
+    // per material, FP64
+    double *sigt_m = nullptr, *sigs_m = nullptr, *nsf_m = nullptr, *chi_m = nullptr;
+    // per internal region
+    int *mat = nullptr, *user_of = nullptr;
+    double *V = nullptr;
+    void *sigt_r = nullptr, *qhat = nullptr;
+    double *tally = nullptr;
+    double *phi[2] = {nullptr, nullptr};
+    double *qext = nullptr;
+    // tracks
+    void *segs = nullptr;
+    int64_t *batch_off = nullptr;
+    int *batch_n = nullptr, *batch_angle = nullptr;
+    void *psi[2] = {nullptr, nullptr};
+    int *link = nullptr;
+    unsigned char *fed = nullptr;
+    int *entry_region = nullptr;   // [2][nslots] internal region entered first, -1 dummy
+    int *slot_of_canon = nullptr, *canon_of_slot = nullptr;
+    void *coef = nullptr, *inv_sin = nullptr;
+    float *exp_table = nullptr;
+    // reductions
+    double *partials = nullptr, *scal = nullptr;
+};
+
+void launch_sweep(const SweepArgs &a, int precision, int exp_mode, int nb, int np, int gb, int n_gb, hipStream_t s);
+void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+void launch_fill_real(void *p, int64_t n, int precision, hipStream_t s);
+void launch_scale_real(void *p, int64_t n, int precision, const double *f, hipStream_t s);
+void launch_scale_f64(double *p, int64_t n, const double *f, hipStream_t s);
+void launch_prep_user(const DevProblem &d, const double *src_user, hipStream_t s);
+void launch_source(const DevProblem &d, const double *phi, hipStream_t s);
+void launch_finalize(const DevProblem &d, double *phi_internal, double *phi_user, double *partials, hipStream_t s);
+void launch_fission_partials(const DevProblem &d, const double *phi, double *partials, hipStream_t s);
+void launch_eigen_update(const DevProblem &d, const double *partials, int mode, hipStream_t s);
+void launch_norm_residual(const DevProblem &d, double *phi_new, const double *phi_old, double *partials, hipStream_t s);
+void launch_psi_canon(const DevProblem &d, double *canon, void *psi, int to_canon, hipStream_t s);
+void launch_psi_from_phi(const DevProblem &d, const double *phi_internal, void *psi, hipStream_t s);
+void launch_permute_rows(const DevProblem &d, const double *src, double *dst, int to_user, hipStream_t s);
+void launch_check_guess(const double *x, int64_t n, double *out2, hipStream_t s);
+
+}  // namespace moc

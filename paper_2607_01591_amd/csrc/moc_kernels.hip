@@ -1,0 +1,575 @@
+// HIP kernels of libmoc for gfx950 (CDNA4): source update, transport sweep, scalar-flux
+// finalisation, FP64 reductions for the eigenvalue and residual, boundary-flux layout
+// conversions.
+//
+// Layouts (internal region order r, which is a locality order of the user's regions):
+//   qhat, sigt_r : Real [R][Gp]   Gp = G padded; padded groups hold zeros
+//   tally        : double [R][Gp]
+//   phi          : double [R][G]
+//   psi          : Real [2 senses][P][Gp][nslots], slot = batch * 64 + lane
+//   segments     : per batch, [step][64 lanes] of {length, region}; shorter tracks are
+//                  padded with zero-length steps
+#include <cmath>
+#include <cstdio>
+
+#include "moc_kernels.h"
+
+namespace moc {
+
+static constexpr double kFourPi = 12.566370614359172953850573533118;
+
+struct SegF {
+    float len;
+    int reg;
+};
+struct alignas(16) SegD {
+    double len;
+    int reg;
+    int pad;
+};
+template <typename Real> struct SegOf;
+template <> struct SegOf<float> { using type = SegF; };
+template <> struct SegOf<double> { using type = SegD; };
+
+// ---------------------------------------------------------------- 1 - exp(-tau)
+// FP32, MOC_EXP_POLY: for tau >= 0.25 use 1 - 2^(-tau log2 e) with the hardware
+// exponential (absolute error ~6e-8, relative <= 3e-7 there); below, the Taylor series
+// of 1 - e^-tau through tau^6 (truncation < tau^7/5040, relative < 2e-7 at 0.25).
+// Relative accuracy matters because the tally takes (psi - qhat) * F directly.
+__device__ __forceinline__ float one_minus_exp_poly(float tau) {
+    const float e = __builtin_amdgcn_exp2f(-tau * 1.4426950408889634f);
+    const float big = 1.0f - e;
+    const float small =
+        tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f - tau * (1.0f / 120.0f - tau * (1.0f / 720.0f))))));
+    return tau < 0.25f ? small : big;
+}
+
+// MOC_EXP_TABLE: linear interpolation of f(x) = (1 - e^-x)/x on a uniform grid held in
+// LDS; F = tau f(tau). Beyond the table the hardware exponential is used.
+struct ExpTable {
+    static constexpr int kN = kExpTableN;
+    static constexpr float kMax = kExpTableMax;
+};
+
+template <int MODE> __device__ __forceinline__ float one_minus_exp_f(float tau, const float *lut) {
+    if constexpr (MODE == MOC_EXP_POLY) {
+        return one_minus_exp_poly(tau);
+    } else if constexpr (MODE == MOC_EXP_TABLE) {
+        const float x = tau * (ExpTable::kN / ExpTable::kMax);
+        if (x < float(ExpTable::kN - 1)) {
+            const int i = int(x);
+            const float fr = x - float(i);
+            const float a = lut[i], b = lut[i + 1];
+            return tau * (a + fr * (b - a));
+        }
+        return 1.0f - __builtin_amdgcn_exp2f(-tau * 1.4426950408889634f);
+    } else {
+        return -expm1f(-tau);
+    }
+}
+
+template <typename Real, int MODE> __device__ __forceinline__ Real one_minus_exp(Real tau, const float *lut) {
+    if constexpr (sizeof(Real) == 8) {
+        return -expm1(-tau);
+    } else {
+        return one_minus_exp_f<MODE>(tau, lut);
+    }
+}
+
+// ---------------------------------------------------------------- sweep
+// One wavefront = one batch of 64 adjacent parallel tracks of one angle, one sense and
+// one group batch [g0, g0 + GB). Lane l walks track l of the batch; all lanes step
+// through the interleaved segment stream together. Per segment and group the update is
+// Eq. MOC_sol: psi_out = qhat + (psi_in - qhat) e^-tau, tau = Sigma_t l / sin(theta_p);
+// the increment Delta = (psi - qhat)(1 - e^-tau) is summed over polar angles with weights
+// c_ap = 2 pi w_a w_p delta_a sin(theta_p) in registers and added to the region tally
+// with one FP64 atomic per (segment, group).
+template <typename Real, int NP, int GB, int MODE>
+__global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
+    using Seg = typename SegOf<Real>::type;
+    __shared__ float lut[MODE == MOC_EXP_TABLE ? ExpTable::kN : 1];
+    if constexpr (MODE == MOC_EXP_TABLE && sizeof(Real) == 4) {
+        for (int i = threadIdx.x; i < ExpTable::kN; i += 64) lut[i] = args.exp_table[i];
+        __syncthreads();
+    }
+    const int b = blockIdx.x, sense = blockIdx.y, gb = blockIdx.z, lane = threadIdx.x;
+    const int nslots = args.nslots;
+    const int slot = b * 64 + lane;
+    const int g0 = gb * GB;
+    const int Gp = args.Gp;
+    const int n = args.batch_n[b];
+    const int a = args.batch_angle[b];
+    const Seg *__restrict__ segs = reinterpret_cast<const Seg *>(args.segs) + args.batch_off[b];
+    const Real *__restrict__ sigt = reinterpret_cast<const Real *>(args.sigt);
+    const Real *__restrict__ qhat = reinterpret_cast<const Real *>(args.qhat);
+    const Real *__restrict__ psi_in = reinterpret_cast<const Real *>(args.psi_in);
+    Real *__restrict__ psi_out = reinterpret_cast<Real *>(args.psi_out);
+    const Real *__restrict__ coef = reinterpret_cast<const Real *>(args.coef);
+    const Real *__restrict__ inv_sin = reinterpret_cast<const Real *>(args.inv_sin);
+    double *__restrict__ tally = args.tally;
+
+    Real c[NP], is[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        c[p] = coef[a * NP + p];
+        is[p] = inv_sin[p];
+    }
+    Real psi[NP][GB];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int j = 0; j < GB; ++j) psi[p][j] = psi_in[(int64_t)((sense * NP + p) * Gp + g0 + j) * nslots + slot];
+
+    for (int i = 0; i < n; ++i) {
+        const int k = sense ? n - 1 - i : i;
+        const Seg sg = segs[(int64_t)k * 64 + lane];
+        const Real len = sg.len;
+        const int64_t base = (int64_t)sg.reg * Gp + g0;
+        Real st[GB], q[GB];
+#pragma unroll
+        for (int j = 0; j < GB; ++j) {
+            st[j] = sigt[base + j];
+            q[j] = qhat[base + j];
+        }
+#pragma unroll
+        for (int j = 0; j < GB; ++j) {
+            const Real sl = st[j] * len;
+            Real acc = 0;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const Real F = one_minus_exp<Real, MODE>(sl * is[p], lut);
+                const Real d = (psi[p][j] - q[j]) * F;
+                psi[p][j] -= d;
+                acc += c[p] * d;
+            }
+            if (len > Real(0)) unsafeAtomicAdd(&tally[base + j], (double)acc);
+        }
+    }
+    const int dst = args.link[sense * nslots + slot];
+    if (dst >= 0) {
+        const int s2 = dst / nslots, slot2 = dst - s2 * nslots;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int j = 0; j < GB; ++j) psi_out[(int64_t)((s2 * NP + p) * Gp + g0 + j) * nslots + slot2] = psi[p][j];
+    }
+    if (!args.fed[sense * nslots + slot]) {
+        // an incoming slot that no link feeds (vacuum side) stays zero in the next buffer
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int j = 0; j < GB; ++j) psi_out[(int64_t)((sense * NP + p) * Gp + g0 + j) * nslots + slot] = Real(0);
+    }
+    if (args.exit_canon) {
+        const int t = args.canon_of_slot[slot];
+        if (t >= 0) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int j = 0; j < GB; ++j)
+                    if (g0 + j < args.G)
+                        args.exit_canon[(((int64_t)t * 2 + sense) * NP + p) * args.G + g0 + j] = (double)psi[p][j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- small kernels
+template <typename T> __global__ void k_fill(T *__restrict__ p, int64_t n, T v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <typename T> __global__ void k_scale(T *__restrict__ p, int64_t n, const double *__restrict__ f) {
+    const T s = (T)(*f);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] *= s;
+}
+
+// qhat from a caller's emission density (user order): qhat = s / (4 pi Sigma_t)
+template <typename Real>
+__global__ void k_prep_user(const double *__restrict__ src_user, const int *__restrict__ user_of, const int *__restrict__ mat,
+                            const double *__restrict__ sigt_m, Real *__restrict__ qhat, int R, int G, int Gp) {
+    const int64_t n = (int64_t)R * Gp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = int(i / Gp), g = int(i - (int64_t)r * Gp);
+        Real v = 0;
+        if (g < G) v = (Real)(src_user[(int64_t)user_of[r] * G + g] / (kFourPi * sigt_m[mat[r] * G + g]));
+        qhat[i] = v;
+    }
+}
+
+// Source update (Eq. MGNTE, isotropic): s_g = sum_g' Sigma_s,g'->g phi_g' + chi_g F / k
+// (+ external), F = sum_g nuSigma_f,g phi_g; qhat = s / (4 pi Sigma_t). FP64 arithmetic.
+template <typename Real>
+__global__ void k_source(const double *__restrict__ phi, const double *__restrict__ scal, const int *__restrict__ mat,
+                         const double *__restrict__ sigt_m, const double *__restrict__ sigs_m,
+                         const double *__restrict__ nsf_m, const double *__restrict__ chi_m,
+                         const double *__restrict__ qext, Real *__restrict__ qhat, int R, int G, int Gp) {
+    const double inv_k = 1.0 / scal[kScalK];
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        const int m = mat[r];
+        const double *ph = phi + (int64_t)r * G;
+        double F = 0.0;
+        for (int gp = 0; gp < G; ++gp) F += nsf_m[m * G + gp] * ph[gp];
+        for (int g = 0; g < G; ++g) {
+            double s = chi_m[m * G + g] * F * inv_k;
+            const double *col = sigs_m + (int64_t)m * G * G + g;
+            for (int gp = 0; gp < G; ++gp) s += col[(int64_t)gp * G] * ph[gp];
+            if (qext) s += qext[(int64_t)r * G + g];
+            qhat[(int64_t)r * Gp + g] = (Real)(s / (kFourPi * sigt_m[m * G + g]));
+        }
+        for (int g = G; g < Gp; ++g) qhat[(int64_t)r * Gp + g] = Real(0);
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// phi = 4 pi qhat + T / (Sigma_t V) (angular integration of segment averages; FP64);
+// either to the internal phi with per-block partials of sum V F, or to a user buffer.
+template <typename Real>
+__global__ void k_finalize(const Real *__restrict__ qhat, const double *__restrict__ tally, const double *__restrict__ V,
+                           const int *__restrict__ mat, const double *__restrict__ sigt_m,
+                           const double *__restrict__ nsf_m, double *__restrict__ phi_internal,
+                           double *__restrict__ phi_user, const int *__restrict__ user_of, double *__restrict__ partials,
+                           int R, int G, int Gp) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        const int m = mat[r];
+        const double v = V[r];
+        double F = 0.0;
+        for (int g = 0; g < G; ++g) {
+            const double st = sigt_m[m * G + g];
+            const double ph = kFourPi * (double)qhat[(int64_t)r * Gp + g] + tally[(int64_t)r * Gp + g] / (st * v);
+            if (phi_internal) phi_internal[(int64_t)r * G + g] = ph;
+            if (phi_user) phi_user[(int64_t)user_of[r] * G + g] = ph;
+            F += nsf_m[m * G + g] * ph;
+        }
+        acc += v * F;
+    }
+    if (partials) {
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
+// sum V F of a flux (for the initial normalisation)
+__global__ void k_fission_partials(const double *__restrict__ phi, const double *__restrict__ V, const int *__restrict__ mat,
+                                   const double *__restrict__ nsf_m, double *__restrict__ partials, int R, int G) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        const int m = mat[r];
+        double F = 0.0;
+        for (int g = 0; g < G; ++g) F += nsf_m[m * G + g] * phi[(int64_t)r * G + g];
+        acc += V[r] * F;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// Single block. mode 0: initial normalisation (f = 1/sum); mode 1: eigenvalue update
+// k <- k * sum V F_new (the old iterate has sum V F = 1), f = 1/sum; mode 2: fixed source
+// (k = 1, f = 1). Partials are summed in a fixed order (deterministic).
+__global__ void k_eigen_update(const double *__restrict__ partials, int nblk, double *__restrict__ scal, int mode) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partials[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        scal[kScalFsum] = s;
+        if (mode == 0) {
+            scal[kScalF] = 1.0 / s;
+        } else if (mode == 1) {
+            scal[kScalKPrev] = scal[kScalK];
+            scal[kScalK] = scal[kScalK] * s;
+            scal[kScalF] = 1.0 / s;
+        } else {
+            scal[kScalKPrev] = scal[kScalK];
+            scal[kScalF] = 1.0;
+        }
+    }
+}
+
+// phi_new *= f; partials of sum V (phi_new - phi_old)^2 and sum V phi_new^2
+__global__ void k_norm_residual(double *__restrict__ phi_new, const double *__restrict__ phi_old,
+                                const double *__restrict__ V, const double *__restrict__ scal,
+                                double *__restrict__ partials, int R, int G) {
+    __shared__ double sh[16];
+    const double f = scal[kScalF];
+    double num = 0.0, den = 0.0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        const double v = V[r];
+        for (int g = 0; g < G; ++g) {
+            const int64_t i = (int64_t)r * G + g;
+            const double x = phi_new[i] * f;
+            phi_new[i] = x;
+            const double d = x - phi_old[i];
+            num += v * d * d;
+            den += v * x * x;
+        }
+    }
+    const double a = block_sum(num, sh);
+    const double b = block_sum(den, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = a;
+        partials[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void k_residual(const double *__restrict__ partials, int nblk, double *__restrict__ scal) {
+    __shared__ double sh[16];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
+    }
+    const double sa = block_sum(a, sh);
+    const double sb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        scal[kScalRes] = sb > 0 ? sqrt(sa / sb) : 0.0;
+        scal[kScalDk] = fabs(scal[kScalK] - scal[kScalKPrev]);
+    }
+}
+
+// canonical [T][2][P][G] FP64 <-> internal psi
+template <typename Real>
+__global__ void k_psi_canon(double *__restrict__ canon, Real *__restrict__ psi, const int *__restrict__ slot_of_canon, int T,
+                            int P, int G, int Gp, int nslots, int to_canon) {
+    const int64_t n = (int64_t)T * 2 * P * G;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = int(i % G);
+        const int p = int((i / G) % P);
+        const int s = int((i / ((int64_t)G * P)) % 2);
+        const int t = int(i / ((int64_t)G * P * 2));
+        const int64_t j = (int64_t)((s * P + p) * Gp + g) * nslots + slot_of_canon[t];
+        if (to_canon)
+            canon[i] = (double)psi[j];
+        else
+            psi[j] = (Real)canon[i];
+    }
+}
+
+// Boundary flux from a scalar-flux guess: psi = phi(r_entry)/(4 pi) for every incoming
+// track-sense (r_entry: internal region of the first segment along that sense).
+template <typename Real>
+__global__ void k_psi_from_phi(const double *__restrict__ phi, const int *__restrict__ entry_region, Real *__restrict__ psi,
+                               int P, int G, int Gp, int nslots) {
+    const int64_t n = (int64_t)2 * P * Gp * nslots;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int slot = int(i % nslots);
+        const int g = int((i / nslots) % Gp);
+        const int s = int(i / ((int64_t)nslots * Gp * P));
+        const int r = entry_region[s * nslots + slot];
+        psi[i] = (r >= 0 && g < G) ? (Real)(phi[(int64_t)r * G + g] / kFourPi) : Real(0);
+    }
+}
+
+// user <-> internal region order for [R][G] FP64 arrays
+__global__ void k_permute_rows(const double *__restrict__ src, double *__restrict__ dst, const int *__restrict__ user_of, int R,
+                               int G, int to_user) {
+    const int64_t n = (int64_t)R * G;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = int(i / G), g = int(i - (int64_t)r * G);
+        const int64_t u = (int64_t)user_of[r] * G + g;
+        if (to_user)
+            dst[u] = src[i];
+        else
+            dst[i] = src[u];
+    }
+}
+
+// validity of a guess: counts of non-finite or negative entries and the number of
+// positive entries
+__global__ void k_check_guess(const double *__restrict__ x, int64_t n, double *__restrict__ out) {
+    __shared__ double sh[16];
+    double bad = 0.0, pos = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = x[i];
+        if (!isfinite(v) || v < 0) bad += 1.0;
+        if (v > 0) pos += 1.0;
+    }
+    const double a = block_sum(bad, sh);
+    const double b = block_sum(pos, sh);
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], a);
+        atomicAdd(&out[1], b);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline int grid_for(int64_t n, int block, int cap = 4096) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+#define MOC_CHECK_LAUNCH()                                                      \
+    do {                                                                        \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess) throw Error(MOC_EHIP, hipGetErrorString(e_));     \
+    } while (0)
+
+template <typename Real, int NP, int GB, int MODE>
+static void sweep_inst(const SweepArgs &a, int nb, int n_gb, hipStream_t s) {
+    hipLaunchKernelGGL((k_sweep<Real, NP, GB, MODE>), dim3(nb, 2, n_gb), dim3(64), 0, s, a);
+}
+
+template <typename Real, int NP, int MODE>
+static bool sweep_gb(const SweepArgs &a, int nb, int gb, int n_gb, hipStream_t s) {
+    switch (gb) {
+        case 1: sweep_inst<Real, NP, 1, MODE>(a, nb, n_gb, s); return true;
+        case 2: sweep_inst<Real, NP, 2, MODE>(a, nb, n_gb, s); return true;
+        case 4: sweep_inst<Real, NP, 4, MODE>(a, nb, n_gb, s); return true;
+        case 7: sweep_inst<Real, NP, 7, MODE>(a, nb, n_gb, s); return true;
+        case 8: sweep_inst<Real, NP, 8, MODE>(a, nb, n_gb, s); return true;
+        case 11: sweep_inst<Real, NP, 11, MODE>(a, nb, n_gb, s); return true;
+        default: return false;
+    }
+}
+
+template <typename Real, int MODE>
+static bool sweep_np(const SweepArgs &a, int nb, int np, int gb, int n_gb, hipStream_t s) {
+    switch (np) {
+        case 1: return sweep_gb<Real, 1, MODE>(a, nb, gb, n_gb, s);
+        case 2: return sweep_gb<Real, 2, MODE>(a, nb, gb, n_gb, s);
+        case 3: return sweep_gb<Real, 3, MODE>(a, nb, gb, n_gb, s);
+        case 4: return sweep_gb<Real, 4, MODE>(a, nb, gb, n_gb, s);
+        default: return false;
+    }
+}
+
+void launch_sweep(const SweepArgs &a, int precision, int exp_mode, int nb, int np, int gb, int n_gb, hipStream_t s) {
+    bool ok;
+    if (precision == MOC_PREC_F64) {
+        ok = sweep_np<double, MOC_EXP_POLY>(a, nb, np, gb, n_gb, s);
+    } else if (exp_mode == MOC_EXP_TABLE) {
+        ok = sweep_np<float, MOC_EXP_TABLE>(a, nb, np, gb, n_gb, s);
+    } else if (exp_mode == MOC_EXP_LIBM) {
+        ok = sweep_np<float, MOC_EXP_LIBM>(a, nb, np, gb, n_gb, s);
+    } else {
+        ok = sweep_np<float, MOC_EXP_POLY>(a, nb, np, gb, n_gb, s);
+    }
+    if (!ok) throw Error(MOC_EINVAL, "sweep: no kernel instance for this polar count / group batch");
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_fill_real(void *p, int64_t n, int precision, hipStream_t s) {
+    if (precision == MOC_PREC_F64)
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, (double *)p, n, 0.0);
+    else
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, (float *)p, n, 0.0f);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_scale_real(void *p, int64_t n, int precision, const double *f, hipStream_t s) {
+    if (precision == MOC_PREC_F64)
+        hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, (double *)p, n, f);
+    else
+        hipLaunchKernelGGL(k_scale<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, (float *)p, n, f);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_scale_f64(double *p, int64_t n, const double *f, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, f);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_prep_user(const DevProblem &d, const double *src_user, hipStream_t s) {
+    const int64_t n = (int64_t)d.R * d.Gp;
+    if (d.precision == MOC_PREC_F64)
+        hipLaunchKernelGGL(k_prep_user<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, src_user, d.user_of, d.mat, d.sigt_m,
+                           (double *)d.qhat, d.R, d.G, d.Gp);
+    else
+        hipLaunchKernelGGL(k_prep_user<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, src_user, d.user_of, d.mat, d.sigt_m,
+                           (float *)d.qhat, d.R, d.G, d.Gp);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_source(const DevProblem &d, const double *phi, hipStream_t s) {
+    const int grid = grid_for(d.R, 256, 8192);
+    if (d.precision == MOC_PREC_F64)
+        hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(256), 0, s, phi, d.scal, d.mat, d.sigt_m, d.sigs_m, d.nsf_m,
+                           d.chi_m, d.qext, (double *)d.qhat, d.R, d.G, d.Gp);
+    else
+        hipLaunchKernelGGL(k_source<float>, dim3(grid), dim3(256), 0, s, phi, d.scal, d.mat, d.sigt_m, d.sigs_m, d.nsf_m,
+                           d.chi_m, d.qext, (float *)d.qhat, d.R, d.G, d.Gp);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_finalize(const DevProblem &d, double *phi_internal, double *phi_user, double *partials, hipStream_t s) {
+    if (d.precision == MOC_PREC_F64)
+        hipLaunchKernelGGL(k_finalize<double>, dim3(kReduceBlocks), dim3(256), 0, s, (const double *)d.qhat, d.tally, d.V, d.mat,
+                           d.sigt_m, d.nsf_m, phi_internal, phi_user, d.user_of, partials, d.R, d.G, d.Gp);
+    else
+        hipLaunchKernelGGL(k_finalize<float>, dim3(kReduceBlocks), dim3(256), 0, s, (const float *)d.qhat, d.tally, d.V, d.mat,
+                           d.sigt_m, d.nsf_m, phi_internal, phi_user, d.user_of, partials, d.R, d.G, d.Gp);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_fission_partials(const DevProblem &d, const double *phi, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_fission_partials, dim3(kReduceBlocks), dim3(256), 0, s, phi, d.V, d.mat, d.nsf_m, partials, d.R, d.G);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_eigen_update(const DevProblem &d, const double *partials, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_eigen_update, dim3(1), dim3(256), 0, s, partials, kReduceBlocks, d.scal, mode);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_norm_residual(const DevProblem &d, double *phi_new, const double *phi_old, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm_residual, dim3(kReduceBlocks), dim3(256), 0, s, phi_new, phi_old, d.V, d.scal, partials, d.R, d.G);
+    hipLaunchKernelGGL(k_residual, dim3(1), dim3(256), 0, s, partials, kReduceBlocks, d.scal);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_psi_canon(const DevProblem &d, double *canon, void *psi, int to_canon, hipStream_t s) {
+    const int64_t n = (int64_t)d.T * 2 * d.P * d.G;
+    if (n == 0) return;
+    if (d.precision == MOC_PREC_F64)
+        hipLaunchKernelGGL(k_psi_canon<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, canon, (double *)psi, d.slot_of_canon,
+                           d.T, d.P, d.G, d.Gp, d.nslots, to_canon);
+    else
+        hipLaunchKernelGGL(k_psi_canon<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, canon, (float *)psi, d.slot_of_canon,
+                           d.T, d.P, d.G, d.Gp, d.nslots, to_canon);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_psi_from_phi(const DevProblem &d, const double *phi_internal, void *psi, hipStream_t s) {
+    const int64_t n = (int64_t)2 * d.P * d.Gp * d.nslots;
+    if (d.precision == MOC_PREC_F64)
+        hipLaunchKernelGGL(k_psi_from_phi<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, phi_internal, d.entry_region,
+                           (double *)psi, d.P, d.G, d.Gp, d.nslots);
+    else
+        hipLaunchKernelGGL(k_psi_from_phi<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, phi_internal, d.entry_region,
+                           (float *)psi, d.P, d.G, d.Gp, d.nslots);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_permute_rows(const DevProblem &d, const double *src, double *dst, int to_user, hipStream_t s) {
+    const int64_t n = (int64_t)d.R * d.G;
+    hipLaunchKernelGGL(k_permute_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, d.user_of, d.R, d.G, to_user);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_check_guess(const double *x, int64_t n, double *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, s, out2, (int64_t)2, 0.0);
+    hipLaunchKernelGGL(k_check_guess, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, x, n, out2);
+    MOC_CHECK_LAUNCH();
+}
+
+}  // namespace moc

@@ -1,0 +1,307 @@
+"""Python binding of libmoc (include/moc.h): argument marshalling only.
+
+Every step of the transport path runs in libmoc's C++ host setup and HIP kernels; this
+module converts numpy arrays and torch device tensors into the C structures and
+pointers the ABI takes. PyTorch is used only to own device memory and streams.
+
+If ``libmoc.so`` has not been built the import of :func:`lib` raises; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmoc.so")
+
+MOC_OK, MOC_EINVAL, MOC_ENOMEM, MOC_EHIP, MOC_ENOCONV, MOC_ESTATE = range(6)
+PREC = {"f32": 0, "f64": 1}
+EXP = {"poly": 0, "table": 1, "libm": 2}
+FLAG_FELL_BACK_TO_COLD = 1
+FLAG_FIXED_SOURCE = 2
+
+_i32, _i64, _f64 = C.c_int32, C.c_int64, C.c_double
+_P = C.POINTER
+
+
+class MocMesh(C.Structure):
+    _fields_ = [("n_vertices", _i32), ("xy", _P(_f64)), ("n_triangles", _i32), ("tri", _P(_i32)),
+                ("tri_region", _P(_i32)), ("n_regions", _i32), ("region_material", _P(_i32)),
+                ("domain", _i32), ("box", _f64 * 4), ("hex_apothem", _f64), ("bc", _i32 * 6)]
+
+
+class MocTracks(C.Structure):
+    _fields_ = [("n_azim", _i32), ("n_polar", _i32), ("spacing", _f64),
+                ("polar_mu", _P(_f64)), ("polar_w", _P(_f64))]
+
+
+class MocXS(C.Structure):
+    _fields_ = [("n_materials", _i32), ("n_groups", _i32), ("sigma_t", _P(_f64)),
+                ("sigma_s", _P(_f64)), ("nu_sigma_f", _P(_f64)), ("chi", _P(_f64))]
+
+
+class MocOptions(C.Structure):
+    _fields_ = [("precision", _i32), ("exp_mode", _i32), ("max_iter", _i32), ("device", _i32),
+                ("check_every", _i32), ("n_threads", _i32)]
+
+
+class MocResult(C.Structure):
+    _fields_ = [("k", _f64), ("iterations", _i32), ("residual", _f64), ("dk", _f64),
+                ("wall_ms", _f64), ("flags", _i32)]
+
+
+class MocInfo(C.Structure):
+    _fields_ = [("n_regions", _i32), ("n_groups", _i32), ("n_materials", _i32), ("n_polar", _i32),
+                ("n_angles", _i32), ("n_tracks", _i32), ("n_segments", _i64), ("n_updates", _i64),
+                ("n_padded_steps", _i64), ("n_batches", _i32), ("setup_ms", _f64),
+                ("device_bytes", _i64), ("precision", _i32)]
+
+
+class MocProfile(C.Structure):
+    _fields_ = [("sweeps", _i64), ("sweep_ms", _f64), ("sweep_ms_min", _f64), ("sweep_ms_max", _f64)]
+
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "moc_create": (C.c_int, [_P(MocMesh), _P(MocTracks), _P(MocXS), _P(MocOptions), _P(C.c_void_p)]),
+    "moc_destroy": (None, [C.c_void_p]),
+    "moc_sweep": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "moc_solve": (C.c_int, [C.c_void_p, _f64, _P(MocResult)]),
+    "moc_run_iterations": (C.c_int, [C.c_void_p, C.c_int, _P(MocResult)]),
+    "moc_set_initial_guess": (C.c_int, [C.c_void_p, C.c_void_p, _f64, C.c_void_p]),
+    "moc_get_flux": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "moc_get_boundary_flux": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "moc_set_boundary_flux": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "moc_set_exit_flux_buffer": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "moc_set_external_source": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "moc_get_info": (C.c_int, [C.c_void_p, _P(MocInfo)]),
+    "moc_get_volumes": (C.c_int, [C.c_void_p, _P(_f64)]),
+    "moc_get_tracks": (C.c_int, [C.c_void_p, _P(_i32), _P(_f64), _P(_i64), _P(_i32), _P(_f64), _P(_i32)]),
+    "moc_get_quadrature": (C.c_int, [C.c_void_p, _P(_f64), _P(_f64), _P(_f64), _P(_f64), _P(_f64)]),
+    "moc_last_error": (C.c_char_p, [C.c_void_p]),
+    "moc_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "moc_get_profile": (C.c_int, [C.c_void_p, _P(MocProfile)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmoc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_01591_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MocError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libmoc error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(_P(ct))
+
+
+def _dptr(t) -> int:
+    """Device pointer of a contiguous torch CUDA tensor."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream_handle(stream=None) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Solver:
+    """One libmoc context for a problem (see ``problems.Problem``).
+
+    precision: "f32" (FP32 sweep, FP64 source/eigenvalue/norms/tallies) or "f64".
+    device: HIP device ordinal, or -1 for a host-only context (tracking, volumes,
+    quadrature and info; no sweeps).
+    """
+
+    def __init__(self, prob, precision: str = "f32", exp_mode: str = "poly", device: int = 0,
+                 max_iter: int = 10000, check_every: int = 1, n_threads: int = 0,
+                 polar: Optional[tuple] = None):
+        L = lib()
+        self._keep = []
+
+        def keep(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        xy = keep(prob.xy, np.float64)
+        tri = keep(prob.tri, np.int32)
+        tr = keep(prob.tri_region, np.int32)
+        rm = keep(prob.region_material, np.int32)
+        m = MocMesh()
+        m.n_vertices, m.xy = len(xy), _ptr(xy, _f64)
+        m.n_triangles, m.tri, m.tri_region = len(tri), _ptr(tri, _i32), _ptr(tr, _i32)
+        m.n_regions, m.region_material = int(prob.n_regions), _ptr(rm, _i32)
+        m.domain = int(prob.domain)
+        for i in range(4):
+            m.box[i] = float(prob.box[i])
+        m.hex_apothem = float(prob.hex_apothem)
+        for i, b in enumerate(np.asarray(prob.bc).ravel()):
+            m.bc[i] = int(b)
+        t = MocTracks()
+        t.n_azim, t.n_polar, t.spacing = int(prob.n_azim), int(prob.n_polar), float(prob.spacing)
+        if polar is not None:
+            mu, w = keep(polar[0], np.float64), keep(polar[1], np.float64)
+            t.polar_mu, t.polar_w = _ptr(mu, _f64), _ptr(w, _f64)
+        st = keep(prob.sigma_t, np.float64)
+        ss = keep(prob.sigma_s, np.float64)
+        nsf = keep(prob.nu_sigma_f, np.float64)
+        chi = keep(prob.chi, np.float64)
+        x = MocXS()
+        x.n_materials, x.n_groups = st.shape
+        x.sigma_t, x.sigma_s, x.nu_sigma_f, x.chi = (_ptr(st, _f64), _ptr(ss, _f64),
+                                                     _ptr(nsf, _f64), _ptr(chi, _f64))
+        o = MocOptions(PREC[precision], EXP[exp_mode], max_iter, device, check_every, n_threads)
+        h = C.c_void_p()
+        rc = L.moc_create(C.byref(m), C.byref(t), C.byref(x), C.byref(o), C.byref(h))
+        if rc != MOC_OK:
+            raise MocError(rc, L.moc_last_error(None).decode())
+        self._h = h
+        self._keep = []
+        self.device = device
+        self.precision = precision
+        inf = MocInfo()
+        L.moc_get_info(self._h, C.byref(inf))
+        self.info = {k: getattr(inf, k) for k, _ in MocInfo._fields_}
+        self.R, self.G, self.P = inf.n_regions, inf.n_groups, inf.n_polar
+        self.T, self.S, self.U = inf.n_tracks, inf.n_segments, inf.n_updates
+        self._exit = None
+        self._qext = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.moc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc, ok=(MOC_OK,)):
+        if rc not in ok:
+            raise MocError(rc, lib().moc_last_error(self._h).decode())
+        return rc
+
+    # ---------------------------------------------------------------- device calls
+    def sweep(self, source, out=None, stream=None):
+        """One sweep for an emission density ``source`` (device FP64 [R, G]); returns
+        the scalar flux (device FP64 [R, G]). Enqueued on the current torch stream."""
+        import torch
+        if out is None:
+            out = torch.empty((self.R, self.G), dtype=torch.float64, device=source.device)
+        self._check(lib().moc_sweep(self._h, _dptr(source), _dptr(out), _stream_handle(stream)))
+        return out
+
+    def solve(self, tol: float = 1e-6, raise_on_noconv: bool = False) -> dict:
+        import torch
+        torch.cuda.current_stream().synchronize()
+        r = MocResult()
+        rc = lib().moc_solve(self._h, tol, C.byref(r))
+        self._check(rc, (MOC_OK,) if raise_on_noconv else (MOC_OK, MOC_ENOCONV))
+        return dict(k=r.k, iterations=r.iterations, residual=r.residual, dk=r.dk,
+                    wall_ms=r.wall_ms, flags=r.flags, converged=(rc == MOC_OK))
+
+    def flux(self, stream=None):
+        import torch
+        out = torch.empty((self.R, self.G), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._check(lib().moc_get_flux(self._h, _dptr(out), _stream_handle(stream)))
+        return out
+
+    def psi_shape(self):
+        return (self.T, 2, self.P, self.G)
+
+    def get_boundary_flux(self, stream=None):
+        import torch
+        out = torch.empty(self.psi_shape(), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._check(lib().moc_get_boundary_flux(self._h, _dptr(out), _stream_handle(stream)))
+        return out
+
+    def set_boundary_flux(self, psi, stream=None):
+        self._keep_psi = psi.contiguous()
+        self._check(lib().moc_set_boundary_flux(self._h, _dptr(self._keep_psi), _stream_handle(stream)))
+
+    def set_exit_buffer(self, buf):
+        """Record the outgoing angular flux of every track-sense in ``buf`` (device FP64
+        [T, 2, P, G]) on every following sweep; None disables."""
+        self._exit = buf
+        self._check(lib().moc_set_exit_flux_buffer(self._h, None if buf is None else _dptr(buf)))
+
+    def set_external_source(self, q):
+        import torch
+        if q is None:
+            self._check(lib().moc_set_external_source(self._h, None))
+            return
+        torch.cuda.current_stream().synchronize()
+        self._check(lib().moc_set_external_source(self._h, _dptr(q.contiguous())))
+
+    def set_initial_guess(self, phi0, k0: float = 1.0, psi0=None):
+        import torch
+        torch.cuda.current_stream().synchronize()
+        self._check(lib().moc_set_initial_guess(self._h, _dptr(phi0), float(k0),
+                                                None if psi0 is None else _dptr(psi0)))
+
+    def set_profiling(self, enable: bool = True):
+        self._check(lib().moc_set_profiling(self._h, int(enable)))
+
+    def profile(self) -> dict:
+        p = MocProfile()
+        self._check(lib().moc_get_profile(self._h, C.byref(p)))
+        return dict(sweeps=p.sweeps, sweep_ms=p.sweep_ms, sweep_ms_min=p.sweep_ms_min,
+                    sweep_ms_max=p.sweep_ms_max)
+
+    def run_iterations(self, n: int) -> dict:
+        """Exactly n power (or source) iterations from a cold start, with one
+        convergence read-back at the end (used for timing)."""
+        r = MocResult()
+        import torch
+        torch.cuda.current_stream().synchronize()
+        self._check(lib().moc_run_iterations(self._h, int(n), C.byref(r)))
+        return dict(k=r.k, iterations=r.iterations, residual=r.residual, dk=r.dk, wall_ms=r.wall_ms)
+
+    # ---------------------------------------------------------------- host queries
+    def volumes(self) -> np.ndarray:
+        V = np.zeros(self.R)
+        self._check(lib().moc_get_volumes(self._h, _ptr(V, _f64)))
+        return V
+
+    def quadrature(self) -> dict:
+        NA, P = self.info["n_angles"], self.P
+        phi, dl, wa = np.zeros(NA), np.zeros(NA), np.zeros(NA)
+        mu, wp = np.zeros(P), np.zeros(P)
+        self._check(lib().moc_get_quadrature(self._h, _ptr(phi, _f64), _ptr(dl, _f64), _ptr(wa, _f64),
+                                             _ptr(mu, _f64), _ptr(wp, _f64)))
+        return dict(phi=phi, delta=dl, w=wa, mu=mu, w_polar=wp)
+
+    def tracks(self) -> dict:
+        T, S = self.T, self.S
+        ang = np.zeros(T, np.int32)
+        xy = np.zeros((T, 4))
+        off = np.zeros(T + 1, np.int64)
+        reg = np.zeros(S, np.int32)
+        ln = np.zeros(S)
+        link = np.zeros((T, 2), np.int32)
+        self._check(lib().moc_get_tracks(self._h, _ptr(ang, _i32), _ptr(xy, _f64), _ptr(off, _i64),
+                                         _ptr(reg, _i32), _ptr(ln, _f64), _ptr(link, _i32)))
+        return dict(angle=ang, xy=xy, offset=off, region=reg, length=ln, link=link)
