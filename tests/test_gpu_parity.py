@@ -151,7 +151,13 @@ def test_solve_matches_oracle(name, precision, oracle_solutions, cuda):
         # same scheme as the oracle: the iteration counts agree closely
         assert abs(r["iterations"] - ref["iterations"]) <= 2
     else:
-        assert abs(r["k"] - ref["k"]) < 1e-5
+        # A 1e-6 residual bounds the step, not the distance to the fixed point (that is
+        # about residual / (1 - dominance ratio)); to compare converged answers, run the
+        # FP32 path for as many iterations as the oracle needed for its tighter tolerance.
+        assert abs(r["k"] - ref["k"]) < 1e-4
+        r2 = s.run_iterations(ref["iterations"] + 10)
+        phi = _host(s.flux())
+        assert abs(r2["k"] - ref["k"]) < 1e-5
         assert rel_err(phi, ref["phi"]) < 1e-5
 
 
