@@ -107,6 +107,9 @@ typedef struct {
                             MOC_ESTATE) */
     int32_t check_every; /* moc_solve reads (k, residual) back every this many iterations (<= 0: 1) */
     int32_t n_threads;   /* host threads for tracking (<= 0: all hardware threads) */
+    double window_cm;    /* tally window length along the tracks in cm (<= 0: about 32
+                            segments per window) */
+    int32_t tally_slots; /* maximum distinct regions per tally window, 64..512 (0: 256) */
 } moc_options;
 
 typedef struct {
@@ -125,6 +128,11 @@ typedef struct {
     int64_t n_updates;         /* U = 2 * P * G * S per sweep */
     int64_t n_padded_steps;    /* segment slots the sweep walks (incl. padding), per sense */
     int32_t n_batches;         /* 64-track wavefront batches */
+    int64_t n_windows;         /* tally windows over all batches */
+    int64_t n_window_slots;    /* sum of distinct regions over all windows (tally flushes per
+                                  group and sense) */
+    double window_cm;          /* tally window length used */
+    int32_t max_window_slots;  /* largest slot count of any window */
     double setup_ms;           /* host setup time of moc_create */
     int64_t device_bytes;      /* device memory held by the context */
     int32_t precision;
@@ -214,6 +222,17 @@ int moc_get_volumes(const moc_ctx *ctx, double *V_host);
  * (destination track*2+sense, or -1 for vacuum). Any pointer may be NULL. */
 int moc_get_tracks(moc_ctx *ctx, int32_t *angle, double *endpoints, int64_t *offsets,
                    int32_t *seg_region, double *seg_length, int32_t *links);
+
+/* Packed sweep layout of a host-only context (MOC_ESTATE otherwise), for tests: batch
+ * window ranges [n_batches + 1] and angles [n_batches]; per window: first entry,
+ * steps, first slot-table entry and slot count [n_windows]; slot table (internal region
+ * ids) [n_window_slots]; per entry [n_padded_steps]: length and key = (internal region
+ * << 9) | slot; the user id of each internal region [n_regions]. Entries of a window
+ * are [step][64 lanes]. Any pointer may be NULL. */
+int moc_get_packing(const moc_ctx *ctx, int64_t *batch_win, int32_t *batch_angle,
+                    int64_t *win_entry_off, int32_t *win_nsteps, int64_t *win_tab_off,
+                    int32_t *win_nslots, int32_t *win_tab, double *seg_len, uint32_t *seg_key,
+                    int32_t *user_of_internal);
 
 /* Quadrature actually used: per track angle phi, delta, weight [n_angles]; polar
  * mu, weight [n_polar]. Any pointer may be NULL. */

@@ -8,6 +8,7 @@
 #include <thread>
 
 #include "moc_kernels.h"
+#include "moc_pack.h"
 
 using namespace moc;
 
@@ -28,7 +29,13 @@ struct moc_ctx {
     std::vector<int> slot_of_canon;
     std::vector<double> V_user;
     std::vector<double> sigt_m_host, nsf_m_host;
-    int64_t S = 0, padded_steps = 0;
+    int64_t S = 0, padded_steps = 0, n_windows = 0, n_slots_total = 0;
+    double window_len = 0;
+    // host-only contexts keep the packed layout for inspection
+    PackOutput host_pack;
+    std::vector<SegF> host_segs_f32;
+    std::vector<SegD> host_segs_f64;
+    std::vector<int> host_batch_angle;
     int64_t device_bytes = 0;
     double setup_ms = 0;
     int max_iter = 10000, check_every = 1, n_threads = 1;
@@ -118,30 +125,6 @@ static int choose_group_batch(int G) {
 
 namespace {
 
-struct CountSink : SegmentSink {
-    int64_t n = 0;
-    void emit(int, double) override { ++n; }
-};
-
-template <typename Seg> struct PackSink : SegmentSink {
-    Seg *base = nullptr;  // first entry of the lane in its batch
-    const int *internal_of_user = nullptr;
-    double *V = nullptr;  // thread-local volumes
-    double w = 0;         // w_a * delta_a
-    int64_t k = 0;
-    int first = -1, last = -1;
-    void emit(int r, double len) override {
-        const int ri = internal_of_user[r];
-        Seg &s = base[k * kBatch];
-        s.len = (decltype(s.len))len;
-        s.reg = ri;
-        V[ri] += w * len;
-        if (first < 0) first = ri;
-        last = ri;
-        ++k;
-    }
-};
-
 struct DumpSink : SegmentSink {
     std::vector<int> reg;
     std::vector<double> len;
@@ -151,51 +134,7 @@ struct DumpSink : SegmentSink {
     }
 };
 
-struct SegF {
-    float len;
-    int reg;
-};
-struct alignas(16) SegD {
-    double len;
-    int reg;
-    int pad;
-};
-
 }  // namespace
-
-template <typename Seg>
-static void pack_segments(moc_ctx *c, const std::vector<int> &counts, const std::vector<int64_t> &batch_off,
-                          const std::vector<int> &batch_of_track, std::vector<int> &entry_region, std::vector<double> &V) {
-    const int T = c->tracks.T;
-    const int64_t total = batch_off.empty() ? 0 : batch_off.back();
-    std::vector<Seg> host((size_t)total);
-    std::memset((void *)host.data(), 0, sizeof(Seg) * host.size());
-    const int nth = c->n_threads;
-    std::vector<std::vector<double>> Vt(nth, std::vector<double>(c->mesh.R, 0.0));
-    entry_region.assign(2 * (size_t)c->d.nslots, -1);
-    parallel_for(T, nth, 64, [&](int64_t b, int64_t e, int w) {
-        PackSink<Seg> sink;
-        sink.internal_of_user = c->internal_of_user.data();
-        sink.V = Vt[w].data();
-        for (int64_t t = b; t < e; ++t) {
-            const int slot = c->slot_of_canon[t];
-            const int bt = batch_of_track[t];
-            sink.base = host.data() + batch_off[bt] + (slot - bt * kBatch);
-            sink.k = 0;
-            sink.first = sink.last = -1;
-            const int a = c->tracks.angle[t];
-            sink.w = c->quad.wa[a] * c->quad.delta[a];
-            const int64_t n = trace_track(c->mesh, c->quad, c->tracks, (int)t, sink);
-            if (n != counts[t]) throw Error(MOC_EINVAL, "tracking: non-deterministic segment count");
-            entry_region[slot] = sink.first;                     // sense 0 enters at the first segment
-            entry_region[c->d.nslots + slot] = sink.last;        // sense 1 at the last
-        }
-    });
-    V.assign(c->mesh.R, 0.0);
-    for (int w = 0; w < nth; ++w)
-        for (int r = 0; r < c->mesh.R; ++r) V[r] += Vt[w][r];
-    c->d.segs = c->upload(host);
-}
 
 static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const moc_xs *xs, const moc_options *opt,
                         moc_ctx *c) {
@@ -205,6 +144,8 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     o.precision = MOC_PREC_F32;
     o.exp_mode = MOC_EXP_POLY;
     if (opt) o = *opt;
+    if (o.tally_slots != 0 && (o.tally_slots < kBatch || o.tally_slots > (1 << kSlotBits)))
+        throw Error(MOC_EINVAL, "options: tally_slots must be 0 or in 64..512");
     if (o.precision != MOC_PREC_F32 && o.precision != MOC_PREC_F64) throw Error(MOC_EINVAL, "options: bad precision");
     if (o.exp_mode < MOC_EXP_POLY || o.exp_mode > MOC_EXP_LIBM) throw Error(MOC_EINVAL, "options: bad exp_mode");
     c->max_iter = o.max_iter > 0 ? o.max_iter : 10000;
@@ -282,41 +223,76 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     std::vector<int> canon_of_slot(d.nslots, -1);
     for (int t = 0; t < T; ++t) canon_of_slot[c->slot_of_canon[t]] = t;
 
-    // ---- pass 1: segment counts
-    std::vector<int> counts(T, 0);
-    parallel_for(T, c->n_threads, 64, [&](int64_t b, int64_t e, int) {
-        CountSink cs;
-        for (int64_t t = b; t < e; ++t) {
-            cs.n = 0;
-            counts[t] = (int)trace_track(c->mesh, c->quad, c->tracks, (int)t, cs);
+    // ---- trace, cut into tally windows, pack (two deterministic passes over batches)
+    PackInput pin;
+    pin.mesh = &c->mesh;
+    pin.quad = &c->quad;
+    pin.tracks = &c->tracks;
+    pin.internal_of_user = c->internal_of_user.data();
+    pin.n_threads = c->n_threads;
+    pin.cap = o.tally_slots > 0 ? o.tally_slots : 256;
+    {
+        double total_len = 0;
+        for (int t = 0; t < T; ++t) total_len += c->tracks.len[t];
+        pin.window_len = o.window_cm > 0 ? o.window_cm : 0.0;
+        if (pin.window_len <= 0) {
+            // about 32 segments per lane per window: estimate the mean segment length
+            // from a sample of tracks
+            struct Cnt : SegmentSink {
+                int64_t n = 0;
+                void emit(int, double) override { ++n; }
+            } cnt;
+            double len = 0;
+            const int stride = std::max(1, T / 512);
+            for (int t = 0; t < T; t += stride) {
+                trace_track(c->mesh, c->quad, c->tracks, t, cnt);
+                len += c->tracks.len[t];
+            }
+            pin.window_len = 32.0 * len / std::max<int64_t>(1, cnt.n);
         }
-    });
-    std::vector<int> batch_n(d.nb, 0);
-    for (int t = 0; t < T; ++t) batch_n[batch_of_track[t]] = std::max(batch_n[batch_of_track[t]], counts[t]);
-    std::vector<int64_t> batch_off(d.nb + 1, 0);
-    for (int b = 0; b < d.nb; ++b) batch_off[b + 1] = batch_off[b] + (int64_t)batch_n[b] * kBatch;
-    c->S = 0;
-    for (int t = 0; t < T; ++t) c->S += counts[t];
-    c->padded_steps = batch_off[d.nb];
-
-    // ---- pass 2: pack segments, volumes, entry regions
-    std::vector<int> entry_region;
-    std::vector<double> V_internal;
-    if (f64)
-        pack_segments<SegD>(c, counts, batch_off, batch_of_track, entry_region, V_internal);
-    else
-        pack_segments<SegF>(c, counts, batch_off, batch_of_track, entry_region, V_internal);
+    }
+    pin.batch_first.assign(d.nb + 1, T);
+    for (int t = T - 1; t >= 0; --t) pin.batch_first[batch_of_track[t]] = t;
+    PackOutput pk;
+    if (f64) {
+        std::vector<SegD> segs;
+        pack_segments_f64(pin, pk, segs);
+        d.segs = c->upload(segs);
+        if (c->host_only) c->host_segs_f64.swap(segs);
+    } else {
+        std::vector<SegF> segs;
+        pack_segments_f32(pin, pk, segs);
+        d.segs = c->upload(segs);
+        if (c->host_only) c->host_segs_f32.swap(segs);
+    }
+    c->S = pk.S;
+    c->padded_steps = pk.entries;
+    c->window_len = pin.window_len;
+    c->n_windows = (int64_t)pk.win_nsteps.size();
+    c->n_slots_total = (int64_t)pk.tab.size();
+    std::vector<double> &V_internal = pk.V;
     for (int r = 0; r < R; ++r)
         if (!(V_internal[r] > 0))
             throw Error(MOC_EINVAL, "tracking: region " + std::to_string(c->user_of_internal[r]) +
                                         " is crossed by no track (refine the track spacing)");
     c->V_user.assign(R, 0.0);
     for (int r = 0; r < R; ++r) c->V_user[c->user_of_internal[r]] = V_internal[r];
-    batch_off.pop_back();
-    d.batch_off = c->upload(batch_off);
-    d.batch_n = c->upload(batch_n);
+    d.cap = pin.cap;
+    int max_slots = 1;
+    for (int v : pk.win_nslots) max_slots = std::max(max_slots, v);
+    d.max_slots = max_slots;
+    d.batch_win = c->upload(pk.batch_win);
+    d.win_entry_off = c->upload(pk.win_entry_off);
+    d.win_nsteps = c->upload(pk.win_nsteps);
+    d.win_tab_off = c->upload(pk.win_tab_off);
+    d.win_nslots = c->upload(pk.win_nslots);
+    d.win_tab = c->upload(pk.tab);
     d.batch_angle = c->upload(batch_angle);
-    d.entry_region = c->upload(entry_region);
+    d.entry_region = c->upload(pk.entry_region);
+    if (c->host_only) {
+        c->host_pack = pk;
+        c->host_batch_angle = batch_angle;
+    }
     d.slot_of_canon = c->upload(c->slot_of_canon);
     d.canon_of_slot = c->upload(canon_of_slot);
 
@@ -410,8 +386,13 @@ static void sweep_impl(moc_ctx *c, hipStream_t s) {
     launch_fill_f64(d.tally, (int64_t)d.R * d.Gp, 0.0, s);
     SweepArgs a{};
     a.segs = d.segs;
-    a.batch_off = d.batch_off;
-    a.batch_n = d.batch_n;
+    a.batch_win = d.batch_win;
+    a.win_entry_off = d.win_entry_off;
+    a.win_nsteps = d.win_nsteps;
+    a.win_tab_off = d.win_tab_off;
+    a.win_nslots = d.win_nslots;
+    a.win_tab = d.win_tab;
+    a.cap = d.max_slots;
     a.batch_angle = d.batch_angle;
     a.sigt = d.sigt_r;
     a.qhat = d.qhat;
@@ -664,6 +645,10 @@ int moc_get_info(const moc_ctx *c, moc_info *info) {
     info->n_updates = 2LL * c->d.P * c->d.G * c->S;
     info->n_padded_steps = c->padded_steps;
     info->n_batches = c->d.nb;
+    info->n_windows = c->n_windows;
+    info->n_window_slots = c->n_slots_total;
+    info->window_cm = c->window_len;
+    info->max_window_slots = c->d.max_slots;
     info->setup_ms = c->setup_ms;
     info->device_bytes = c->device_bytes;
     info->precision = c->d.precision;
@@ -744,6 +729,38 @@ int moc_get_tracks(moc_ctx *c, int32_t *angle, double *endpoints, int64_t *offse
         }
         if (offsets) offsets[t.T] = off;
     });
+}
+
+int moc_get_packing(const moc_ctx *c, int64_t *batch_win, int32_t *batch_angle, int64_t *win_entry_off,
+                    int32_t *win_nsteps, int64_t *win_tab_off, int32_t *win_nslots, int32_t *win_tab,
+                    double *seg_len, uint32_t *seg_key, int32_t *user_of_internal) {
+    if (!c) return MOC_EINVAL;
+    if (!c->host_only) return MOC_ESTATE;
+    if (user_of_internal)
+        for (int r = 0; r < c->mesh.R; ++r) user_of_internal[r] = c->user_of_internal[r];
+    const PackOutput &pk = c->host_pack;
+    auto cp = [](auto *dst, const auto &v) {
+        if (dst)
+            for (size_t i = 0; i < v.size(); ++i) dst[i] = v[i];
+    };
+    cp(batch_win, pk.batch_win);
+    cp(batch_angle, c->host_batch_angle);
+    cp(win_entry_off, pk.win_entry_off);
+    cp(win_nsteps, pk.win_nsteps);
+    cp(win_tab_off, pk.win_tab_off);
+    cp(win_nslots, pk.win_nslots);
+    cp(win_tab, pk.tab);
+    const size_t n = c->d.precision == MOC_PREC_F64 ? c->host_segs_f64.size() : c->host_segs_f32.size();
+    for (size_t i = 0; i < n; ++i) {
+        if (c->d.precision == MOC_PREC_F64) {
+            if (seg_len) seg_len[i] = c->host_segs_f64[i].len;
+            if (seg_key) seg_key[i] = c->host_segs_f64[i].key;
+        } else {
+            if (seg_len) seg_len[i] = c->host_segs_f32[i].len;
+            if (seg_key) seg_key[i] = c->host_segs_f32[i].key;
+        }
+    }
+    return MOC_OK;
 }
 
 int moc_get_quadrature(const moc_ctx *c, double *phi, double *delta, double *w_azim, double *mu, double *w_polar) {

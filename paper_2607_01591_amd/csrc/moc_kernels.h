@@ -16,10 +16,15 @@ constexpr float kExpTableMax = 16.0f;
 constexpr int kReduceBlocks = 512;
 
 struct SweepArgs {
-    const void *segs;          // SegF / SegD interleaved per batch
-    const int64_t *batch_off;  // [nb] first segment entry of each batch
-    const int *batch_n;        // [nb] steps of each batch
-    const int *batch_angle;    // [nb]
+    const void *segs;             // SegF / SegD, per window [step][64 lanes]
+    const int64_t *batch_win;     // [nb + 1] window range of each batch
+    const int64_t *win_entry_off; // [nw] first entry of each window
+    const int *win_nsteps;        // [nw]
+    const int64_t *win_tab_off;   // [nw] first slot-table entry of each window
+    const int *win_nslots;        // [nw]
+    const int *win_tab;           // slot -> internal region
+    int cap;                      // LDS tally rows per group (>= every window's slot count)
+    const int *batch_angle;       // [nb]
     const void *sigt;          // Real [R][Gp]
     const void *qhat;          // Real [R][Gp]
     const void *psi_in;        // Real [2][P][Gp][nslots]
@@ -48,10 +53,12 @@ struct DevProblem {
     double *tally = nullptr;
     double *phi[2] = {nullptr, nullptr};
     double *qext = nullptr;
-    // tracks
+    // tracks and tally windows
     void *segs = nullptr;
-    int64_t *batch_off = nullptr;
-    int *batch_n = nullptr, *batch_angle = nullptr;
+    int64_t *batch_win = nullptr, *win_entry_off = nullptr, *win_tab_off = nullptr;
+    int *win_nsteps = nullptr, *win_nslots = nullptr, *win_tab = nullptr;
+    int *batch_angle = nullptr;
+    int cap = 256, max_slots = 1;
     void *psi[2] = {nullptr, nullptr};
     int *link = nullptr;
     unsigned char *fed = nullptr;

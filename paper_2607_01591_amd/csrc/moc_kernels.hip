@@ -13,20 +13,12 @@
 #include <cstdio>
 
 #include "moc_kernels.h"
+#include "moc_pack.h"
 
 namespace moc {
 
 static constexpr double kFourPi = 12.566370614359172953850573533118;
 
-struct SegF {
-    float len;
-    int reg;
-};
-struct alignas(16) SegD {
-    double len;
-    int reg;
-    int pad;
-};
 template <typename Real> struct SegOf;
 template <> struct SegOf<float> { using type = SegF; };
 template <> struct SegOf<double> { using type = SegD; };
@@ -78,28 +70,34 @@ template <typename Real, int MODE> __device__ __forceinline__ Real one_minus_exp
 
 // ---------------------------------------------------------------- sweep
 // One wavefront = one batch of 64 adjacent parallel tracks of one angle, one sense and
-// one group batch [g0, g0 + GB). Lane l walks track l of the batch; all lanes step
-// through the interleaved segment stream together. Per segment and group the update is
-// Eq. MOC_sol: psi_out = qhat + (psi_in - qhat) e^-tau, tau = Sigma_t l / sin(theta_p);
-// the increment Delta = (psi - qhat)(1 - e^-tau) is summed over polar angles with weights
-// c_ap = 2 pi w_a w_p delta_a sin(theta_p) in registers and added to the region tally
-// with one FP64 atomic per (segment, group).
+// one group batch [g0, g0 + GB). Lane l walks track l; the lanes step together through
+// the batch's tally windows (forward windows and steps in order for sense 0, both
+// reversed for sense 1). Per segment and group the update is Eq. MOC_sol:
+// psi_out = qhat + (psi_in - qhat) e^-tau with tau = Sigma_t l / sin(theta_p); the
+// increment Delta = (psi - qhat)(1 - e^-tau) is summed over the polar angles with the
+// weights c_ap = 2 pi w_a w_p delta_a sin(theta_p) in registers, then added to the
+// window-local tally slot in LDS. At the end of each window every slot is flushed with
+// one FP64 atomic per group (consecutive lanes hit consecutive groups of a region row).
 template <typename Real, int NP, int GB, int MODE>
 __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     using Seg = typename SegOf<Real>::type;
-    __shared__ float lut[MODE == MOC_EXP_TABLE ? ExpTable::kN : 1];
+    extern __shared__ unsigned char smem[];
+    Real *tl = reinterpret_cast<Real *>(smem);   // tally [GB][cap]
+    const int cap = args.cap;
+    float *lut = reinterpret_cast<float *>(smem + sizeof(Real) * GB * cap);
     if constexpr (MODE == MOC_EXP_TABLE && sizeof(Real) == 4) {
         for (int i = threadIdx.x; i < ExpTable::kN; i += 64) lut[i] = args.exp_table[i];
-        __syncthreads();
     }
+    for (int i = threadIdx.x; i < GB * cap; i += 64) tl[i] = Real(0);
+    __syncthreads();
+
     const int b = blockIdx.x, sense = blockIdx.y, gb = blockIdx.z, lane = threadIdx.x;
     const int nslots = args.nslots;
     const int slot = b * 64 + lane;
     const int g0 = gb * GB;
     const int Gp = args.Gp;
-    const int n = args.batch_n[b];
     const int a = args.batch_angle[b];
-    const Seg *__restrict__ segs = reinterpret_cast<const Seg *>(args.segs) + args.batch_off[b];
+    const Seg *__restrict__ segs = reinterpret_cast<const Seg *>(args.segs);
     const Real *__restrict__ sigt = reinterpret_cast<const Real *>(args.sigt);
     const Real *__restrict__ qhat = reinterpret_cast<const Real *>(args.qhat);
     const Real *__restrict__ psi_in = reinterpret_cast<const Real *>(args.psi_in);
@@ -120,30 +118,51 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
 #pragma unroll
         for (int j = 0; j < GB; ++j) psi[p][j] = psi_in[(int64_t)((sense * NP + p) * Gp + g0 + j) * nslots + slot];
 
-    for (int i = 0; i < n; ++i) {
-        const int k = sense ? n - 1 - i : i;
-        const Seg sg = segs[(int64_t)k * 64 + lane];
-        const Real len = sg.len;
-        const int64_t base = (int64_t)sg.reg * Gp + g0;
-        Real st[GB], q[GB];
+    const int64_t w0 = args.batch_win[b], w1 = args.batch_win[b + 1];
+    for (int64_t wi = 0; wi < w1 - w0; ++wi) {
+        const int64_t w = sense ? w1 - 1 - wi : w0 + wi;
+        const int n = args.win_nsteps[w];
+        const Seg *__restrict__ ws = segs + args.win_entry_off[w];
+        for (int i = 0; i < n; ++i) {
+            const int k = sense ? n - 1 - i : i;
+            const Seg sg = ws[(int64_t)k * 64 + lane];
+            const Real len = sg.len;
+            const uint32_t key = sg.key;
+            const int64_t base = (int64_t)(key >> kSlotBits) * Gp + g0;
+            const int ts = int(key & ((1u << kSlotBits) - 1));
+            Real st[GB], q[GB];
 #pragma unroll
-        for (int j = 0; j < GB; ++j) {
-            st[j] = sigt[base + j];
-            q[j] = qhat[base + j];
-        }
-#pragma unroll
-        for (int j = 0; j < GB; ++j) {
-            const Real sl = st[j] * len;
-            Real acc = 0;
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const Real F = one_minus_exp<Real, MODE>(sl * is[p], lut);
-                const Real d = (psi[p][j] - q[j]) * F;
-                psi[p][j] -= d;
-                acc += c[p] * d;
+            for (int j = 0; j < GB; ++j) {
+                st[j] = sigt[base + j];
+                q[j] = qhat[base + j];
             }
-            if (len > Real(0)) unsafeAtomicAdd(&tally[base + j], (double)acc);
+#pragma unroll
+            for (int j = 0; j < GB; ++j) {
+                const Real sl = st[j] * len;
+                Real acc = 0;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    const Real F = one_minus_exp<Real, MODE>(sl * is[p], lut);
+                    const Real d = (psi[p][j] - q[j]) * F;
+                    psi[p][j] -= d;
+                    acc += c[p] * d;
+                }
+                atomicAdd(&tl[j * cap + ts], acc);
+            }
         }
+        __syncthreads();
+        // flush the window's slots: (slot, group) pairs, groups fastest
+        const int ns = args.win_nslots[w];
+        const int *__restrict__ tab = args.win_tab + args.win_tab_off[w];
+        for (int e = lane; e < ns * GB; e += 64) {
+            const int sl = e / GB, j = e - sl * GB;
+            const Real v = tl[j * cap + sl];
+            if (v != Real(0)) {
+                unsafeAtomicAdd(&tally[(int64_t)tab[sl] * Gp + g0 + j], (double)v);
+                tl[j * cap + sl] = Real(0);
+            }
+        }
+        __syncthreads();
     }
     const int dst = args.link[sense * nslots + slot];
     if (dst >= 0) {
@@ -421,7 +440,10 @@ static inline int grid_for(int64_t n, int block, int cap = 4096) {
 
 template <typename Real, int NP, int GB, int MODE>
 static void sweep_inst(const SweepArgs &a, int nb, int n_gb, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep<Real, NP, GB, MODE>), dim3(nb, 2, n_gb), dim3(64), 0, s, a);
+    size_t lds = sizeof(Real) * GB * (size_t)a.cap;
+    if (MODE == MOC_EXP_TABLE && sizeof(Real) == 4) lds += sizeof(float) * ExpTable::kN;
+    if (lds > 64 * 1024) throw Error(MOC_EINVAL, "sweep: tally window does not fit in LDS");
+    hipLaunchKernelGGL((k_sweep<Real, NP, GB, MODE>), dim3(nb, 2, n_gb), dim3(64), lds, s, a);
 }
 
 template <typename Real, int NP, int MODE>

@@ -1,0 +1,46 @@
+// Packing of traced tracks into 64-track batches and LDS tally windows (moc_pack.cpp).
+#pragma once
+
+#include "moc_internal.h"
+
+namespace moc {
+
+// low bits of a segment key hold the window-local tally slot
+constexpr int kSlotBits = 9;
+
+struct SegF {
+    float len;
+    uint32_t key;   // (internal region << kSlotBits) | slot
+};
+struct alignas(16) SegD {
+    double len;
+    uint32_t key;
+    uint32_t pad;
+};
+
+struct PackInput {
+    const Mesh *mesh = nullptr;
+    const Quadrature *quad = nullptr;
+    const Tracks *tracks = nullptr;
+    const int *internal_of_user = nullptr;
+    std::vector<int> batch_first;   // [nb + 1] first canonical track of each batch
+    double window_len = 1.0;        // cm
+    int cap = 256;                  // maximum tally slots per window
+    int n_threads = 1;
+};
+
+struct PackOutput {
+    int64_t S = 0;                   // real segments
+    int64_t entries = 0;             // padded entries (steps * 64)
+    std::vector<int64_t> batch_win;  // [nb + 1] window range of each batch
+    std::vector<int64_t> win_entry_off, win_tab_off;
+    std::vector<int> win_nsteps, win_nslots;
+    std::vector<int> tab;            // window slot -> internal region
+    std::vector<int> entry_region;   // [2][nslots] internal region entered first per track-sense
+    std::vector<double> V;           // internal order
+};
+
+void pack_segments_f32(const PackInput &in, PackOutput &out, std::vector<SegF> &segs);
+void pack_segments_f64(const PackInput &in, PackOutput &out, std::vector<SegD> &segs);
+
+}  // namespace moc

@@ -46,7 +46,8 @@ class MocXS(C.Structure):
 
 class MocOptions(C.Structure):
     _fields_ = [("precision", _i32), ("exp_mode", _i32), ("max_iter", _i32), ("device", _i32),
-                ("check_every", _i32), ("n_threads", _i32)]
+                ("check_every", _i32), ("n_threads", _i32), ("window_cm", _f64),
+                ("tally_slots", _i32)]
 
 
 class MocResult(C.Structure):
@@ -57,7 +58,9 @@ class MocResult(C.Structure):
 class MocInfo(C.Structure):
     _fields_ = [("n_regions", _i32), ("n_groups", _i32), ("n_materials", _i32), ("n_polar", _i32),
                 ("n_angles", _i32), ("n_tracks", _i32), ("n_segments", _i64), ("n_updates", _i64),
-                ("n_padded_steps", _i64), ("n_batches", _i32), ("setup_ms", _f64),
+                ("n_padded_steps", _i64), ("n_batches", _i32), ("n_windows", _i64),
+                ("n_window_slots", _i64), ("window_cm", _f64), ("max_window_slots", _i32),
+                ("setup_ms", _f64),
                 ("device_bytes", _i64), ("precision", _i32)]
 
 
@@ -81,6 +84,8 @@ SIGNATURES = {
     "moc_get_info": (C.c_int, [C.c_void_p, _P(MocInfo)]),
     "moc_get_volumes": (C.c_int, [C.c_void_p, _P(_f64)]),
     "moc_get_tracks": (C.c_int, [C.c_void_p, _P(_i32), _P(_f64), _P(_i64), _P(_i32), _P(_f64), _P(_i32)]),
+    "moc_get_packing": (C.c_int, [C.c_void_p, _P(_i64), _P(_i32), _P(_i64), _P(_i32), _P(_i64),
+                                 _P(_i32), _P(_i32), _P(_f64), _P(C.c_uint32), _P(_i32)]),
     "moc_get_quadrature": (C.c_int, [C.c_void_p, _P(_f64), _P(_f64), _P(_f64), _P(_f64), _P(_f64)]),
     "moc_last_error": (C.c_char_p, [C.c_void_p]),
     "moc_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
@@ -138,7 +143,7 @@ class Solver:
 
     def __init__(self, prob, precision: str = "f32", exp_mode: str = "poly", device: int = 0,
                  max_iter: int = 10000, check_every: int = 1, n_threads: int = 0,
-                 polar: Optional[tuple] = None):
+                 polar: Optional[tuple] = None, window_cm: float = 0.0, tally_slots: int = 0):
         L = lib()
         self._keep = []
 
@@ -174,7 +179,8 @@ class Solver:
         x.n_materials, x.n_groups = st.shape
         x.sigma_t, x.sigma_s, x.nu_sigma_f, x.chi = (_ptr(st, _f64), _ptr(ss, _f64),
                                                      _ptr(nsf, _f64), _ptr(chi, _f64))
-        o = MocOptions(PREC[precision], EXP[exp_mode], max_iter, device, check_every, n_threads)
+        o = MocOptions(PREC[precision], EXP[exp_mode], max_iter, device, check_every, n_threads,
+                       float(window_cm), int(tally_slots))
         h = C.c_void_p()
         rc = L.moc_create(C.byref(m), C.byref(t), C.byref(x), C.byref(o), C.byref(h))
         if rc != MOC_OK:
@@ -293,6 +299,23 @@ class Solver:
         self._check(lib().moc_get_quadrature(self._h, _ptr(phi, _f64), _ptr(dl, _f64), _ptr(wa, _f64),
                                              _ptr(mu, _f64), _ptr(wp, _f64)))
         return dict(phi=phi, delta=dl, w=wa, mu=mu, w_polar=wp)
+
+    def packing(self) -> dict:
+        """Packed sweep layout (host-only contexts)."""
+        nb, nw, ns = self.info["n_batches"], self.info["n_windows"], self.info["n_window_slots"]
+        ne = self.info["n_padded_steps"]
+        out = dict(batch_win=np.zeros(nb + 1, np.int64), batch_angle=np.zeros(nb, np.int32),
+                   win_entry_off=np.zeros(nw, np.int64), win_nsteps=np.zeros(nw, np.int32),
+                   win_tab_off=np.zeros(nw, np.int64), win_nslots=np.zeros(nw, np.int32),
+                   win_tab=np.zeros(ns, np.int32), seg_len=np.zeros(ne), seg_key=np.zeros(ne, np.uint32),
+                   user_of_internal=np.zeros(self.R, np.int32))
+        self._check(lib().moc_get_packing(
+            self._h, _ptr(out["batch_win"], _i64), _ptr(out["batch_angle"], _i32),
+            _ptr(out["win_entry_off"], _i64), _ptr(out["win_nsteps"], _i32),
+            _ptr(out["win_tab_off"], _i64), _ptr(out["win_nslots"], _i32), _ptr(out["win_tab"], _i32),
+            _ptr(out["seg_len"], _f64), _ptr(out["seg_key"], C.c_uint32),
+            _ptr(out["user_of_internal"], _i32)))
+        return out
 
     def tracks(self) -> dict:
         T, S = self.T, self.S

@@ -114,3 +114,80 @@ def test_host_only_context_refuses_device_calls():
     s = moc.Solver(P.box_problem(1.0, 1.0, 2, 2), device=-1)
     rc = moc.lib().moc_set_exit_flux_buffer(s._h, None)
     assert rc == moc.MOC_ESTATE
+
+
+def _check_packing(prob, precision="f32", **kw):
+    """Walk the packed layout exactly as the sweep kernel does and check every index it
+    forms, then rebuild each track's segment list from it and compare with the tracker."""
+    s = moc.Solver(prob, device=-1, precision=precision, **kw)
+    pk = s.packing()
+    tr = s.tracks()
+    info = s.info
+    R, nb = s.R, info["n_batches"]
+    ne = info["n_padded_steps"]
+    cap = info["max_window_slots"]
+    assert cap <= (kw.get("tally_slots") or 256)
+    key, ln = pk["seg_key"], pk["seg_len"]
+    reg_int = (key >> 9).astype(np.int64)
+    slot = (key & 511).astype(np.int64)
+    assert reg_int.max() < R and reg_int.min() >= 0
+    uoi = pk["user_of_internal"]
+    assert np.array_equal(np.sort(uoi), np.arange(R))
+    bw = pk["batch_win"]
+    assert bw[0] == 0 and bw[-1] == info["n_windows"] and np.all(np.diff(bw) >= 1)
+    # batches: consecutive canonical tracks of one angle, at most 64
+    ang = tr["angle"]
+    first = [0]
+    for t in range(1, s.T):
+        if ang[t] != ang[t - 1] or t - first[-1] == 64:
+            first.append(t)
+    first.append(s.T)
+    assert len(first) - 1 == nb
+    off = tr["offset"]
+    expect_end = 0
+    for b in range(nb):
+        assert pk["batch_angle"][b] == ang[first[b]]
+        lanes = [[] for _ in range(64)]
+        for w in range(bw[b], bw[b + 1]):
+            e0, n = pk["win_entry_off"][w], pk["win_nsteps"][w]
+            ns, t0 = pk["win_nslots"][w], pk["win_tab_off"][w]
+            assert e0 == expect_end and n >= 1 and e0 + 64 * n <= ne
+            expect_end = e0 + 64 * n
+            assert 1 <= ns <= cap and t0 + ns <= len(pk["win_tab"])
+            tab = pk["win_tab"][t0:t0 + ns]
+            assert np.all(np.diff(tab) > 0)
+            blk = slice(e0, e0 + 64 * n)
+            sl, rg, lg = slot[blk], reg_int[blk], ln[blk]
+            assert sl.max() < ns
+            assert np.array_equal(tab[sl], rg)      # key region == slot table entry
+            L = lg.reshape(n, 64)
+            RG = rg.reshape(n, 64)
+            for l in range(64):
+                real = L[:, l] > 0
+                k = int(real.sum())
+                assert real[:k].all()              # padding only after the real steps
+                lanes[l] += list(zip(uoi[RG[:k, l]], L[:k, l]))
+        for l in range(64):
+            t = first[b] + l
+            if t >= first[b + 1]:
+                assert not lanes[l]
+                continue
+            ref_r = tr["region"][off[t]:off[t + 1]]
+            ref_l = tr["length"][off[t]:off[t + 1]]
+            assert [r for r, _ in lanes[l]] == list(ref_r)
+            rt = 1e-15 if precision == "f64" else 1e-7
+            np.testing.assert_allclose([x for _, x in lanes[l]], ref_l, rtol=rt)
+    assert expect_end == ne
+    return s
+
+
+@pytest.mark.parametrize("name,prob,kw", [
+    ("pincell", P.config(1), {}),
+    ("lattice_mixed", P.square_lattice(3, 2, seed=3, n_azim=32, spacing=0.05, bc=(1, 0, 1, 0)), {}),
+    ("lattice_small_cap", P.square_lattice(3, 3, seed=4, n_azim=16, spacing=0.03),
+     {"tally_slots": 64, "window_cm": 5.0}),
+    ("hex_small", P.hex_assembly(seed=5, rings=3, edge=0.25, G=4, spacing=0.05, n_azim=16), {}),
+])
+def test_packing_indices_and_sequences(name, prob, kw):
+    _check_packing(prob, **kw)
+    _check_packing(prob, precision="f64", **kw)
