@@ -321,18 +321,18 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     d.sigs_m = c->upload(std::vector<double>(xs->sigma_s, xs->sigma_s + M * G * G));
     d.nsf_m = c->upload(c->nsf_m_host);
     d.chi_m = c->upload(std::vector<double>(xs->chi, xs->chi + M * G));
+    // (Sigma_t, qhat) pairs per region and padded group; qhat starts at zero
     if (f64) {
-        std::vector<double> st((size_t)R * d.Gp, 0.0);
+        std::vector<double> xq((size_t)R * d.Gp * 2, 0.0);
         for (int r = 0; r < R; ++r)
-            for (int g = 0; g < G; ++g) st[(size_t)r * d.Gp + g] = xs->sigma_t[mat[r] * G + g];
-        d.sigt_r = c->upload(st);
+            for (int g = 0; g < G; ++g) xq[((size_t)r * d.Gp + g) * 2] = xs->sigma_t[mat[r] * G + g];
+        d.xsq = c->upload(xq);
     } else {
-        std::vector<float> st((size_t)R * d.Gp, 0.0f);
+        std::vector<float> xq((size_t)R * d.Gp * 2, 0.0f);
         for (int r = 0; r < R; ++r)
-            for (int g = 0; g < G; ++g) st[(size_t)r * d.Gp + g] = (float)xs->sigma_t[mat[r] * G + g];
-        d.sigt_r = c->upload(st);
+            for (int g = 0; g < G; ++g) xq[((size_t)r * d.Gp + g) * 2] = (float)xs->sigma_t[mat[r] * G + g];
+        d.xsq = c->upload(xq);
     }
-    d.qhat = c->dalloc<char>((size_t)R * d.Gp * rs);
     d.tally = c->dalloc<double>((size_t)R * d.Gp);
     d.phi[0] = c->dalloc<double>((size_t)R * G);
     d.phi[1] = c->dalloc<double>((size_t)R * G);
@@ -342,7 +342,6 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     if (!c->host_only) {
         launch_fill_real(d.psi[0], (int64_t)npsi, d.precision, c->stream);
         launch_fill_real(d.psi[1], (int64_t)npsi, d.precision, c->stream);
-        launch_fill_real(d.qhat, (int64_t)R * d.Gp, d.precision, c->stream);
     }
 
     // tally weights c_ap = 2 pi w_a w_p delta_a sin(theta_p); 1/sin(theta_p)
@@ -394,8 +393,7 @@ static void sweep_impl(moc_ctx *c, hipStream_t s) {
     a.win_tab = d.win_tab;
     a.cap = d.max_slots;
     a.batch_angle = d.batch_angle;
-    a.sigt = d.sigt_r;
-    a.qhat = d.qhat;
+    a.xsq = d.xsq;
     a.psi_in = d.psi[c->cur_psi];
     a.psi_out = d.psi[1 - c->cur_psi];
     a.link = d.link;

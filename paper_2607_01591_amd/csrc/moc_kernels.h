@@ -25,8 +25,7 @@ struct SweepArgs {
     const int *win_tab;           // slot -> internal region
     int cap;                      // LDS tally rows per group (>= every window's slot count)
     const int *batch_angle;       // [nb]
-    const void *sigt;          // Real [R][Gp]
-    const void *qhat;          // Real [R][Gp]
+    const void *xsq;           // Real [R][Gp][2] (Sigma_t, qhat)
     const void *psi_in;        // Real [2][P][Gp][nslots]
     void *psi_out;
     const int *link;           // [2][nslots] -> sense' * nslots + slot', or -1
@@ -49,7 +48,7 @@ struct DevProblem {
     // per internal region
     int *mat = nullptr, *user_of = nullptr;
     double *V = nullptr;
-    void *sigt_r = nullptr, *qhat = nullptr;
+    void *xsq = nullptr;   // Real [R][Gp][2] (Sigma_t, qhat)
     double *tally = nullptr;
     double *phi[2] = {nullptr, nullptr};
     double *qext = nullptr;

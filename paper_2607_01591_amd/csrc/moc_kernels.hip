@@ -3,7 +3,8 @@
 // conversions.
 //
 // Layouts (internal region order r, which is a locality order of the user's regions):
-//   qhat, sigt_r : Real [R][Gp]   Gp = G padded; padded groups hold zeros
+//   xsq          : Real [R][Gp][2] = (Sigma_t, qhat) pairs; Gp = G padded (multiple of 4),
+//                  padded groups hold zeros
 //   tally        : double [R][Gp]
 //   phi          : double [R][G]
 //   psi          : Real [2 senses][P][Gp][nslots], slot = batch * 64 + lane
@@ -24,16 +25,15 @@ template <> struct SegOf<float> { using type = SegF; };
 template <> struct SegOf<double> { using type = SegD; };
 
 // ---------------------------------------------------------------- 1 - exp(-tau)
-// FP32, MOC_EXP_POLY: for tau >= 0.25 use 1 - 2^(-tau log2 e) with the hardware
-// exponential (absolute error ~6e-8, relative <= 3e-7 there); below, the Taylor series
-// of 1 - e^-tau through tau^6 (truncation < tau^7/5040, relative < 2e-7 at 0.25).
-// Relative accuracy matters because the tally takes (psi - qhat) * F directly.
+// FP32, MOC_EXP_POLY: for tau >= 1/16 use 1 - 2^(-tau log2 e) with the hardware
+// exponential (absolute error ~6e-8, so relative <= 1e-6 there); below, the Taylor
+// series of 1 - e^-tau through tau^4 (truncation < tau^5/120, relative < 1.3e-7 at
+// 1/16). Relative accuracy matters because the tally takes (psi - qhat) * F directly.
 __device__ __forceinline__ float one_minus_exp_poly(float tau) {
-    const float e = __builtin_amdgcn_exp2f(-tau * 1.4426950408889634f);
+    const float e = __builtin_amdgcn_exp2f(tau * -1.4426950408889634f);
     const float big = 1.0f - e;
-    const float small =
-        tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f - tau * (1.0f / 120.0f - tau * (1.0f / 720.0f))))));
-    return tau < 0.25f ? small : big;
+    const float small = tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f))));
+    return tau < 0.0625f ? small : big;
 }
 
 // MOC_EXP_TABLE: linear interpolation of f(x) = (1 - e^-x)/x on a uniform grid held in
@@ -98,8 +98,6 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     const int Gp = args.Gp;
     const int a = args.batch_angle[b];
     const Seg *__restrict__ segs = reinterpret_cast<const Seg *>(args.segs);
-    const Real *__restrict__ sigt = reinterpret_cast<const Real *>(args.sigt);
-    const Real *__restrict__ qhat = reinterpret_cast<const Real *>(args.qhat);
     const Real *__restrict__ psi_in = reinterpret_cast<const Real *>(args.psi_in);
     Real *__restrict__ psi_out = reinterpret_cast<Real *>(args.psi_out);
     const Real *__restrict__ coef = reinterpret_cast<const Real *>(args.coef);
@@ -118,24 +116,59 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
 #pragma unroll
         for (int j = 0; j < GB; ++j) psi[p][j] = psi_in[(int64_t)((sense * NP + p) * Gp + g0 + j) * nslots + slot];
 
+    // Sigma_t and qhat of a region's group batch: float4 loads when aligned
+    const Real *__restrict__ xsq = reinterpret_cast<const Real *>(args.xsq);
+    constexpr int NQ = (2 * GB + 3) / 4;
+    const bool vec = sizeof(Real) == 4 && ((g0 * 2) & 3) == 0 && g0 + 2 * NQ <= Gp;
+    auto load_xs = [&](uint32_t key, Real (&st)[GB], Real (&q)[GB]) {
+        const Real *row = xsq + ((int64_t)(key >> kSlotBits) * Gp + g0) * 2;
+        if constexpr (sizeof(Real) == 4) {
+            if (vec) {
+                float4 v[NQ];
+#pragma unroll
+                for (int u = 0; u < NQ; ++u) v[u] = reinterpret_cast<const float4 *>(row)[u];
+#pragma unroll
+                for (int j = 0; j < GB; ++j) {
+                    const float4 &w = v[j >> 1];
+                    st[j] = (j & 1) ? w.z : w.x;
+                    q[j] = (j & 1) ? w.w : w.y;
+                }
+                return;
+            }
+#pragma unroll
+            for (int j = 0; j < GB; ++j) {
+                const float2 w = reinterpret_cast<const float2 *>(row)[j];
+                st[j] = w.x;
+                q[j] = w.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < GB; ++j) {
+                const double2 w = reinterpret_cast<const double2 *>(row)[j];
+                st[j] = w.x;
+                q[j] = w.y;
+            }
+        }
+    };
+
     const int64_t w0 = args.batch_win[b], w1 = args.batch_win[b + 1];
     for (int64_t wi = 0; wi < w1 - w0; ++wi) {
         const int64_t w = sense ? w1 - 1 - wi : w0 + wi;
         const int n = args.win_nsteps[w];
         const Seg *__restrict__ ws = segs + args.win_entry_off[w];
+        auto step_of = [&](int i) { return (int64_t)(sense ? n - 1 - i : i) * 64 + lane; };
+        // software pipeline: the segment two steps ahead and the cross sections one
+        // step ahead are in flight while the current step computes
+        Seg s_cur = ws[step_of(0)];
+        Seg s_nxt = ws[step_of(n > 1 ? 1 : 0)];
+        Real st[GB], q[GB];
+        load_xs(s_cur.key, st, q);
         for (int i = 0; i < n; ++i) {
-            const int k = sense ? n - 1 - i : i;
-            const Seg sg = ws[(int64_t)k * 64 + lane];
-            const Real len = sg.len;
-            const uint32_t key = sg.key;
-            const int64_t base = (int64_t)(key >> kSlotBits) * Gp + g0;
-            const int ts = int(key & ((1u << kSlotBits) - 1));
-            Real st[GB], q[GB];
-#pragma unroll
-            for (int j = 0; j < GB; ++j) {
-                st[j] = sigt[base + j];
-                q[j] = qhat[base + j];
-            }
+            const Seg s_nn = ws[step_of(i + 2 < n ? i + 2 : n - 1)];
+            Real st2[GB], q2[GB];
+            load_xs(s_nxt.key, st2, q2);
+            const Real len = s_cur.len;
+            const int ts = int(s_cur.key & ((1u << kSlotBits) - 1));
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
                 const Real sl = st[j] * len;
@@ -148,6 +181,13 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
                     acc += c[p] * d;
                 }
                 atomicAdd(&tl[j * cap + ts], acc);
+            }
+            s_cur = s_nxt;
+            s_nxt = s_nn;
+#pragma unroll
+            for (int j = 0; j < GB; ++j) {
+                st[j] = st2[j];
+                q[j] = q2[j];
             }
         }
         __syncthreads();
@@ -205,13 +245,13 @@ template <typename T> __global__ void k_scale(T *__restrict__ p, int64_t n, cons
 // qhat from a caller's emission density (user order): qhat = s / (4 pi Sigma_t)
 template <typename Real>
 __global__ void k_prep_user(const double *__restrict__ src_user, const int *__restrict__ user_of, const int *__restrict__ mat,
-                            const double *__restrict__ sigt_m, Real *__restrict__ qhat, int R, int G, int Gp) {
+                            const double *__restrict__ sigt_m, Real *__restrict__ xsq, int R, int G, int Gp) {
     const int64_t n = (int64_t)R * Gp;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int r = int(i / Gp), g = int(i - (int64_t)r * Gp);
         Real v = 0;
         if (g < G) v = (Real)(src_user[(int64_t)user_of[r] * G + g] / (kFourPi * sigt_m[mat[r] * G + g]));
-        qhat[i] = v;
+        xsq[2 * i + 1] = v;
     }
 }
 
@@ -221,7 +261,7 @@ template <typename Real>
 __global__ void k_source(const double *__restrict__ phi, const double *__restrict__ scal, const int *__restrict__ mat,
                          const double *__restrict__ sigt_m, const double *__restrict__ sigs_m,
                          const double *__restrict__ nsf_m, const double *__restrict__ chi_m,
-                         const double *__restrict__ qext, Real *__restrict__ qhat, int R, int G, int Gp) {
+                         const double *__restrict__ qext, Real *__restrict__ xsq, int R, int G, int Gp) {
     const double inv_k = 1.0 / scal[kScalK];
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
         const int m = mat[r];
@@ -233,9 +273,8 @@ __global__ void k_source(const double *__restrict__ phi, const double *__restric
             const double *col = sigs_m + (int64_t)m * G * G + g;
             for (int gp = 0; gp < G; ++gp) s += col[(int64_t)gp * G] * ph[gp];
             if (qext) s += qext[(int64_t)r * G + g];
-            qhat[(int64_t)r * Gp + g] = (Real)(s / (kFourPi * sigt_m[m * G + g]));
+            xsq[((int64_t)r * Gp + g) * 2 + 1] = (Real)(s / (kFourPi * sigt_m[m * G + g]));
         }
-        for (int g = G; g < Gp; ++g) qhat[(int64_t)r * Gp + g] = Real(0);
     }
 }
 
@@ -254,7 +293,7 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 // phi = 4 pi qhat + T / (Sigma_t V) (angular integration of segment averages; FP64);
 // either to the internal phi with per-block partials of sum V F, or to a user buffer.
 template <typename Real>
-__global__ void k_finalize(const Real *__restrict__ qhat, const double *__restrict__ tally, const double *__restrict__ V,
+__global__ void k_finalize(const Real *__restrict__ xsq, const double *__restrict__ tally, const double *__restrict__ V,
                            const int *__restrict__ mat, const double *__restrict__ sigt_m,
                            const double *__restrict__ nsf_m, double *__restrict__ phi_internal,
                            double *__restrict__ phi_user, const int *__restrict__ user_of, double *__restrict__ partials,
@@ -267,7 +306,7 @@ __global__ void k_finalize(const Real *__restrict__ qhat, const double *__restri
         double F = 0.0;
         for (int g = 0; g < G; ++g) {
             const double st = sigt_m[m * G + g];
-            const double ph = kFourPi * (double)qhat[(int64_t)r * Gp + g] + tally[(int64_t)r * Gp + g] / (st * v);
+            const double ph = kFourPi * (double)xsq[((int64_t)r * Gp + g) * 2 + 1] + tally[(int64_t)r * Gp + g] / (st * v);
             if (phi_internal) phi_internal[(int64_t)r * G + g] = ph;
             if (phi_user) phi_user[(int64_t)user_of[r] * G + g] = ph;
             F += nsf_m[m * G + g] * ph;
@@ -515,10 +554,10 @@ void launch_prep_user(const DevProblem &d, const double *src_user, hipStream_t s
     const int64_t n = (int64_t)d.R * d.Gp;
     if (d.precision == MOC_PREC_F64)
         hipLaunchKernelGGL(k_prep_user<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, src_user, d.user_of, d.mat, d.sigt_m,
-                           (double *)d.qhat, d.R, d.G, d.Gp);
+                           (double *)d.xsq, d.R, d.G, d.Gp);
     else
         hipLaunchKernelGGL(k_prep_user<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, src_user, d.user_of, d.mat, d.sigt_m,
-                           (float *)d.qhat, d.R, d.G, d.Gp);
+                           (float *)d.xsq, d.R, d.G, d.Gp);
     MOC_CHECK_LAUNCH();
 }
 
@@ -526,19 +565,19 @@ void launch_source(const DevProblem &d, const double *phi, hipStream_t s) {
     const int grid = grid_for(d.R, 256, 8192);
     if (d.precision == MOC_PREC_F64)
         hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(256), 0, s, phi, d.scal, d.mat, d.sigt_m, d.sigs_m, d.nsf_m,
-                           d.chi_m, d.qext, (double *)d.qhat, d.R, d.G, d.Gp);
+                           d.chi_m, d.qext, (double *)d.xsq, d.R, d.G, d.Gp);
     else
         hipLaunchKernelGGL(k_source<float>, dim3(grid), dim3(256), 0, s, phi, d.scal, d.mat, d.sigt_m, d.sigs_m, d.nsf_m,
-                           d.chi_m, d.qext, (float *)d.qhat, d.R, d.G, d.Gp);
+                           d.chi_m, d.qext, (float *)d.xsq, d.R, d.G, d.Gp);
     MOC_CHECK_LAUNCH();
 }
 
 void launch_finalize(const DevProblem &d, double *phi_internal, double *phi_user, double *partials, hipStream_t s) {
     if (d.precision == MOC_PREC_F64)
-        hipLaunchKernelGGL(k_finalize<double>, dim3(kReduceBlocks), dim3(256), 0, s, (const double *)d.qhat, d.tally, d.V, d.mat,
+        hipLaunchKernelGGL(k_finalize<double>, dim3(kReduceBlocks), dim3(256), 0, s, (const double *)d.xsq, d.tally, d.V, d.mat,
                            d.sigt_m, d.nsf_m, phi_internal, phi_user, d.user_of, partials, d.R, d.G, d.Gp);
     else
-        hipLaunchKernelGGL(k_finalize<float>, dim3(kReduceBlocks), dim3(256), 0, s, (const float *)d.qhat, d.tally, d.V, d.mat,
+        hipLaunchKernelGGL(k_finalize<float>, dim3(kReduceBlocks), dim3(256), 0, s, (const float *)d.xsq, d.tally, d.V, d.mat,
                            d.sigt_m, d.nsf_m, phi_internal, phi_user, d.user_of, partials, d.R, d.G, d.Gp);
     MOC_CHECK_LAUNCH();
 }
