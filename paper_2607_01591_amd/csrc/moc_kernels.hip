@@ -158,37 +158,43 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
         const int n = args.win_nsteps[w];
         const Seg *__restrict__ ws = segs + args.win_entry_off[w];
         auto step_of = [&](int i) { return (int64_t)(sense ? n - 1 - i : i) * 64 + lane; };
-        // software pipeline: the segment two steps ahead and the cross sections one
-        // step ahead are in flight while the current step computes
-        Seg s_cur = ws[step_of(0)];
-        Seg s_nxt = ws[step_of(n > 1 ? 1 : 0)];
-        Real st[GB], q[GB];
-        load_xs(s_cur.key, st, q);
+        // software pipeline: segment entries four steps ahead and cross sections two
+        // steps ahead are in flight while the current step computes
+        auto clampi = [&](int i) { return i < n ? i : n - 1; };
+        Seg s0 = ws[step_of(0)], s1 = ws[step_of(clampi(1))], s2 = ws[step_of(clampi(2))],
+            s3 = ws[step_of(clampi(3))];
+        Real st0[GB], q0[GB], st1[GB], q1[GB];
+        load_xs(s0.key, st0, q0);
+        load_xs(s1.key, st1, q1);
         for (int i = 0; i < n; ++i) {
-            const Seg s_nn = ws[step_of(i + 2 < n ? i + 2 : n - 1)];
+            const Seg s4 = ws[step_of(clampi(i + 4))];
             Real st2[GB], q2[GB];
-            load_xs(s_nxt.key, st2, q2);
-            const Real len = s_cur.len;
-            const int ts = int(s_cur.key & ((1u << kSlotBits) - 1));
+            load_xs(s2.key, st2, q2);
+            const Real len = s0.len;
+            const int ts = int(s0.key & ((1u << kSlotBits) - 1));
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
-                const Real sl = st[j] * len;
+                const Real sl = st0[j] * len;
                 Real acc = 0;
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
                     const Real F = one_minus_exp<Real, MODE>(sl * is[p], lut);
-                    const Real d = (psi[p][j] - q[j]) * F;
+                    const Real d = (psi[p][j] - q0[j]) * F;
                     psi[p][j] -= d;
                     acc += c[p] * d;
                 }
-                atomicAdd(&tl[j * cap + ts], (double)acc);
+                if (len > Real(0)) atomicAdd(&tl[j * cap + ts], (double)acc);   // padding steps add nothing
             }
-            s_cur = s_nxt;
-            s_nxt = s_nn;
+            s0 = s1;
+            s1 = s2;
+            s2 = s3;
+            s3 = s4;
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
-                st[j] = st2[j];
-                q[j] = q2[j];
+                st0[j] = st1[j];
+                q0[j] = q1[j];
+                st1[j] = st2[j];
+                q1[j] = q2[j];
             }
         }
         __syncthreads();

@@ -1,0 +1,76 @@
+"""Pins for the numpy CNN oracle: central finite differences of the loss, and a 1x1
+special case against a plain matrix product."""
+import numpy as np
+
+from oracle import cnn_oracle as C
+
+
+def _params(rng, chans):
+    return [(rng.normal(0, 0.4, size=(co, 3, 3, ci)), rng.normal(0, 0.1, size=co))
+            for ci, co in zip(chans[:-1], chans[1:])]
+
+
+def test_conv_center_tap_is_matmul():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, 5, 4, 3))
+    W = np.zeros((6, 3, 3, 3))
+    W[:, 1, 1, :] = rng.normal(size=(6, 3))
+    b = rng.normal(size=6)
+    np.testing.assert_allclose(C.conv_forward(x, W, b), x @ W[:, 1, 1, :].T + b, rtol=1e-14)
+
+
+def test_conv_shift_tap_and_zero_padding():
+    x = np.zeros((1, 4, 4, 1))
+    x[0, 2, 1, 0] = 1.0
+    W = np.zeros((1, 3, 3, 1))
+    W[0, 0, 2, 0] = 1.0            # z[y, x] = x[y - 1, x + 1]
+    z = C.conv_forward(x, W, np.zeros(1))
+    expect = np.zeros((1, 4, 4, 1))
+    expect[0, 3, 0, 0] = 1.0
+    np.testing.assert_array_equal(z, expect)
+
+
+def test_gradients_match_central_differences():
+    rng = np.random.default_rng(1)
+    params = _params(rng, [3, 5, 4, 2])
+    x = rng.normal(size=(2, 6, 5, 3))
+    t = rng.normal(size=(2, 6, 5, 2))
+    y, acts, pre = C.forward(x, params)
+    grads = C.backward(params, acts, pre, t)
+    h = 1e-6
+    for li, (W, b) in enumerate(params):
+        for arr, g in ((W, grads[li][0]), (b, grads[li][1])):
+            flat = arr.reshape(-1)
+            gf = g.reshape(-1)
+            for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
+                old = flat[idx]
+                flat[idx] = old + h
+                lp = C.mse(C.forward(x, params)[0], t)
+                flat[idx] = old - h
+                lm = C.mse(C.forward(x, params)[0], t)
+                flat[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - gf[idx]) < 1e-7 + 1e-5 * abs(fd), (li, idx, fd, gf[idx])
+
+
+def test_input_gradient_matches_central_differences():
+    rng = np.random.default_rng(2)
+    W = rng.normal(size=(4, 3, 3, 3))
+    x = rng.normal(size=(1, 5, 5, 3))
+    dz = rng.normal(size=(1, 5, 5, 4))
+    dx, _, _ = C.conv_backward(x, W, dz)
+    h = 1e-6
+    for idx in rng.choice(x.size, size=15, replace=False):
+        xf = x.reshape(-1)
+        old = xf[idx]
+        xf[idx] = old + h
+        lp = np.sum(C.conv_forward(x, W, np.zeros(4)) * dz)
+        xf[idx] = old - h
+        lm = np.sum(C.conv_forward(x, W, np.zeros(4)) * dz)
+        xf[idx] = old
+        assert abs((lp - lm) / (2 * h) - dx.reshape(-1)[idx]) < 1e-6
+
+
+def test_adam_first_step_moves_by_lr():
+    p, m, v = C.adam_step(np.array([1.0, -2.0]), np.array([0.3, -5.0]), np.zeros(2), np.zeros(2), 1, lr=0.01)
+    np.testing.assert_allclose(p, [0.99, -1.99], rtol=1e-6)
