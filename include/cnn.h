@@ -1,0 +1,81 @@
+/*
+ * cnn.h -- C ABI of the warm-start network kernels in libmoc (gfx950).
+ *
+ * A small convolutional network predicts the scalar flux of a lattice from its
+ * rasterised cross sections; the prediction is handed to moc_set_initial_guess and
+ * the plain power iteration (moc_solve) remains the judge of convergence. This is a
+ * project addition; the paper itself accelerates with CMFD (Sec. 2.1, Alg. 1).
+ *
+ * Conventions:
+ *   - Activations are NHWC: [N][H][W][C], C fastest. BF16 tensors are passed as
+ *     uint16_t bit patterns (bfloat16: the upper half of an IEEE float).
+ *   - Convolutions are 3x3, stride 1, zero padding ("same"); weights are
+ *     W[co][tap][ci] with tap = 3 ky + kx, i.e. z[n,y,x,co] = b[co] +
+ *     sum W[co][3 ky + kx][ci] x[n, y + ky - 1, x + kx - 1, ci].
+ *   - Channel counts: Ci a multiple of 32, Co a multiple of 16 (pad with zeros).
+ *   - All pointers are device pointers on the current HIP device unless stated;
+ *     calls enqueue on `stream` (NULL = the null stream) and return without waiting.
+ *   - Return MOC_OK (0) or MOC_EINVAL (bad sizes or null pointers) / MOC_EHIP.
+ */
+#ifndef CNN_H
+#define CNN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* y = act(conv3x3(x, w) + bias): BF16 operands, FP32 accumulation on the matrix cores
+ * (implicit GEMM: M = pixels, N = Co, K = 9 Ci). bias may be NULL. relu != 0 applies
+ * max(0, .). Writes y_bf16 [N][H][W][Co] and/or y_f32 (either may be NULL). */
+int cnn_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias, int32_t N,
+                        int32_t H, int32_t W, int32_t Ci, int32_t Co, int32_t relu,
+                        uint16_t *y_bf16, float *y_f32, void *stream);
+
+/* Weight layout for the input gradient: wt[ci][tap][co] = bf16(w[co][8 - tap][ci]) from
+ * FP32 w [Co][9][Ci]; then dx = cnn_conv3x3_forward(dz, wt, NULL, ..., Ci'=Co, Co'=Ci). */
+int cnn_weights_for_dgrad(const float *w, int32_t Co, int32_t Ci, uint16_t *wt, void *stream);
+
+/* Weight gradient, accumulated: dw[co][tap][ci] += sum_{n,y,x} dz[n,y,x,co] x[n, y+ky-1,
+ * x+kx-1, ci] (BF16 operands on the matrix cores, FP32 accumulation; dw FP32, caller
+ * zeroes it). */
+int cnn_conv3x3_wgrad(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t H, int32_t W,
+                      int32_t Ci, int32_t Co, float *dw, void *stream);
+
+/* db[co] += sum over pixels of dz (FP32 dz [npix][Co]). */
+int cnn_bias_grad(const float *dz, int64_t npix, int32_t Co, float *db, void *stream);
+
+/* Through a ReLU: dz = dy * (y > 0), y the layer's BF16 output. Writes FP32 and BF16. */
+int cnn_relu_backward(const float *dy, const uint16_t *y, int64_t n, float *dz_f32, uint16_t *dz_bf16,
+                      void *stream);
+
+/* Mean squared error over the first `cv` of every `cs` channels (the rest are padding):
+ * dy = 2 (y - t) / count on those channels, 0 elsewhere; loss_partials[block] receives
+ * per-block sums of squares (nblocks = 256; the caller sums and divides by count). */
+int cnn_mse_grad(const float *y, const float *t, int64_t npix, int32_t cs, int32_t cv, float *dy,
+                 double *loss_partials, void *stream);
+
+/* Adam with bias correction (step t >= 1) on FP32 master parameters p; also writes the
+ * BF16 copy p_bf16 (may be NULL). */
+int cnn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
+             float beta2, float eps, int32_t t, uint16_t *p_bf16, void *stream);
+
+/* BF16 copy of FP32 data. */
+int cnn_to_bf16(const float *src, int64_t n, uint16_t *dst, void *stream);
+
+/* Rasterise: out[p][c] = bf16(table[idx[p]][c]) for c < C, 0 for C <= c < Cp
+ * (idx [npix] int32 in [0, rows), table FP32 [rows][C]). */
+int cnn_gather_rows(const float *table, const int32_t *idx, int64_t npix, int32_t C, int32_t Cp,
+                    uint16_t *out, void *stream);
+
+/* De-rasterise: for each of n points with pixel coordinates (u, v) (x then y, pixel
+ * centres at integers), bilinear interpolation of img FP32 [H][W][Cs] channels [0, C),
+ * clamped at the border; out FP64 [n][C] = exp(value) if apply_exp else value. */
+int cnn_bilinear_sample(const float *img, int32_t H, int32_t W, int32_t Cs, int32_t C, const float *uv,
+                        int64_t n, int32_t apply_exp, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CNN_H */

@@ -1,0 +1,325 @@
+// Warm-start network kernels for gfx950: 3x3 convolutions as implicit GEMMs on the
+// BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation), their gradients,
+// loss, Adam, and the raster <-> region transfers. C ABI in include/cnn.h.
+//
+// MFMA 16x16x32 operand layout (per lane l of a wavefront): A supplies row l % 16,
+// k = 8 (l / 16) .. + 7; B supplies column l % 16, the same k; the 16x16 FP32 result
+// holds rows 4 (l / 16) .. + 3 of column l % 16.
+#include <cmath>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "cnn.h"
+#include "moc.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);                                     // round to nearest even
+    return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// ---------------------------------------------------------------- forward
+// Block = 4 wavefronts = 64 consecutive pixels of one image row; wave w owns pixels
+// [16 w, 16 w + 16) and all Co = 16 NCT output channels.
+template <int NCT>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
+                                                  const float *__restrict__ bias, int N, int H, int W, int Ci, int relu,
+                                                  uint16_t *__restrict__ yb, float *__restrict__ yf) {
+    const int Co = NCT * 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tiles_x = (W + 63) / 64;
+    int t = blockIdx.x;
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int y = t % H, n = t / H;
+    const int xbase = tx * 64 + wv * 16;
+    const int m = lane & 15, kb = lane >> 4;
+    f32x4 acc[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y + tap / 3 - 1, xx = xbase + m + tap % 3 - 1;
+        const bool inb = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const int64_t xoff = inb ? (((int64_t)n * H + yy) * W + xx) * Ci : 0;
+        for (int c0 = 0; c0 < Ci; c0 += 32) {
+            const uint4 av = inb ? *reinterpret_cast<const uint4 *>(x + xoff + c0 + kb * 8) : make_uint4(0, 0, 0, 0);
+            const bf16x8 a = as_bf16x8(av);
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                const int co = c * 16 + m;
+                const uint4 bv = *reinterpret_cast<const uint4 *>(w + ((int64_t)co * 9 + tap) * Ci + c0 + kb * 8);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(bv), acc[c], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+        const int co = c * 16 + (lane & 15);
+        const float b = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int px = xbase + 4 * (lane >> 4) + i;
+            if (px >= W) continue;
+            float v = acc[c][i] + b;
+            if (relu) v = fmaxf(v, 0.f);
+            const int64_t o = (((int64_t)n * H + y) * W + px) * Co + co;
+            if (yb) yb[o] = f2bf(v);
+            if (yf) yf[o] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- weight gradient
+// Block (row chunk, tap): rows [r0, r0 + rows) of the N*H image rows. The 16x16
+// output tiles (co, ci) are spread over the 4 wavefronts; K = pixels in steps of 32.
+__global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dz, int N,
+                                                    int H, int W, int Ci, int Co, float *__restrict__ dw, int rows) {
+    const int tap = blockIdx.y, ky = tap / 3, kx = tap % 3;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kb = lane >> 4;
+    const int nct = Co / 16, ncit = Ci / 16;
+    const int r0 = blockIdx.x * rows, r1 = min(N * H, r0 + rows);
+    for (int tile = wv; tile < nct * ncit; tile += 4) {
+        const int ct = tile / ncit, it = tile % ncit;
+        const int co = ct * 16 + m, ci = it * 16 + m;
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int row = r0; row < r1; ++row) {
+            const int n = row / H, y = row % H;
+            const int yy = y + ky - 1;
+            if (yy < 0 || yy >= H) continue;     // uniform over the block
+            const uint16_t *dzr = dz + ((int64_t)n * H + y) * W * Co;
+            const uint16_t *xr = x + ((int64_t)n * H + yy) * W * Ci;
+            for (int p0 = 0; p0 < W; p0 += 32) {
+                uint16_t av[8], bv[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int px = p0 + kb * 8 + i;
+                    const int xx = px + kx - 1;
+                    av[i] = px < W ? dzr[(int64_t)px * Co + co] : uint16_t(0);
+                    bv[i] = (px < W && xx >= 0 && xx < W) ? xr[(int64_t)xx * Ci + ci] : uint16_t(0);
+                }
+                const uint4 a4 = make_uint4(av[0] | (uint32_t(av[1]) << 16), av[2] | (uint32_t(av[3]) << 16),
+                                            av[4] | (uint32_t(av[5]) << 16), av[6] | (uint32_t(av[7]) << 16));
+                const uint4 b4 = make_uint4(bv[0] | (uint32_t(bv[1]) << 16), bv[2] | (uint32_t(bv[3]) << 16),
+                                            bv[4] | (uint32_t(bv[5]) << 16), bv[6] | (uint32_t(bv[7]) << 16));
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a4), as_bf16x8(b4), acc, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int cor = ct * 16 + 4 * (lane >> 4) + i, cic = it * 16 + (lane & 15);
+            atomicAdd(&dw[((int64_t)cor * 9 + tap) * Ci + cic], acc[i]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- small kernels
+__global__ void k_weights_for_dgrad(const float *__restrict__ w, int Co, int Ci, uint16_t *__restrict__ wt) {
+    const int64_t n = (int64_t)Co * 9 * Ci;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int co = int(i % Co);
+        const int tap = int((i / Co) % 9);
+        const int ci = int(i / ((int64_t)Co * 9));
+        wt[i] = f2bf(w[((int64_t)co * 9 + (8 - tap)) * Ci + ci]);   // wt[ci][tap][co]
+    }
+}
+
+__global__ void k_bias_grad(const float *__restrict__ dz, int64_t npix, int Co, float *__restrict__ db) {
+    // one block per channel group of 64 threads; grid-stride over pixels
+    const int co = blockIdx.y;
+    float s = 0.f;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x)
+        s += dz[p * Co + co];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ float sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+        atomicAdd(&db[co], t);
+    }
+}
+
+__global__ void k_relu_backward(const float *__restrict__ dy, const uint16_t *__restrict__ y, int64_t n, float *__restrict__ dzf,
+                                uint16_t *__restrict__ dzb) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = bf2f(y[i]) > 0.f ? dy[i] : 0.f;
+        if (dzf) dzf[i] = v;
+        if (dzb) dzb[i] = f2bf(v);
+    }
+}
+
+__global__ void k_mse_grad(const float *__restrict__ y, const float *__restrict__ t, int64_t npix, int cs, int cv,
+                           float *__restrict__ dy, double *__restrict__ partials) {
+    const int64_t n = npix * cs;
+    const double count = (double)npix * cv;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = int(i % cs);
+        float g = 0.f;
+        if (c < cv) {
+            const float d = y[i] - t[i];
+            g = float(2.0 * d / count);
+            acc += (double)d * d;
+        }
+        dy[i] = g;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+        partials[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v, int64_t n,
+                       float lr, float b1, float b2, float eps, float c1, float c2, uint16_t *__restrict__ pb) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        if (pb) pb[i] = f2bf(pi);
+    }
+}
+
+__global__ void k_to_bf16(const float *__restrict__ s, int64_t n, uint16_t *__restrict__ d) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) d[i] = f2bf(s[i]);
+}
+
+__global__ void k_gather_rows(const float *__restrict__ table, const int32_t *__restrict__ idx, int64_t npix, int C, int Cp,
+                              uint16_t *__restrict__ out) {
+    const int64_t n = npix * Cp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = i / Cp;
+        const int c = int(i - p * Cp);
+        out[i] = c < C ? f2bf(table[(int64_t)idx[p] * C + c]) : uint16_t(0);
+    }
+}
+
+__global__ void k_bilinear(const float *__restrict__ img, int H, int W, int Cs, int C, const float *__restrict__ uv, int64_t n,
+                           int apply_exp, double *__restrict__ out) {
+    const int64_t tot = n * C;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / C;
+        const int c = int(i - r * C);
+        const float u = fminf(fmaxf(uv[2 * r], 0.f), float(W - 1));
+        const float v = fminf(fmaxf(uv[2 * r + 1], 0.f), float(H - 1));
+        const int x0 = min(int(u), W - 2 < 0 ? 0 : W - 2), y0 = min(int(v), H - 2 < 0 ? 0 : H - 2);
+        const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);
+        const float fx = u - float(x0), fy = v - float(y0);
+        auto at = [&](int yy, int xx) { return img[((int64_t)yy * W + xx) * Cs + c]; };
+        const float val = (1.f - fy) * ((1.f - fx) * at(y0, x0) + fx * at(y0, x1)) + fy * ((1.f - fx) * at(y1, x0) + fx * at(y1, x1));
+        out[i] = apply_exp ? exp((double)val) : (double)val;
+    }
+}
+
+inline int grid_for(int64_t n, int block, int cap = 4096) {
+    int64_t g = (n + block - 1) / block;
+    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+inline int launched() { return hipGetLastError() == hipSuccess ? MOC_OK : MOC_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+int cnn_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias, int32_t N, int32_t H, int32_t W, int32_t Ci,
+                        int32_t Co, int32_t relu, uint16_t *y_bf16, float *y_f32, void *stream) {
+    if (!x || !w || (!y_bf16 && !y_f32) || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 32 || Co <= 0 || Co % 16)
+        return MOC_EINVAL;
+    const dim3 grid((unsigned)((int64_t)N * H * ((W + 63) / 64)));
+    hipStream_t s = (hipStream_t)stream;
+    switch (Co / 16) {
+        case 1: hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, y_bf16, y_f32); break;
+        case 2: hipLaunchKernelGGL(k_conv_fwd<2>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, y_bf16, y_f32); break;
+        case 4: hipLaunchKernelGGL(k_conv_fwd<4>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, y_bf16, y_f32); break;
+        default: return MOC_EINVAL;
+    }
+    return launched();
+}
+
+int cnn_weights_for_dgrad(const float *w, int32_t Co, int32_t Ci, uint16_t *wt, void *stream) {
+    if (!w || !wt || Co <= 0 || Ci <= 0) return MOC_EINVAL;
+    const int64_t n = (int64_t)Co * 9 * Ci;
+    hipLaunchKernelGGL(k_weights_for_dgrad, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, w, Co, Ci, wt);
+    return launched();
+}
+
+int cnn_conv3x3_wgrad(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co, float *dw,
+                      void *stream) {
+    if (!x || !dz || !dw || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 16 || Co <= 0 || Co % 16) return MOC_EINVAL;
+    const int rows = 4;
+    const dim3 grid((unsigned)(((int64_t)N * H + rows - 1) / rows), 9);
+    hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, (hipStream_t)stream, x, dz, N, H, W, Ci, Co, dw, rows);
+    return launched();
+}
+
+int cnn_bias_grad(const float *dz, int64_t npix, int32_t Co, float *db, void *stream) {
+    if (!dz || !db || npix <= 0 || Co <= 0) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_bias_grad, dim3(grid_for(npix, 256, 64), Co), dim3(256), 0, (hipStream_t)stream, dz, npix, Co, db);
+    return launched();
+}
+
+int cnn_relu_backward(const float *dy, const uint16_t *y, int64_t n, float *dz_f32, uint16_t *dz_bf16, void *stream) {
+    if (!dy || !y || n <= 0 || (!dz_f32 && !dz_bf16)) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_relu_backward, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, dy, y, n, dz_f32, dz_bf16);
+    return launched();
+}
+
+int cnn_mse_grad(const float *y, const float *t, int64_t npix, int32_t cs, int32_t cv, float *dy, double *loss_partials,
+                 void *stream) {
+    if (!y || !t || !dy || !loss_partials || npix <= 0 || cs <= 0 || cv <= 0 || cv > cs) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_mse_grad, dim3(256), dim3(256), 0, (hipStream_t)stream, y, t, npix, cs, cv, dy, loss_partials);
+    return launched();
+}
+
+int cnn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2, float eps, int32_t t,
+             uint16_t *p_bf16, void *stream) {
+    if (!p || !g || !m || !v || n <= 0 || t < 1) return MOC_EINVAL;
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n, lr, beta1, beta2, eps, c1,
+                       c2, p_bf16);
+    return launched();
+}
+
+int cnn_to_bf16(const float *src, int64_t n, uint16_t *dst, void *stream) {
+    if (!src || !dst || n <= 0) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, src, n, dst);
+    return launched();
+}
+
+int cnn_gather_rows(const float *table, const int32_t *idx, int64_t npix, int32_t C, int32_t Cp, uint16_t *out, void *stream) {
+    if (!table || !idx || !out || npix <= 0 || C <= 0 || Cp < C) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(npix * Cp, 256)), dim3(256), 0, (hipStream_t)stream, table, idx, npix, C, Cp,
+                       out);
+    return launched();
+}
+
+int cnn_bilinear_sample(const float *img, int32_t H, int32_t W, int32_t Cs, int32_t C, const float *uv, int64_t n,
+                        int32_t apply_exp, double *out, void *stream) {
+    if (!img || !uv || !out || H <= 0 || W <= 0 || C <= 0 || Cs < C || n <= 0) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_bilinear, dim3(grid_for(n * C, 256)), dim3(256), 0, (hipStream_t)stream, img, H, W, Cs, C, uv, n,
+                       apply_exp, out);
+    return launched();
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""GPU checks of the BF16 matrix-core network kernels against the FP64 numpy oracle.
+
+Single kernels run on BF16-representable inputs, so the only differences are FP32
+accumulation order (tolerance 1e-5 relative). The whole network's gradients are
+compared at BF16 level (relative L2 error <= 3e-2), since activations are rounded to
+BF16 between layers.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cnn_oracle as CO
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _bf(a, cuda):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, np.float32), device=cuda).to(torch.bfloat16)
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("N,H,W,Ci,Co,relu", [(2, 5, 70, 32, 16, False), (1, 4, 64, 64, 64, True),
+                                               (1, 3, 20, 32, 32, True)])
+def test_conv_forward_exact(N, H, W, Ci, Co, relu, cuda):
+    import torch
+    from paper_2607_01591_amd import cnn
+    log(f"[cnn fwd] {N}x{H}x{W} {Ci}->{Co}")
+    rng = np.random.default_rng(0)
+    x = _bf(rng.normal(size=(N, H, W, Ci)), cuda)
+    w = _bf(rng.normal(0, 0.2, size=(Co, 9, Ci)), cuda)
+    b = torch.as_tensor(rng.normal(size=Co).astype(np.float32), device=cuda)
+    yf = torch.empty((N, H, W, Co), dtype=torch.float32, device=cuda)
+    yb = torch.empty((N, H, W, Co), dtype=torch.bfloat16, device=cuda)
+    cnn.conv3x3(x, w, b, relu=relu, out_bf16=yb, out_f32=yf)
+    ref = CO.conv_forward(_np(x), _np(w).reshape(Co, 3, 3, Ci), _np(b))
+    if relu:
+        ref = np.maximum(ref, 0)
+    np.testing.assert_allclose(_np(yf), ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())
+    np.testing.assert_allclose(_np(yb), ref, rtol=1e-2, atol=1e-2 * np.abs(ref).max())
+
+
+def test_wgrad_and_dgrad_exact(cuda):
+    import torch
+    from paper_2607_01591_amd import cnn
+    log("[cnn wgrad/dgrad]")
+    rng = np.random.default_rng(1)
+    N, H, W, Ci, Co = 2, 6, 40, 32, 32
+    x = _bf(rng.normal(size=(N, H, W, Ci)), cuda)
+    dz = _bf(rng.normal(size=(N, H, W, Co)), cuda)
+    w = rng.normal(0, 0.2, size=(Co, 9, Ci)).astype(np.float32)
+    w_bf = _np(_bf(w, cuda))                       # the dgrad kernel rounds weights to BF16
+    dx_ref, dW_ref, _ = CO.conv_backward(_np(x), w_bf.reshape(Co, 3, 3, Ci), _np(dz))
+    dW = torch.zeros((Co, 9, Ci), dtype=torch.float32, device=cuda)
+    cnn.wgrad(x, dz, dW)
+    np.testing.assert_allclose(_np(dW), dW_ref.reshape(Co, 9, Ci), rtol=1e-5, atol=1e-5 * np.abs(dW_ref).max())
+    wt = torch.empty((Ci, 9, Co), dtype=torch.bfloat16, device=cuda)
+    cnn.weights_for_dgrad(torch.as_tensor(w, device=cuda), wt)
+    dx = torch.empty((N, H, W, Ci), dtype=torch.float32, device=cuda)
+    cnn.conv3x3(dz, wt, None, relu=False, out_f32=dx)
+    np.testing.assert_allclose(_np(dx), dx_ref, rtol=1e-5, atol=1e-5 * np.abs(dx_ref).max())
+
+
+def test_network_gradients_match_oracle(cuda):
+    import torch
+    from paper_2607_01591_amd import cnn
+    log("[cnn network gradients]")
+    rng = np.random.default_rng(2)
+    chans = [32, 32, 32, 32]
+    net = cnn.ConvNet(chans, cuda, seed=3, in_used=32, out_used=5)
+    N, H, W = 2, 8, 64
+    x = _bf(rng.normal(size=(N, H, W, 32)), cuda)
+    t = torch.as_tensor(rng.normal(size=(N, H, W, 32)).astype(np.float32), device=cuda)
+    loss, grads = net.gradients(x, t, cv=5)
+    params = [(_np(net.Wb[i]).reshape(co, 3, 3, ci), _np(net.b[i])) for i, (ci, co) in
+              enumerate(zip(chans[:-1], chans[1:]))]
+    y, acts, pre = CO.forward(_np(x), params)
+    tt = _np(t).copy()
+    tt[..., 5:] = y[..., 5:]                   # padding channels carry no loss
+    ref = CO.backward(params, acts, pre, tt)
+    scale = y[..., :5].size / y.size           # oracle MSE averages over all channels
+    loss_ref = np.mean((y[..., :5] - _np(t)[..., :5]) ** 2)
+    assert abs(loss - loss_ref) < 2e-2 * loss_ref
+    for li in range(len(chans) - 1):
+        for g_gpu, g_ref in ((grads[li][0], ref[li][0]), (grads[li][1], ref[li][1])):
+            a = _np(g_gpu).reshape(-1)
+            b = (g_ref / scale).reshape(-1)
+            err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            assert err < 3e-2, (li, err)
+
+
+def test_adam_matches_oracle(cuda):
+    import torch
+    from paper_2607_01591_amd import cnn
+    rng = np.random.default_rng(4)
+    p0, g = rng.normal(size=1000), rng.normal(size=1000)
+    p = torch.as_tensor(p0.astype(np.float32), device=cuda)
+    gt = torch.as_tensor(g.astype(np.float32), device=cuda)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    pr, mr, vr = p0.copy(), np.zeros(1000), np.zeros(1000)
+    for step in (1, 2, 3):
+        cnn.adam(p, gt, m, v, step, lr=1e-2)
+        pr, mr, vr = CO.adam_step(pr, g, mr, vr, step, lr=1e-2)
+    np.testing.assert_allclose(_np(p), pr, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_loss(cuda):
+    import torch
+    from paper_2607_01591_amd import cnn
+    log("[cnn training]")
+    rng = np.random.default_rng(5)
+    N, H, W = 4, 16, 64
+    xin = rng.normal(size=(N, H, W, 32)).astype(np.float32)
+    # target: a fixed smooth function of the inputs (a blurred linear map)
+    tgt = np.zeros((N, H, W, 32), np.float32)
+    tgt[..., :3] = xin[..., :3] * 0.5 + 0.25 * np.roll(xin[..., 3:6], 1, axis=2)
+    net = cnn.ConvNet([32, 32, 32, 32], cuda, seed=1, out_used=3)
+    x = _bf(xin, cuda)
+    t = torch.as_tensor(tgt, device=cuda)
+    losses = [net.train_step(x, t, cv=3, lr=3e-3) for _ in range(60)]
+    assert losses[-1] < 0.3 * losses[0], (losses[0], losses[-1])
+
+
+def test_gather_and_bilinear(cuda):
+    import torch
+    from paper_2607_01591_amd import cnn
+    rng = np.random.default_rng(6)
+    table = rng.normal(size=(5, 3)).astype(np.float32)
+    idx = rng.integers(0, 5, size=(4, 6)).astype(np.int32)
+    out = torch.empty((4, 6, 8), dtype=torch.bfloat16, device=cuda)
+    cnn.gather_rows(torch.as_tensor(table, device=cuda), torch.as_tensor(idx, device=cuda), 8, out)
+    ref = np.zeros((4, 6, 8))
+    ref[..., :3] = table[idx]
+    np.testing.assert_allclose(_np(out), ref, rtol=1e-2, atol=1e-2)
+    img = rng.normal(size=(4, 6, 8)).astype(np.float32)
+    uv = np.array([[0.0, 0.0], [2.5, 1.25], [5.0, 3.0], [-1.0, 7.0]], np.float32)
+    o = torch.empty((4, 3), dtype=torch.float64, device=cuda)
+    cnn.bilinear(torch.as_tensor(img, device=cuda), 3, torch.as_tensor(uv, device=cuda), o, apply_exp=False)
+    def bil(u, v):
+        u, v = min(max(u, 0), 5), min(max(v, 0), 3)
+        x0, y0 = min(int(u), 4), min(int(v), 2)
+        fx, fy = u - x0, v - y0
+        return ((1 - fy) * ((1 - fx) * img[y0, x0] + fx * img[y0, x0 + 1])
+                + fy * ((1 - fx) * img[y0 + 1, x0] + fx * img[y0 + 1, x0 + 1]))[:3]
+    np.testing.assert_allclose(o.cpu().numpy(), np.array([bil(*p) for p in uv]), rtol=1e-6, atol=1e-6)

@@ -25,6 +25,16 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(moc.SIGNATURES), declared ^ set(moc.SIGNATURES)
 
 
+def test_library_exports_every_cnn_symbol():
+    from paper_2607_01591_amd import cnn
+    hdr = open(os.path.join(ROOT, "include", "cnn.h")).read()
+    declared = set(re.findall(r"\b(cnn_[a-z0-9_]+)\s*\(", hdr))
+    L = cnn.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(cnn.SIGNATURES), declared ^ set(cnn.SIGNATURES)
+
+
 def _compare_tracking(prob):
     s = moc.Solver(prob, device=-1)
     o = Oracle.from_problem(prob)
