@@ -69,6 +69,11 @@ int cnn_to_bf16(const float *src, int64_t n, uint16_t *dst, void *stream);
 int cnn_gather_rows(const float *table, const int32_t *idx, int64_t npix, int32_t C, int32_t Cp,
                     uint16_t *out, void *stream);
 
+/* out[p][c] = log(table[idx[p]][c]) for c < C, 0 for C <= c < Cp (table FP64 [rows][C],
+ * positive; out FP32 [npix][Cp]): training targets from a converged scalar flux. */
+int cnn_gather_log(const double *table, const int32_t *idx, int64_t npix, int32_t C, int32_t Cp,
+                   float *out, void *stream);
+
 /* De-rasterise: for each of n points with pixel coordinates (u, v) (x then y, pixel
  * centres at integers), bilinear interpolation of img FP32 [H][W][Cs] channels [0, C),
  * clamped at the border; out FP64 [n][C] = exp(value) if apply_exp else value. */

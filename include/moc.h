@@ -119,6 +119,7 @@ typedef struct {
     double dk;           /* |k_n - k_n-1| of the last iteration */
     double wall_ms;      /* host wall time of the solve */
     int32_t flags;       /* MOC_FLAG_* */
+    int32_t sweeps;      /* transport sweeps performed, including warm-start boundary sweeps */
 } moc_result;
 
 typedef struct {
@@ -179,9 +180,12 @@ int moc_solve(moc_ctx *ctx, double tol, moc_result *out);
  * values. Returns MOC_OK after n iterations. */
 int moc_run_iterations(moc_ctx *ctx, int n, moc_result *out);
 
-/* Initial guess for the next moc_solve: phi0_dev device FP64 [R][G] (required), k0 > 0,
- * psi_b0_dev device FP64 [T][2][P][G] incoming boundary fluxes in canonical track order
- * (NULL: psi = phi0 / 4 pi of the region where each track-sense enters). A guess with a
+/* Initial guess for the next moc_solve: phi0_dev device FP64 [R][G] (required, any
+ * scale); k0 > 0, or k0 <= 0 to estimate it as sum V nuSigma_f phi0 / sum V Sigma_a phi0;
+ * psi_b0_dev device FP64 [T][2][P][G] incoming boundary fluxes in canonical track order,
+ * or NULL: then psi starts at phi0 / 4 pi of the region where each track-sense enters and
+ * two transport sweeps with the source frozen at (phi0, k0) make it consistent with the
+ * guess before the iteration starts (counted in moc_result.sweeps). A guess with a
  * non-finite or negative entry, or all zeros, is not an error: moc_solve then cold-starts
  * and sets MOC_FLAG_FELL_BACK_TO_COLD. */
 int moc_set_initial_guess(moc_ctx *ctx, const double *phi0_dev, double k0, const double *psi_b0_dev);
@@ -204,6 +208,19 @@ int moc_set_exit_flux_buffer(moc_ctx *ctx, double *psi_exit_dev);
  * NULL to return to eigenvalue mode. In fixed-source mode moc_solve iterates
  * s = Sigma_s^T phi + chi F + q with k = 1 and no normalisation. */
 int moc_set_external_source(moc_ctx *ctx, const double *q_dev);
+
+/* Replace the cross sections and the region -> material map of an existing context
+ * without re-tracking (same mesh, same number of groups and materials). region_material
+ * host [R] (user order); xs host arrays as in moc_create. Clears any external source and
+ * pending initial guess. Errors: MOC_EINVAL (sizes differ, Sigma_t <= 0, bad material). */
+int moc_set_materials(moc_ctx *ctx, const int32_t *region_material, const moc_xs *xs);
+
+/* Region containing each of n points (host xy [n][2]; host out [n] user region ids, -1
+ * outside the mesh); a point on a shared edge gets one of the adjacent regions. */
+int moc_locate_points(moc_ctx *ctx, const double *xy, int64_t n, int32_t *region_out);
+
+/* Area-weighted centroid of every region (host [R][2], user order). */
+int moc_get_centroids(const moc_ctx *ctx, double *xy_out);
 
 int moc_get_info(const moc_ctx *ctx, moc_info *info);
 

@@ -23,6 +23,7 @@ SIGNATURES = {
     "cnn_adam": [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i32, _vp, _vp],
     "cnn_to_bf16": [_vp, _i64, _vp, _vp],
     "cnn_gather_rows": [_vp, _vp, _i64, _i32, _i32, _vp, _vp],
+    "cnn_gather_log": [_vp, _vp, _i64, _i32, _i32, _vp, _vp],
     "cnn_bilinear_sample": [_vp, _i32, _i32, _i32, _i32, _vp, _i64, _i32, _vp, _vp],
 }
 
@@ -106,6 +107,11 @@ def to_bf16(src, dst, stream=None):
 def gather_rows(table, idx, Cp, out, stream=None):
     _ok(lib().cnn_gather_rows(_p(table), _p(idx), idx.numel(), table.shape[-1], Cp, _p(out), _s(stream)),
         "cnn_gather_rows")
+
+
+def gather_log(table, idx, Cp, out, stream=None):
+    _ok(lib().cnn_gather_log(_p(table), _p(idx), idx.numel(), table.shape[-1], Cp, _p(out), _s(stream)),
+        "cnn_gather_log")
 
 
 def bilinear(img, C_used, uv, out, apply_exp=True, stream=None):

@@ -214,6 +214,16 @@ __global__ void k_gather_rows(const float *__restrict__ table, const int32_t *__
     }
 }
 
+__global__ void k_gather_log(const double *__restrict__ table, const int32_t *__restrict__ idx, int64_t npix, int C, int Cp,
+                             float *__restrict__ out) {
+    const int64_t n = npix * Cp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = i / Cp;
+        const int c = int(i - p * Cp);
+        out[i] = c < C ? (float)log(table[(int64_t)idx[p] * C + c]) : 0.f;
+    }
+}
+
 __global__ void k_bilinear(const float *__restrict__ img, int H, int W, int Cs, int C, const float *__restrict__ uv, int64_t n,
                            int apply_exp, double *__restrict__ out) {
     const int64_t tot = n * C;
@@ -310,6 +320,13 @@ int cnn_to_bf16(const float *src, int64_t n, uint16_t *dst, void *stream) {
 int cnn_gather_rows(const float *table, const int32_t *idx, int64_t npix, int32_t C, int32_t Cp, uint16_t *out, void *stream) {
     if (!table || !idx || !out || npix <= 0 || C <= 0 || Cp < C) return MOC_EINVAL;
     hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(npix * Cp, 256)), dim3(256), 0, (hipStream_t)stream, table, idx, npix, C, Cp,
+                       out);
+    return launched();
+}
+
+int cnn_gather_log(const double *table, const int32_t *idx, int64_t npix, int32_t C, int32_t Cp, float *out, void *stream) {
+    if (!table || !idx || !out || npix <= 0 || C <= 0 || Cp < C) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_gather_log, dim3(grid_for(npix * Cp, 256)), dim3(256), 0, (hipStream_t)stream, table, idx, npix, C, Cp,
                        out);
     return launched();
 }

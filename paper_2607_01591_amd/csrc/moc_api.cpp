@@ -36,6 +36,10 @@ struct moc_ctx {
     std::vector<SegF> host_segs_f32;
     std::vector<SegD> host_segs_f64;
     std::vector<int> host_batch_angle;
+    // point-location buckets (moc_locate_points)
+    int loc_nx = 0, loc_ny = 0;
+    std::vector<int64_t> loc_off;
+    std::vector<int> loc_tri;
     int64_t device_bytes = 0;
     double setup_ms = 0;
     int max_iter = 10000, check_every = 1, n_threads = 1;
@@ -92,6 +96,9 @@ struct moc_ctx {
 };
 
 static thread_local std::string g_create_error;
+
+// transport sweeps with a frozen source that precede a warm start without boundary fluxes
+static constexpr int kWarmBoundarySweeps = 2;
 
 template <typename F> static int guarded(moc_ctx *ctx, F &&f) {
     try {
@@ -484,7 +491,7 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         double chk[2];
         HIP_OK(hipMemcpyAsync(chk, d.partials, sizeof chk, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        use_guess = chk[0] == 0.0 && chk[1] > 0.0 && std::isfinite(c->guess_k) && c->guess_k > 0;
+        use_guess = chk[0] == 0.0 && chk[1] > 0.0 && std::isfinite(c->guess_k);
         if (!use_guess) flags |= MOC_FLAG_FELL_BACK_TO_COLD;
     }
     c->cur_phi = 0;
@@ -498,8 +505,19 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         launch_fill_real(d.psi[0], npsi, d.precision, s);
         launch_fill_real(d.psi[1], npsi, d.precision, s);
     }
-    c->host_scal[0] = eigen ? k0 : 1.0;
+    c->host_scal[0] = eigen ? (k0 > 0 ? k0 : 1.0) : 1.0;
     HIP_OK(hipMemcpyAsync(d.scal + kScalK, c->host_scal, sizeof(double), hipMemcpyHostToDevice, s));
+    if (use_guess && eigen && !(k0 > 0)) launch_k_estimate(d, d.phi[0], d.partials, s);
+    int sweeps = 0;
+    if (use_guess && !c->guess_has_psi) {
+        // boundary fluxes consistent with the guess: sweeps with the source frozen at
+        // (phi0, k0); the scalar flux of these sweeps is discarded
+        launch_source(d, d.phi[0], s);
+        for (int i = 0; i < kWarmBoundarySweeps; ++i) {
+            sweep_impl(c, s);
+            ++sweeps;
+        }
+    }
     if (eigen) {
         launch_fission_partials(d, d.phi[0], d.partials, s);
         launch_eigen_update(d, d.partials, 0, s);
@@ -513,6 +531,7 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         double *phi_old = d.phi[c->cur_phi], *phi_new = d.phi[1 - c->cur_phi];
         launch_source(d, phi_old, s);
         sweep_impl(c, s);
+        ++sweeps;
         launch_finalize(d, phi_new, nullptr, d.partials, s);
         launch_eigen_update(d, d.partials, eigen ? 1 : 2, s);
         launch_norm_residual(d, phi_new, phi_old, d.partials, s);
@@ -536,6 +555,7 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
     out->residual = res;
     out->dk = dk;
     out->flags = flags;
+    out->sweeps = sweeps;
     out->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return conv ? MOC_OK : MOC_ENOCONV;
 }
@@ -629,6 +649,134 @@ int moc_set_external_source(moc_ctx *c, const double *q_dev) {
         c->d.qext = buf;
         c->fixed_source = true;
     });
+}
+
+int moc_set_materials(moc_ctx *c, const int32_t *region_material, const moc_xs *xs) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        need_device(c);
+        DevProblem &d = c->d;
+        if (!region_material || !xs || !xs->sigma_t || !xs->sigma_s || !xs->nu_sigma_f || !xs->chi)
+            throw Error(MOC_EINVAL, "set_materials: null argument");
+        if (xs->n_groups != d.G || xs->n_materials != d.M)
+            throw Error(MOC_EINVAL, "set_materials: group and material counts must match the context");
+        const int M = d.M, G = d.G, R = d.R;
+        for (int i = 0; i < M * G; ++i)
+            if (!(xs->sigma_t[i] > 0) || !std::isfinite(xs->sigma_t[i]) || !std::isfinite(xs->nu_sigma_f[i]) ||
+                !std::isfinite(xs->chi[i]))
+                throw Error(MOC_EINVAL, "set_materials: bad cross sections");
+        for (int i = 0; i < M * G * G; ++i)
+            if (!std::isfinite(xs->sigma_s[i])) throw Error(MOC_EINVAL, "set_materials: non-finite Sigma_s");
+        std::vector<int> mat(R);
+        for (int r = 0; r < R; ++r) {
+            const int m = region_material[c->user_of_internal[r]];
+            if (m < 0 || m >= M) throw Error(MOC_EINVAL, "set_materials: material index out of range");
+            mat[r] = m;
+        }
+        HIP_OK(hipSetDevice(c->device));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        auto put = [&](void *dst, const void *src, size_t bytes) {
+            HIP_OK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+        };
+        put(d.mat, mat.data(), sizeof(int) * R);
+        put(d.sigt_m, xs->sigma_t, sizeof(double) * M * G);
+        put(d.sigs_m, xs->sigma_s, sizeof(double) * M * G * G);
+        put(d.nsf_m, xs->nu_sigma_f, sizeof(double) * M * G);
+        put(d.chi_m, xs->chi, sizeof(double) * M * G);
+        if (d.precision == MOC_PREC_F64) {
+            std::vector<double> xq((size_t)R * d.Gp * 2, 0.0);
+            for (int r = 0; r < R; ++r)
+                for (int g = 0; g < G; ++g) xq[((size_t)r * d.Gp + g) * 2] = xs->sigma_t[mat[r] * G + g];
+            put(d.xsq, xq.data(), sizeof(double) * xq.size());
+        } else {
+            std::vector<float> xq((size_t)R * d.Gp * 2, 0.0f);
+            for (int r = 0; r < R; ++r)
+                for (int g = 0; g < G; ++g) xq[((size_t)r * d.Gp + g) * 2] = (float)xs->sigma_t[mat[r] * G + g];
+            put(d.xsq, xq.data(), sizeof(float) * xq.size());
+        }
+        c->sigt_m_host.assign(xs->sigma_t, xs->sigma_t + M * G);
+        c->nsf_m_host.assign(xs->nu_sigma_f, xs->nu_sigma_f + M * G);
+        c->fissile = false;
+        for (int i = 0; i < M * G; ++i) c->fissile |= xs->nu_sigma_f[i] > 0;
+        c->fixed_source = false;
+        d.qext = nullptr;
+        c->guess_pending = false;
+    });
+}
+
+int moc_locate_points(moc_ctx *c, const double *xy, int64_t n, int32_t *region_out) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        if (!xy || !region_out || n < 0) throw Error(MOC_EINVAL, "locate_points: bad argument");
+        const Mesh &m = c->mesh;
+        // uniform bucket grid over the bounding box, built on first use
+        if (c->loc_nx == 0) {
+            const int nb = std::max(1, (int)std::sqrt((double)m.nt / 4.0));
+            c->loc_nx = nb;
+            c->loc_ny = nb;
+            const double W = m.box[2] - m.box[0], H = m.box[3] - m.box[1];
+            std::vector<std::vector<int>> cells((size_t)nb * nb);
+            for (int t = 0; t < m.nt; ++t) {
+                double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+                for (int k = 0; k < 3; ++k)
+                    for (int d2 = 0; d2 < 2; ++d2) {
+                        const double v = m.xy[2 * (size_t)m.tri[3 * (size_t)t + k] + d2];
+                        lo[d2] = std::min(lo[d2], v);
+                        hi[d2] = std::max(hi[d2], v);
+                    }
+                const int i0 = std::max(0, (int)((lo[0] - m.box[0]) / W * nb)), i1 = std::min(nb - 1, (int)((hi[0] - m.box[0]) / W * nb));
+                const int j0 = std::max(0, (int)((lo[1] - m.box[1]) / H * nb)), j1 = std::min(nb - 1, (int)((hi[1] - m.box[1]) / H * nb));
+                for (int j = j0; j <= j1; ++j)
+                    for (int i = i0; i <= i1; ++i) cells[(size_t)j * nb + i].push_back(t);
+            }
+            c->loc_off.assign((size_t)nb * nb + 1, 0);
+            for (size_t k = 0; k < cells.size(); ++k) c->loc_off[k + 1] = c->loc_off[k] + (int64_t)cells[k].size();
+            c->loc_tri.resize(c->loc_off.back());
+            for (size_t k = 0; k < cells.size(); ++k)
+                std::copy(cells[k].begin(), cells[k].end(), c->loc_tri.begin() + c->loc_off[k]);
+        }
+        const double W = m.box[2] - m.box[0], H = m.box[3] - m.box[1];
+        for (int64_t q = 0; q < n; ++q) {
+            const double px = xy[2 * q], py = xy[2 * q + 1];
+            int found = -1;
+            const int i = (int)((px - m.box[0]) / W * c->loc_nx), j = (int)((py - m.box[1]) / H * c->loc_ny);
+            if (i >= 0 && i < c->loc_nx && j >= 0 && j < c->loc_ny) {
+                const size_t cell = (size_t)j * c->loc_nx + i;
+                for (int64_t k = c->loc_off[cell]; k < c->loc_off[cell + 1] && found < 0; ++k) {
+                    const int t = c->loc_tri[k];
+                    const int *v = &m.tri[3 * (size_t)t];
+                    bool inside = true;
+                    for (int e = 0; e < 3 && inside; ++e) {
+                        const double *a = &m.xy[2 * (size_t)v[e]], *b = &m.xy[2 * (size_t)v[(e + 1) % 3]];
+                        inside = (b[0] - a[0]) * (py - a[1]) - (b[1] - a[1]) * (px - a[0]) >= 0;
+                    }
+                    if (inside) found = m.tri_region[t];
+                }
+            }
+            region_out[q] = found;
+        }
+    });
+}
+
+int moc_get_centroids(const moc_ctx *c, double *xy_out) {
+    if (!c || !xy_out) return MOC_EINVAL;
+    const Mesh &m = c->mesh;
+    std::vector<double> w(m.R, 0.0);
+    for (int r = 0; r < m.R; ++r) xy_out[2 * r] = xy_out[2 * r + 1] = 0.0;
+    for (int t = 0; t < m.nt; ++t) {
+        const int *v = &m.tri[3 * (size_t)t];
+        const double *a = &m.xy[2 * (size_t)v[0]], *b = &m.xy[2 * (size_t)v[1]], *cc = &m.xy[2 * (size_t)v[2]];
+        const double ar = 0.5 * ((b[0] - a[0]) * (cc[1] - a[1]) - (b[1] - a[1]) * (cc[0] - a[0]));
+        const int r = m.tri_region[t];
+        xy_out[2 * r] += ar * (a[0] + b[0] + cc[0]) / 3;
+        xy_out[2 * r + 1] += ar * (a[1] + b[1] + cc[1]) / 3;
+        w[r] += ar;
+    }
+    for (int r = 0; r < m.R; ++r) {
+        xy_out[2 * r] /= w[r];
+        xy_out[2 * r + 1] /= w[r];
+    }
+    return MOC_OK;
 }
 
 int moc_get_info(const moc_ctx *c, moc_info *info) {

@@ -78,6 +78,7 @@ void launch_prep_user(const DevProblem &d, const double *src_user, hipStream_t s
 void launch_source(const DevProblem &d, const double *phi, hipStream_t s);
 void launch_finalize(const DevProblem &d, double *phi_internal, double *phi_user, double *partials, hipStream_t s);
 void launch_fission_partials(const DevProblem &d, const double *phi, double *partials, hipStream_t s);
+void launch_k_estimate(const DevProblem &d, const double *phi, double *partials, hipStream_t s);
 void launch_eigen_update(const DevProblem &d, const double *partials, int mode, hipStream_t s);
 void launch_norm_residual(const DevProblem &d, double *phi_new, const double *phi_old, double *partials, hipStream_t s);
 void launch_psi_canon(const DevProblem &d, double *canon, void *psi, int to_canon, hipStream_t s);

@@ -341,6 +341,39 @@ __global__ void k_fission_partials(const double *__restrict__ phi, const double 
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// partials of sum V Sigma_a phi (absorption), Sigma_a = Sigma_t - sum_g' Sigma_s,g->g'
+__global__ void k_absorption_partials(const double *__restrict__ phi, const double *__restrict__ V, const int *__restrict__ mat,
+                                      const double *__restrict__ sigt_m, const double *__restrict__ sigs_m,
+                                      double *__restrict__ partials, int R, int G) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        const int m = mat[r];
+        double a = 0.0;
+        for (int g = 0; g < G; ++g) {
+            double out = 0.0;
+            for (int gp = 0; gp < G; ++gp) out += sigs_m[((int64_t)m * G + g) * G + gp];
+            a += (sigt_m[m * G + g] - out) * phi[(int64_t)r * G + g];
+        }
+        acc += V[r] * a;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// k = (sum of partials_f) / (sum of partials_a), single block
+__global__ void k_k_estimate(const double *__restrict__ pf, const double *__restrict__ pa, int nblk, double *__restrict__ scal) {
+    __shared__ double sh[16];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        a += pf[i];
+        b += pa[i];
+    }
+    const double sa = block_sum(a, sh);
+    const double sb = block_sum(b, sh);
+    if (threadIdx.x == 0) scal[kScalK] = (sb > 0 && sa > 0) ? sa / sb : 1.0;
+}
+
 // Single block. mode 0: initial normalisation (f = 1/sum); mode 1: eigenvalue update
 // k <- k * sum V F_new (the old iterate has sum V F = 1), f = 1/sum; mode 2: fixed source
 // (k = 1, f = 1). Partials are summed in a fixed order (deterministic).
@@ -591,6 +624,14 @@ void launch_finalize(const DevProblem &d, double *phi_internal, double *phi_user
 
 void launch_fission_partials(const DevProblem &d, const double *phi, double *partials, hipStream_t s) {
     hipLaunchKernelGGL(k_fission_partials, dim3(kReduceBlocks), dim3(256), 0, s, phi, d.V, d.mat, d.nsf_m, partials, d.R, d.G);
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_k_estimate(const DevProblem &d, const double *phi, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_fission_partials, dim3(kReduceBlocks), dim3(256), 0, s, phi, d.V, d.mat, d.nsf_m, partials, d.R, d.G);
+    hipLaunchKernelGGL(k_absorption_partials, dim3(kReduceBlocks), dim3(256), 0, s, phi, d.V, d.mat, d.sigt_m, d.sigs_m,
+                       partials + kReduceBlocks, d.R, d.G);
+    hipLaunchKernelGGL(k_k_estimate, dim3(1), dim3(256), 0, s, partials, partials + kReduceBlocks, kReduceBlocks, d.scal);
     MOC_CHECK_LAUNCH();
 }
 

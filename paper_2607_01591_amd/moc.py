@@ -52,7 +52,7 @@ class MocOptions(C.Structure):
 
 class MocResult(C.Structure):
     _fields_ = [("k", _f64), ("iterations", _i32), ("residual", _f64), ("dk", _f64),
-                ("wall_ms", _f64), ("flags", _i32)]
+                ("wall_ms", _f64), ("flags", _i32), ("sweeps", _i32)]
 
 
 class MocInfo(C.Structure):
@@ -89,6 +89,9 @@ SIGNATURES = {
     "moc_get_quadrature": (C.c_int, [C.c_void_p, _P(_f64), _P(_f64), _P(_f64), _P(_f64), _P(_f64)]),
     "moc_last_error": (C.c_char_p, [C.c_void_p]),
     "moc_set_profiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "moc_set_materials": (C.c_int, [C.c_void_p, _P(_i32), _P(MocXS)]),
+    "moc_locate_points": (C.c_int, [C.c_void_p, _P(_f64), _i64, _P(_i32)]),
+    "moc_get_centroids": (C.c_int, [C.c_void_p, _P(_f64)]),
     "moc_get_profile": (C.c_int, [C.c_void_p, _P(MocProfile)]),
 }
 
@@ -227,7 +230,7 @@ class Solver:
         rc = lib().moc_solve(self._h, tol, C.byref(r))
         self._check(rc, (MOC_OK,) if raise_on_noconv else (MOC_OK, MOC_ENOCONV))
         return dict(k=r.k, iterations=r.iterations, residual=r.residual, dk=r.dk,
-                    wall_ms=r.wall_ms, flags=r.flags, converged=(rc == MOC_OK))
+                    wall_ms=r.wall_ms, flags=r.flags, sweeps=r.sweeps, converged=(rc == MOC_OK))
 
     def flux(self, stream=None):
         import torch
@@ -285,6 +288,26 @@ class Solver:
         torch.cuda.current_stream().synchronize()
         self._check(lib().moc_run_iterations(self._h, int(n), C.byref(r)))
         return dict(k=r.k, iterations=r.iterations, residual=r.residual, dk=r.dk, wall_ms=r.wall_ms)
+
+    def set_materials(self, prob):
+        """Swap in the cross sections and material map of ``prob`` (same mesh)."""
+        rm = np.ascontiguousarray(prob.region_material, np.int32)
+        arrs = [np.ascontiguousarray(a, np.float64) for a in (prob.sigma_t, prob.sigma_s, prob.nu_sigma_f, prob.chi)]
+        x = MocXS()
+        x.n_materials, x.n_groups = arrs[0].shape
+        x.sigma_t, x.sigma_s, x.nu_sigma_f, x.chi = (_ptr(a, _f64) for a in arrs)
+        self._check(lib().moc_set_materials(self._h, _ptr(rm, _i32), C.byref(x)))
+
+    def locate(self, xy) -> np.ndarray:
+        xy = np.ascontiguousarray(xy, np.float64).reshape(-1, 2)
+        out = np.zeros(len(xy), np.int32)
+        self._check(lib().moc_locate_points(self._h, _ptr(xy, _f64), len(xy), _ptr(out, _i32)))
+        return out
+
+    def centroids(self) -> np.ndarray:
+        out = np.zeros((self.R, 2))
+        self._check(lib().moc_get_centroids(self._h, _ptr(out, _f64)))
+        return out
 
     # ---------------------------------------------------------------- host queries
     def volumes(self) -> np.ndarray:

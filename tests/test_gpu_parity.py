@@ -192,11 +192,13 @@ def test_initial_guess_and_fallback(oracle_solutions, cuda):
     again = s.solve(1e-9)
     assert again["converged"] and again["iterations"] <= 3
     assert again["flags"] & moc.FLAG_FELL_BACK_TO_COLD == 0
-    # the oracle's converged flux with boundary fluxes estimated from it: fewer
-    # iterations than cold, same answer
-    s.set_initial_guess(_dev(ref["phi"], cuda), ref["k"])
+    # the oracle's converged flux without boundary fluxes: two frozen-source sweeps make
+    # them consistent, so the iteration needs a small fraction of the cold count; k0 is
+    # estimated from the flux when not given
+    s.set_initial_guess(_dev(ref["phi"], cuda), -1.0)
     warm = s.solve(1e-9)
-    assert warm["converged"] and warm["iterations"] < cold["iterations"]
+    assert warm["converged"] and warm["sweeps"] == warm["iterations"] + 2
+    assert warm["sweeps"] < cold["iterations"] / 3, (warm, cold)
     assert abs(warm["k"] - ref["k"]) < 1e-8
     # garbage guesses fall back to cold start and still converge to the same answer
     for bad in (np.full_like(ref["phi"], np.nan), -ref["phi"], np.zeros_like(ref["phi"])):
