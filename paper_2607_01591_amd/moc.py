@@ -340,6 +340,12 @@ class Solver:
             _ptr(out["user_of_internal"], _i32)))
         return out
 
+    def tracks_angles(self) -> np.ndarray:
+        """Track angle index of every canonical track (no segment dump)."""
+        ang = np.zeros(self.T, np.int32)
+        self._check(lib().moc_get_tracks(self._h, _ptr(ang, _i32), None, None, None, None, None))
+        return ang
+
     def tracks(self) -> dict:
         T, S = self.T, self.S
         ang = np.zeros(T, np.int32)
