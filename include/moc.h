@@ -110,6 +110,7 @@ typedef struct {
     double window_cm;    /* tally window length along the tracks in cm (<= 0: about 32
                             segments per window) */
     int32_t tally_slots; /* maximum distinct regions per tally window, 64..512 (0: 256) */
+    int32_t group_batch; /* groups per sweep wavefront: 1, 2, 4, 7, 8 or 11 (0: chosen from G) */
 } moc_options;
 
 typedef struct {

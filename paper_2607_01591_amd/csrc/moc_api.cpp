@@ -201,7 +201,10 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     d.T = T;
     d.precision = o.precision;
     d.exp_mode = o.exp_mode;
-    d.gb = choose_group_batch(G);
+    if (o.group_batch != 0 && o.group_batch != 1 && o.group_batch != 2 && o.group_batch != 4 && o.group_batch != 7 &&
+        o.group_batch != 8 && o.group_batch != 11)
+        throw Error(MOC_EINVAL, "options: group_batch must be 0, 1, 2, 4, 7, 8 or 11");
+    d.gb = o.group_batch > 0 ? o.group_batch : choose_group_batch(G);
     d.n_gb = (G + d.gb - 1) / d.gb;
     d.Gp = ((d.n_gb * d.gb + 3) / 4) * 4;
     const bool f64 = o.precision == MOC_PREC_F64;

@@ -25,15 +25,21 @@ template <> struct SegOf<float> { using type = SegF; };
 template <> struct SegOf<double> { using type = SegD; };
 
 // ---------------------------------------------------------------- 1 - exp(-tau)
-// FP32, MOC_EXP_POLY: for tau >= 1/16 use 1 - 2^(-tau log2 e) with the hardware
-// exponential (absolute error ~6e-8, so relative <= 1e-6 there); below, the Taylor
-// series of 1 - e^-tau through tau^4 (truncation < tau^5/120, relative < 1.3e-7 at
-// 1/16). Relative accuracy matters because the tally takes (psi - qhat) * F directly.
-__device__ __forceinline__ float one_minus_exp_poly(float tau) {
-    const float e = __builtin_amdgcn_exp2f(tau * -1.4426950408889634f);
-    const float big = 1.0f - e;
-    const float small = tau * (1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f))));
-    return tau < 0.0625f ? small : big;
+// FP32, MOC_EXP_POLY, evaluated from x = -tau log2(e) (folded into the per-polar
+// constant, so one multiply forms x): for tau >= 0.094 use 1 - 2^x with the hardware
+// exponential (absolute error ~6e-8, relative <= 6.4e-7 there); below, the Taylor series
+// of 1 - 2^x through x^4 (truncation < tau^4/120 <= 6.5e-7 relative). Relative accuracy
+// matters because the tally takes (psi - qhat) * F directly.
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kPolyC1 = -kLn2;
+constexpr float kPolyC2 = -kLn2 * kLn2 / 2.0f;
+constexpr float kPolyC3 = -kLn2 * kLn2 * kLn2 / 6.0f;
+constexpr float kPolyC4 = -kLn2 * kLn2 * kLn2 * kLn2 / 24.0f;
+constexpr float kPolyXThreshold = -0.094f * 1.4426950408889634f;
+__device__ __forceinline__ float one_minus_exp2_poly(float x) {
+    const float big = 1.0f - __builtin_amdgcn_exp2f(x);
+    const float small = x * (kPolyC1 + x * (kPolyC2 + x * (kPolyC3 + x * kPolyC4)));
+    return x > kPolyXThreshold ? small : big;
 }
 
 // MOC_EXP_TABLE: linear interpolation of f(x) = (1 - e^-x)/x on a uniform grid held in
@@ -44,9 +50,7 @@ struct ExpTable {
 };
 
 template <int MODE> __device__ __forceinline__ float one_minus_exp_f(float tau, const float *lut) {
-    if constexpr (MODE == MOC_EXP_POLY) {
-        return one_minus_exp_poly(tau);
-    } else if constexpr (MODE == MOC_EXP_TABLE) {
+    if constexpr (MODE == MOC_EXP_TABLE) {
         const float x = tau * (ExpTable::kN / ExpTable::kMax);
         if (x < float(ExpTable::kN - 1)) {
             const int i = int(x);
@@ -105,11 +109,14 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     const Real *__restrict__ inv_sin = reinterpret_cast<const Real *>(args.inv_sin);
     double *__restrict__ tally = args.tally;
 
+    // per polar angle: tally weight, and the factor turning Sigma_t l into the exponent
+    // argument (tau = Sigma_t l / sin(theta), or x = -tau log2(e) for the POLY mode)
+    constexpr bool kX = sizeof(Real) == 4 && MODE == MOC_EXP_POLY;
     Real c[NP], is[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         c[p] = coef[a * NP + p];
-        is[p] = inv_sin[p];
+        is[p] = kX ? Real(-1.4426950408889634) * inv_sin[p] : inv_sin[p];
     }
     Real psi[NP][GB];
 #pragma unroll
@@ -178,7 +185,11 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
                 Real acc = 0;
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
-                    const Real F = one_minus_exp<Real, MODE>(sl * is[p], lut);
+                    Real F;
+                    if constexpr (kX)
+                        F = one_minus_exp2_poly(sl * is[p]);
+                    else
+                        F = one_minus_exp<Real, MODE>(sl * is[p], lut);
                     const Real d = (psi[p][j] - q0[j]) * F;
                     psi[p][j] -= d;
                     acc += c[p] * d;
