@@ -39,7 +39,11 @@ def parse():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-hex", action="store_true")
+    ap.add_argument("--solve-seeds", type=int, default=3)
     ap.add_argument("--exp-mode", default="poly")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also launch a plain 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
 
 
@@ -121,6 +125,14 @@ def main():
         f"setup {info['setup_ms']:.0f} ms, device {info['device_bytes'] / 2**30:.2f} GiB")
     ms, prof, r = time_iterations(s32, args.steps, args.warmup)
     U = info["n_updates"]
+    if args.copy_probe:
+        src_c = torch.ones(1 << 28, dtype=torch.float32, device="cuda")     # 1 GiB
+        dst_c = torch.empty_like(src_c)
+        for _ in range(2):
+            dst_c.copy_(src_c)
+        torch.cuda.synchronize()
+        log("copy probe: 2 x 1 GiB device-to-device copies")
+        del src_c, dst_c
     sweep_ms = prof["sweep_ms"] / max(1, prof["sweeps"])
     log(f"FP32: {ms:.3f} ms/iteration, sweep kernel {sweep_ms:.3f} ms avg over {prof['sweeps']}, "
         f"k={r['k']:.6f}")
@@ -147,16 +159,49 @@ def main():
         del s64
         torch.cuda.empty_cache()
 
+    hexa = None
+    if not args.no_hex:
+        log("hexagonal assembly (33 groups): FP32 sweep throughput")
+        ph = P.config(4)
+        sh = moc.Solver(ph, precision="f32", check_every=1 << 30)
+        msh, profh, _ = time_iterations(sh, 5, 1)
+        swh = profh["sweep_ms"] / max(1, profh["sweeps"])
+        hexa = {"workload": f"{ph.name}: {sh.R} regions, 33 groups", "updates_per_sweep": sh.U,
+                "updates_per_s": sh.U / (msh * 1e-3), "ms_per_step": msh, "sweep_kernel_ms": swh}
+        log(f"hexagon: {msh:.3f} ms/iteration, sweep {swh:.3f} ms, {sh.U / (msh * 1e-3):.3e} updates/s")
+        del sh
+        torch.cuda.empty_cache()
+
     solve = None
     if not args.no_solve:
-        log("cold solve to 1e-6 on a 17x17 lattice (held-out seed 200000)")
-        p5 = P.config(5, seed=200000)
-        s5 = moc.Solver(p5, precision="f32", max_iter=20000)
-        r5 = s5.solve(1e-6)
-        solve = {"workload": "17x17 lattice seed 200000, FP32 sweep", "cold_iterations": r5["iterations"],
-                 "cold_wall_ms": r5["wall_ms"], "converged": r5["converged"], "k": r5["k"],
-                 "warm": None}
-        log(f"cold solve: {r5['iterations']} iterations, {r5['wall_ms']:.0f} ms")
+        import numpy as np
+        weights = os.path.join(ROOT, "paper_2607_01591_amd", "weights", "warmstart_17x17.npz")
+        log("time to 1e-6 on 17x17 lattices (held-out seeds), cold vs warm start")
+        base = P.config(5, seed=100000)
+        s5 = moc.Solver(base, precision="f32", max_iter=20000, check_every=10)
+        ws = None
+        if os.path.exists(weights):
+            from paper_2607_01591_amd.warmstart import CHANNELS, WarmStart
+            ws = WarmStart(s5, base, torch.device("cuda:0"))
+            st = np.load(weights)
+            ws.net.load({"W": [st[f"W{i}"] for i in range(len(CHANNELS) - 1)],
+                         "b": [st[f"b{i}"] for i in range(len(CHANNELS) - 1)]})
+        rows = []
+        for sd in range(200000, 200000 + args.solve_seeds):
+            p5 = P.config(5, seed=sd)
+            s5.set_materials(p5)
+            c = s5.solve(1e-6)
+            row = {"seed": sd, "cold_iterations": c["iterations"], "cold_ms": c["wall_ms"]}
+            if ws is not None:
+                w = ws.solve_warm(p5, 1e-6)
+                row.update(warm_sweeps=w["sweeps"], warm_iterations=w["iterations"], warm_ms=w["total_ms"],
+                           warm_predict_ms=w["predict_ms"], warm_converged=w["converged"])
+            rows.append(row)
+            log(f"seed {sd}: {row}")
+        med = lambda k: float(np.median([r[k] for r in rows])) if rows and k in rows[0] else None
+        solve = {"workload": "17x17 lattice family (31k regions), FP32 sweep, residual 1e-6",
+                 "cold_iterations_median": med("cold_iterations"), "cold_ms_median": med("cold_ms"),
+                 "warm_sweeps_median": med("warm_sweeps"), "warm_ms_median": med("warm_ms"), "runs": rows}
 
     cpu = None
     if not args.no_cpu:
@@ -185,6 +230,7 @@ def main():
         "hbm_view": hbm,
         "fp64": fp64,
         "time_to_tol": solve,
+        "hexagon_g33": hexa,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -1,0 +1,79 @@
+"""Learned warm start on the GPU: the trained network's guess (BF16 matrix-core
+inference) must lead the plain power iteration to the same converged answer as the
+cold start, in fewer transport sweeps; a corrupted prediction must fall back to the
+cold start. The comparison runs the FP64 sweep to a tight tolerance so that the two
+converged answers can be compared closely (the network's guess itself is precision-
+independent)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2607_01591_amd import moc
+from paper_2607_01591_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2607_01591_amd", "weights", "warmstart_17x17.npz")
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup(cuda):
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("no trained warm-start weights in the tree")
+    from paper_2607_01591_amd.warmstart import CHANNELS, WarmStart
+    base = P.config(5, seed=100000)
+    s = moc.Solver(base, precision="f64", max_iter=20000, check_every=1)
+    ws = WarmStart(s, base, cuda)
+    st = np.load(WEIGHTS)
+    ws.net.load({"W": [st[f"W{i}"] for i in range(len(CHANNELS) - 1)],
+                 "b": [st[f"b{i}"] for i in range(len(CHANNELS) - 1)]})
+    return s, ws
+
+
+@pytest.mark.parametrize("seed", [200000, 200001])
+def test_warm_start_same_answer_fewer_sweeps(seed, setup, cuda):
+    from paper_2607_01591_amd.warmstart import homogenized_guess
+    s, ws = setup
+    log(f"[warm start] seed {seed}")
+    p = P.config(5, seed=seed)
+    s.set_materials(p)
+    cold = s.solve(1e-9)
+    phi_c = s.flux().cpu().numpy()
+    warm = ws.solve_warm(p, 1e-9)
+    phi_w = s.flux().cpu().numpy()
+    assert cold["converged"] and warm["converged"]
+    assert not warm["flags"] & moc.FLAG_FELL_BACK_TO_COLD
+    assert abs(warm["k"] - cold["k"]) < 1e-8
+    assert np.max(np.abs(phi_w - phi_c) / phi_c) < 1e-6
+    log(f"  cold {cold['sweeps']} sweeps, warm {warm['sweeps']} sweeps")
+    assert warm["sweeps"] < cold["sweeps"]
+    # the network does better than the non-learned flat homogenised guess
+    s.set_initial_guess(homogenized_guess(p, s.volumes(), cuda), -1.0)
+    hom = s.solve(1e-9)
+    log(f"  homogenised guess {hom['sweeps']} sweeps")
+    assert warm["sweeps"] < hom["sweeps"]
+
+
+def test_corrupted_prediction_falls_back(setup, cuda):
+    import torch
+    s, ws = setup
+    p = P.config(5, seed=200002)
+    s.set_materials(p)
+    phi0, _ = ws.predict(p)
+    phi0[0, 0] = float("nan")
+    s.set_initial_guess(phi0, -1.0)
+    r = s.solve(1e-8)
+    assert r["flags"] & moc.FLAG_FELL_BACK_TO_COLD and r["converged"]
+    phi0 = torch.abs(phi0.nan_to_num(1.0)) * -1.0
+    s.set_initial_guess(phi0, -1.0)
+    r2 = s.solve(1e-8)
+    assert r2["flags"] & moc.FLAG_FELL_BACK_TO_COLD and r2["converged"]
+    assert abs(r2["k"] - r["k"]) < 1e-8
