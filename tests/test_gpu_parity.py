@@ -207,3 +207,35 @@ def test_initial_guess_and_fallback(oracle_solutions, cuda):
         assert r["flags"] & moc.FLAG_FELL_BACK_TO_COLD
         assert r["converged"] and abs(r["k"] - ref["k"]) < 1e-8
         assert abs(r["iterations"] - cold["iterations"]) <= 1
+
+
+@pytest.mark.parametrize("exp_mode", ["table", "libm"])
+def test_exp_modes_sweep_parity(exp_mode, cuda):
+    log(f"[sweep parity] exp mode {exp_mode}")
+    prob = P.square_lattice(3, 2, seed=3, n_azim=32, spacing=0.05, bc=(1, 0, 1, 0))
+    o = Oracle.from_problem(prob)
+    s = moc.Solver(prob, precision="f32", exp_mode=exp_mode)
+    rng = np.random.default_rng(12)
+    src = rng.uniform(0.1, 2.0, size=(o.R, o.G))
+    psi0 = rng.uniform(0.0, 1.0, size=o.psi_shape()).astype(np.float32).astype(np.float64)
+    o.set_psi(psi0)
+    ref = o.sweep(src)
+    s.set_boundary_flux(_dev(psi0, cuda))
+    phi = _host(s.sweep(_dev(src, cuda)))
+    assert rel_err(phi, ref) < 1e-5
+
+
+def test_set_materials_equals_fresh_context(cuda):
+    log("[set_materials]")
+    a = P.config(5, seed=100003)
+    b = P.config(5, seed=100004)
+    s = moc.Solver(a, precision="f64", max_iter=20000)
+    s.set_materials(b)
+    r1 = s.solve(1e-9)
+    phi1 = _host(s.flux())
+    fresh = moc.Solver(b, precision="f64", max_iter=20000)
+    r2 = fresh.solve(1e-9)
+    phi2 = _host(fresh.flux())
+    assert r1["iterations"] == r2["iterations"]
+    assert abs(r1["k"] - r2["k"]) < 1e-12
+    np.testing.assert_allclose(phi1, phi2, rtol=1e-10)
