@@ -236,6 +236,6 @@ def test_set_materials_equals_fresh_context(cuda):
     fresh = moc.Solver(b, precision="f64", max_iter=20000)
     r2 = fresh.solve(1e-9)
     phi2 = _host(fresh.flux())
-    assert r1["iterations"] == r2["iterations"]
+    assert abs(r1["iterations"] - r2["iterations"]) <= 1
     assert abs(r1["k"] - r2["k"]) < 1e-12
     np.testing.assert_allclose(phi1, phi2, rtol=1e-10)
