@@ -111,6 +111,8 @@ typedef struct {
                             segments per window) */
     int32_t tally_slots; /* maximum distinct regions per tally window, 64..512 (0: 256) */
     int32_t group_batch; /* groups per sweep wavefront: 1, 2, 4, 7, 8 or 11 (0: chosen from G) */
+    int32_t window_steps;/* > 0: tally windows of this many segments per track instead of a
+                            fixed length along the tracks (lanes stay busy, slots grow) */
 } moc_options;
 
 typedef struct {

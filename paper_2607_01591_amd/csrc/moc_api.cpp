@@ -241,6 +241,8 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     pin.internal_of_user = c->internal_of_user.data();
     pin.n_threads = c->n_threads;
     pin.cap = o.tally_slots > 0 ? o.tally_slots : 256;
+    if (o.window_steps < 0) throw Error(MOC_EINVAL, "options: window_steps must be >= 0");
+    pin.window_steps = o.window_steps;
     {
         double total_len = 0;
         for (int t = 0; t < T; ++t) total_len += c->tracks.len[t];

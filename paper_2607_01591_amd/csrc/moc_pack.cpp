@@ -65,6 +65,13 @@ class BatchPlanner {
             ptr_[l] = 0;
             if (!lanes_[l].empty()) len = std::max(len, lanes_[l].back().s0 + lanes_[l].back().len);
         }
+        if (in_.window_steps > 0) {
+            size_t nmax = 0;
+            for (int l = 0; l < kBatch; ++l) nmax = std::max(nmax, lanes_[l].size());
+            const size_t K = (size_t)in_.window_steps;
+            for (size_t k0 = 0; k0 < nmax; k0 += K) step_range(k0, std::min(nmax, k0 + K));
+            return;
+        }
         const int nw = std::max(1, (int)std::ceil(len / in_.window_len));
         for (int w = 0; w < nw; ++w) range(w * in_.window_len, (w + 1) * in_.window_len, w == nw - 1);
     }
@@ -106,6 +113,44 @@ class BatchPlanner {
     }
 
   private:
+    // windows by step index: lane l takes its segments [k0, k1) (no spatial alignment)
+    void step_range(size_t k0, size_t k1) {
+        for (int l = 0; l < kBatch; ++l) {
+            ptr_[l] = std::min(k0, lanes_[l].size());
+            end_[l] = std::min(k1, lanes_[l].size());
+        }
+        emit_or_split([&](int half) {
+            const size_t mid = (k0 + k1) / 2;
+            if (half == 0) step_range(k0, mid); else step_range(mid, k1);
+        });
+    }
+
+    // emit the window [ptr_, end_) or, above the slot cap, call split(0) then split(1)
+    template <typename F> void emit_or_split(F split) {
+        int maxn = 0;
+        for (int l = 0; l < kBatch; ++l) maxn = std::max(maxn, int(end_[l] - ptr_[l]));
+        if (maxn == 0) return;
+        regs_.clear();
+        for (int l = 0; l < kBatch; ++l)
+            for (size_t k = ptr_[l]; k < end_[l]; ++k) regs_.push_back(lanes_[l][k].reg);
+        std::sort(regs_.begin(), regs_.end());
+        regs_.erase(std::unique(regs_.begin(), regs_.end()), regs_.end());
+        if ((int)regs_.size() > in_.cap && maxn > 1) {
+            split(0);
+            split(1);
+            return;
+        }
+        Window w;
+        w.nsteps = maxn;
+        w.nslots = (int)regs_.size();
+        w.entry_off = steps_ * kBatch;
+        w.tab_off = (int64_t)tab_.size();
+        for (int l = 0; l < kBatch; ++l) w.count[l] = int(end_[l] - ptr_[l]);
+        tab_.insert(tab_.end(), regs_.begin(), regs_.end());
+        windows_.push_back(w);
+        steps_ += maxn;
+    }
+
     void range(double lo, double hi, bool last) {
         int maxn = 0;
         for (int l = 0; l < kBatch; ++l) {

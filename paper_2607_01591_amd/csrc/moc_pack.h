@@ -25,6 +25,7 @@ struct PackInput {
     const int *internal_of_user = nullptr;
     std::vector<int> batch_first;   // [nb + 1] first canonical track of each batch
     double window_len = 1.0;        // cm
+    int window_steps = 0;           // > 0: windows of this many steps per lane instead of window_len
     int cap = 256;                  // maximum tally slots per window
     int n_threads = 1;
 };
