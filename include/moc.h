@@ -109,7 +109,7 @@ typedef struct {
     int32_t n_threads;   /* host threads for tracking (<= 0: all hardware threads) */
     double window_cm;    /* tally window length along the tracks in cm (<= 0: about 32
                             segments per window) */
-    int32_t tally_slots; /* maximum distinct regions per tally window, 64..512 (0: 256) */
+    int32_t tally_slots; /* maximum distinct regions per tally window, 64..256 (0: 256) */
     int32_t group_batch; /* groups per sweep wavefront: 1, 2, 4, 7, 8 or 11 (0: chosen from G) */
     int32_t window_steps;/* > 0: tally windows of this many segments per track instead of a
                             fixed length along the tracks (lanes stay busy, slots grow) */

@@ -151,8 +151,8 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     o.precision = MOC_PREC_F32;
     o.exp_mode = MOC_EXP_POLY;
     if (opt) o = *opt;
-    if (o.tally_slots != 0 && (o.tally_slots < kBatch || o.tally_slots > (1 << kSlotBits)))
-        throw Error(MOC_EINVAL, "options: tally_slots must be 0 or in 64..512");
+    if (o.tally_slots != 0 && (o.tally_slots < kBatch || o.tally_slots > kMaxSlots))
+        throw Error(MOC_EINVAL, "options: tally_slots must be 0 or in 64..256");
     if (o.precision != MOC_PREC_F32 && o.precision != MOC_PREC_F64) throw Error(MOC_EINVAL, "options: bad precision");
     if (o.exp_mode < MOC_EXP_POLY || o.exp_mode > MOC_EXP_LIBM) throw Error(MOC_EINVAL, "options: bad exp_mode");
     c->max_iter = o.max_iter > 0 ? o.max_iter : 10000;

@@ -12,6 +12,9 @@ enum { kScalK = 0, kScalKPrev = 1, kScalF = 2, kScalRes = 3, kScalDk = 4, kScalF
 constexpr int kExpTableN = 2048;
 constexpr float kExpTableMax = 16.0f;
 
+// largest tally window the sweep kernel accepts (slots per window)
+constexpr int kMaxSlots = 256;
+
 // fixed number of blocks for the FP64 reductions (partials are summed in block order)
 constexpr int kReduceBlocks = 512;
 

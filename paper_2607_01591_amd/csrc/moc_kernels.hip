@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     double *tl = reinterpret_cast<double *>(smem);   // tally [GB][cap], FP64 (ds_add_f64 is much
     // faster than ds_add_f32 on gfx950 and keeps the window sums exact to FP64 rounding)
     const int cap = args.cap;
-    float *lut = reinterpret_cast<float *>(smem + sizeof(double) * GB * cap);
+    float *lut = reinterpret_cast<float *>(smem + (sizeof(double) * GB + sizeof(int)) * cap);
     if constexpr (MODE == MOC_EXP_TABLE && sizeof(Real) == 4) {
         for (int i = threadIdx.x; i < ExpTable::kN; i += 64) lut[i] = args.exp_table[i];
     }
@@ -159,11 +159,18 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
         }
     };
 
+    int *tabl = reinterpret_cast<int *>(smem + sizeof(double) * GB * cap);   // slot -> region
     const int64_t w0 = args.batch_win[b], w1 = args.batch_win[b + 1];
     for (int64_t wi = 0; wi < w1 - w0; ++wi) {
         const int64_t w = sense ? w1 - 1 - wi : w0 + wi;
         const int n = args.win_nsteps[w];
         const Seg *__restrict__ ws = segs + args.win_entry_off[w];
+        // the window's slot table, fetched now and staged in LDS for the flush
+        const int ns = args.win_nslots[w];
+        const int *__restrict__ tab = args.win_tab + args.win_tab_off[w];
+        int tabv[kMaxSlots / 64];
+#pragma unroll
+        for (int u = 0; u < kMaxSlots / 64; ++u) tabv[u] = (u * 64 + lane < ns) ? tab[u * 64 + lane] : 0;
         auto step_of = [&](int i) { return (int64_t)(sense ? n - 1 - i : i) * 64 + lane; };
         // software pipeline: segment entries four steps ahead and cross sections two
         // steps ahead are in flight while the current step computes
@@ -208,15 +215,16 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
                 q1[j] = q2[j];
             }
         }
+#pragma unroll
+        for (int u = 0; u < kMaxSlots / 64; ++u)
+            if (u * 64 + lane < ns) tabl[u * 64 + lane] = tabv[u];
         __syncthreads();
         // flush the window's slots: (slot, group) pairs, groups fastest
-        const int ns = args.win_nslots[w];
-        const int *__restrict__ tab = args.win_tab + args.win_tab_off[w];
         for (int e = lane; e < ns * GB; e += 64) {
             const int sl = e / GB, j = e - sl * GB;
             const double v = tl[j * cap + sl];
             if (v != 0.0) {
-                unsafeAtomicAdd(&tally[(int64_t)tab[sl] * Gp + g0 + j], v);
+                unsafeAtomicAdd(&tally[(int64_t)tabl[sl] * Gp + g0 + j], v);
                 tl[j * cap + sl] = 0.0;
             }
         }
@@ -530,7 +538,8 @@ static inline int grid_for(int64_t n, int block, int cap = 4096) {
 
 template <typename Real, int NP, int GB, int MODE>
 static void sweep_inst(const SweepArgs &a, int nb, int n_gb, hipStream_t s) {
-    size_t lds = sizeof(double) * GB * (size_t)a.cap;
+    if (a.cap > kMaxSlots) throw Error(MOC_EINVAL, "sweep: window slot count above the kernel maximum");
+    size_t lds = (sizeof(double) * GB + sizeof(int)) * (size_t)a.cap;
     if (MODE == MOC_EXP_TABLE && sizeof(Real) == 4) lds += sizeof(float) * ExpTable::kN;
     if (lds > 64 * 1024) throw Error(MOC_EINVAL, "sweep: tally window does not fit in LDS");
     hipLaunchKernelGGL((k_sweep<Real, NP, GB, MODE>), dim3(nb, 2, n_gb), dim3(64), lds, s, a);
