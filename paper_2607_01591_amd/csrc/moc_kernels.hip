@@ -172,23 +172,15 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
 #pragma unroll
         for (int u = 0; u < kMaxSlots / 64; ++u) tabv[u] = (u * 64 + lane < ns) ? tab[u * 64 + lane] : 0;
         auto step_of = [&](int i) { return (int64_t)(sense ? n - 1 - i : i) * 64 + lane; };
-        // software pipeline: segment entries four steps ahead and cross sections two
-        // steps ahead are in flight while the current step computes
         auto clampi = [&](int i) { return i < n ? i : n - 1; };
-        Seg s0 = ws[step_of(0)], s1 = ws[step_of(clampi(1))], s2 = ws[step_of(clampi(2))],
-            s3 = ws[step_of(clampi(3))];
-        Real st0[GB], q0[GB], st1[GB], q1[GB];
-        load_xs(s0.key, st0, q0);
-        load_xs(s1.key, st1, q1);
-        for (int i = 0; i < n; ++i) {
-            const Seg s4 = ws[step_of(clampi(i + 4))];
-            Real st2[GB], q2[GB];
-            load_xs(s2.key, st2, q2);
-            const Real len = s0.len;
-            const int ts = int(s0.key & ((1u << kSlotBits) - 1));
+        // one step: Eq. MOC_sol for every group of the batch and polar angle, polar-summed
+        // increments into the window's LDS tally
+        auto update = [&](const Seg &sg, const Real (&st)[GB], const Real (&q)[GB]) {
+            const Real len = sg.len;
+            const int ts = int(sg.key & ((1u << kSlotBits) - 1));
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
-                const Real sl = st0[j] * len;
+                const Real sl = st[j] * len;
                 Real acc = 0;
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
@@ -197,24 +189,59 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
                         F = one_minus_exp2_poly(sl * is[p]);
                     else
                         F = one_minus_exp<Real, MODE>(sl * is[p], lut);
-                    const Real d = (psi[p][j] - q0[j]) * F;
+                    const Real d = (psi[p][j] - q[j]) * F;
                     psi[p][j] -= d;
                     acc += c[p] * d;
                 }
                 if (len > Real(0)) atomicAdd(&tl[j * cap + ts], (double)acc);   // padding steps add nothing
             }
-            s0 = s1;
-            s1 = s2;
-            s2 = s3;
-            s3 = s4;
+        };
+        if constexpr (sizeof(Real) == 4) {
+            // software pipeline: segment entries four steps ahead and cross sections two
+            // steps ahead are in flight while the current step computes
+            Seg s0 = ws[step_of(0)], s1 = ws[step_of(clampi(1))], s2 = ws[step_of(clampi(2))],
+                s3 = ws[step_of(clampi(3))];
+            Real st0[GB], q0[GB], st1[GB], q1[GB];
+            load_xs(s0.key, st0, q0);
+            load_xs(s1.key, st1, q1);
+            for (int i = 0; i < n; ++i) {
+                const Seg s4 = ws[step_of(clampi(i + 4))];
+                Real st2[GB], q2[GB];
+                load_xs(s2.key, st2, q2);
+                update(s0, st0, q0);
+                s0 = s1;
+                s1 = s2;
+                s2 = s3;
+                s3 = s4;
 #pragma unroll
-            for (int j = 0; j < GB; ++j) {
-                st0[j] = st1[j];
-                q0[j] = q1[j];
-                st1[j] = st2[j];
-                q1[j] = q2[j];
+                for (int j = 0; j < GB; ++j) {
+                    st0[j] = st1[j];
+                    q0[j] = q1[j];
+                    st1[j] = st2[j];
+                    q1[j] = q2[j];
+                }
+            }
+        } else {
+            // FP64: a shallower pipeline (register budget): segment entries two steps and
+            // cross sections one step ahead
+            Seg s0 = ws[step_of(0)], s1 = ws[step_of(clampi(1))];
+            Real st0[GB], q0[GB];
+            load_xs(s0.key, st0, q0);
+            for (int i = 0; i < n; ++i) {
+                const Seg s2 = ws[step_of(clampi(i + 2))];
+                Real st1[GB], q1[GB];
+                load_xs(s1.key, st1, q1);
+                update(s0, st0, q0);
+                s0 = s1;
+                s1 = s2;
+#pragma unroll
+                for (int j = 0; j < GB; ++j) {
+                    st0[j] = st1[j];
+                    q0[j] = q1[j];
+                }
             }
         }
+        __syncthreads();
 #pragma unroll
         for (int u = 0; u < kMaxSlots / 64; ++u)
             if (u * 64 + lane < ns) tabl[u * 64 + lane] = tabv[u];
