@@ -11,6 +11,7 @@ updates per sweep.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +25,37 @@ HBM_PEAK_GBS = 8000.0
 N_CU, CLOCK_GHZ = 256, 2.4
 FP32_NONPACKED_TFLOPS = N_CU * 64 * 2 * CLOCK_GHZ / 1000.0      # FMA = 2 flops, no packed FP32
 FLOPS_PER_UPDATE = 7     # tau mul, 1 - e^-tau (1), psi - q, * F, psi -= d, tally fma (2)
+COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_f32_lattice51x51_counters.txt")
+
+
+def kernel_sources_hash():
+    """sha256 over the sources that decide what the sweep kernel reads and writes (its code,
+    the segment packing and the launch set-up); measured counters are only reported while
+    this hash matches the one recorded with them."""
+    csrc = os.path.join(ROOT, "paper_2607_01591_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.startswith("moc_") and name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, each scaled by what the same counter reads for a 1 GiB device copy; None when
+    there is no summary or the kernel sources changed since it was taken."""
+    if not os.path.exists(COUNTERS):
+        return None, "no counter summary"
+    kv = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None, "kernel changed since the counters were taken"
+    return float(kv["traffic_bytes_per_launch"]), os.path.relpath(COUNTERS, ROOT)
 
 
 def log(msg):
@@ -138,13 +170,16 @@ def main():
         f"k={r['k']:.6f}")
     value = U / (ms * 1e-3)
     achieved = U * FLOPS_PER_UPDATE / (sweep_ms * 1e-3) / 1e12
+    traffic, traffic_src = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_NONPACKED_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_NONPACKED_TFLOPS, "traffic": None,
-                "kernel": "k_sweep<float,3,7,POLY>", "kernel_ms": sweep_ms,
+                "unit": "TFLOP/s", "frac": achieved / FP32_NONPACKED_TFLOPS, "traffic": traffic,
+                "traffic_source": traffic_src, "kernel": "k_sweep<float,3,7,POLY>", "kernel_ms": sweep_ms,
                 "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": U}
     alg_bytes = algorithmic_bytes(info, "f32")
     hbm = {"algorithmic_bytes": alg_bytes, "achieved_GBs": alg_bytes / (sweep_ms * 1e-3) / 1e9,
            "frac_of_8TBs": alg_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if traffic is not None:
+        hbm["measured_GBs"] = traffic / (sweep_ms * 1e-3) / 1e9
     del s32
     torch.cuda.empty_cache()
 

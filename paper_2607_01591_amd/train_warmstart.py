@@ -38,7 +38,11 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--report", default=None)
     ap.add_argument("--weights", default=None, help="skip training, load these weights")
+    ap.add_argument("--data-budget", type=float, default=0.0,
+                    help="seconds: stop generating training problems once this is spent (0 = no limit)")
     a = ap.parse_args(argv)
+    if a.train > 1800 or a.val > 200:
+        ap.error("training seeds are 100000..101799 and validation seeds 101800..101999")
 
     import torch
     from . import cnn, moc
@@ -52,12 +56,15 @@ def main(argv=None):
     ws = WarmStart(solver, base, dev)
     log(f"mesh: {solver.R} regions, {solver.S} segments; image 128x128")
 
-    def make_data(seeds, tag):
+    def make_data(seeds, tag, budget=0.0):
         X = torch.empty((len(seeds), 128, 128, 32), dtype=torch.bfloat16, device=dev)
         T = torch.empty((len(seeds), 128, 128, C_OUT_PAD), dtype=torch.float32, device=dev)
         t0 = time.perf_counter()
         iters = []
         for i, sd in enumerate(seeds):
+            if budget > 0 and time.perf_counter() - t0 > budget:
+                log(f"{tag}: data budget spent after {i} problems")
+                return X[:i], T[:i], iters
             p = P.config(5, seed=sd)
             solver.set_materials(p)
             r = solver.solve(a.tol_data)
@@ -76,8 +83,10 @@ def main(argv=None):
                      "b": [st[f"b{i}"] for i in range(len(CHANNELS) - 1)]})
         log(f"loaded {a.weights}")
     else:
-        Xtr, Ttr, it_tr = make_data(list(range(100000, 100000 + a.train)), "train")
         Xva, Tva, _ = make_data(list(range(101800, 101800 + a.val)), "val")
+        Xtr, Ttr, it_tr = make_data(list(range(100000, 100000 + a.train)), "train", a.data_budget)
+        n_train = int(Xtr.shape[0])
+        report["n_train"], report["n_val"] = n_train, a.val
         report["data_iterations_mean"] = float(np.mean(it_tr))
         net = ws.net
         G = base.n_groups
@@ -86,9 +95,9 @@ def main(argv=None):
         hist = []
         for ep in range(a.epochs):
             lr = a.lr * (0.5 ** (ep // max(1, a.epochs // 4)))
-            perm = rng.permutation(a.train)
+            perm = rng.permutation(n_train)
             tl = []
-            for b0 in range(0, a.train - a.batch + 1, a.batch):
+            for b0 in range(0, n_train - a.batch + 1, a.batch):
                 idx = torch.as_tensor(perm[b0:b0 + a.batch], device=dev)
                 tl.append(net.train_step(Xtr[idx].contiguous(), Ttr[idx].contiguous(), G, lr=lr))
             vl = []
