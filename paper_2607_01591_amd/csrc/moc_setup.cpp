@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <functional>
 #include <climits>
 #include <thread>
@@ -355,20 +356,27 @@ static int locate_boundary_edge(const Mesh &m, int side, double px, double py) {
     side_line(m, side, nx, ny, c, tx, ty);
     const double pos = tx * px + ty * py;
     const auto &v = m.side_edges[side];
-    auto it = std::upper_bound(v.begin(), v.end(), std::make_pair(pos, INT32_MAX));
-    // candidates: the edge starting at or before pos, and its neighbour
-    for (int k = 0; k < 2; ++k) {
-        if (it == v.begin()) break;
-        --it;
-        const int h = it->second;
+    // the same tolerance that admitted the edges to this side: a mesh corner vertex may sit
+    // that far from the exact corner, where tracks through the corner enter
+    const double tol = 1e-9 * ((m.box[2] - m.box[0]) + (m.box[3] - m.box[1]));
+    const size_t ub = size_t(std::upper_bound(v.begin(), v.end(), std::make_pair(pos, INT32_MAX)) - v.begin());
+    // candidates: the edge starting at or before pos, the one before it, and the first edge
+    const size_t cand[3] = {ub >= 1 ? ub - 1 : v.size(), ub >= 2 ? ub - 2 : v.size(), 0};
+    for (size_t ci : cand) {
+        if (ci >= v.size()) continue;
+        const int h = v[ci].second;
         const int t = h / 3, e = h % 3;
         const double *p = &m.xy[2 * (size_t)m.tri[3 * (size_t)t + e]];
         const double *q = &m.xy[2 * (size_t)m.tri[3 * (size_t)t + (e + 1) % 3]];
         const double a = tx * p[0] + ty * p[1], b = tx * q[0] + ty * q[1];
-        const double lo = std::min(a, b), hi = std::max(a, b), tol = 1e-12 * (1.0 + std::fabs(pos));
+        const double lo = std::min(a, b), hi = std::max(a, b);
         if (pos >= lo - tol && pos <= hi + tol) return h;
     }
-    throw Error(MOC_EINVAL, "tracking: entry point not on any boundary edge (mesh does not cover the domain)");
+    char msg[256];
+    std::snprintf(msg, sizeof msg,
+                  "tracking: entry point (%.17g, %.17g) not on any boundary edge of side %d "
+                  "(mesh does not cover the domain; %zu edges on that side)", px, py, side, v.size());
+    throw Error(MOC_EINVAL, msg);
 }
 
 int64_t trace_track(const Mesh &m, const Quadrature &q, const Tracks &tk, int track, SegmentSink &sink) {

@@ -81,6 +81,16 @@ def test_hexagon_volume_close_to_area():
     assert abs(V.sum() - area) < 1e-3 * area
 
 
+def test_tracks_through_hexagon_corners():
+    """In the 271-pin assembly some tracks enter exactly at a corner of the hexagon,
+    where the mesh's corner vertex sits about 4e-11 cm from the exact corner; such a
+    track must still find its entry edge and be traced over the domain's full area."""
+    prob = P.config(4)
+    s = moc.Solver(prob, device=-1)
+    area = 2 * np.sqrt(3) * prob.hex_apothem ** 2
+    assert abs(s.volumes().sum() - area) < 1e-3 * area
+
+
 def _expect_einval(prob, **kw):
     with pytest.raises(moc.MocError) as e:
         moc.Solver(prob, device=-1, **kw)
