@@ -65,6 +65,13 @@ typedef struct {
     int gs_boundary;       /* 1: boundary Gauss-Seidel inside a sweep */
     int gs_energy;         /* 1: energy Gauss-Seidel inside a power iteration */
     double max_gap;        /* largest uncovered gap found while tracking (diagnostic) */
+    /* coarse mesh for CMFD (off when n_cells == 0): surface partial currents */
+    int n_cells;
+    int *region_cell;      /* [R] coarse cell of each region */
+    int64_t *nbr_off;      /* [n_cells + 1] neighbour slots of each cell */
+    int *nbr;              /* neighbour cell of each slot; -1 = the domain boundary */
+    double *jpart;         /* [slots][G] partial current leaving the cell through the slot */
+    double *jin_bnd;       /* [n_cells][G] partial current entering the cell from outside */
     char err[256];
 } orc_t;
 
@@ -487,6 +494,7 @@ void orc_destroy(orc_t *o) {
     free(o->t_angle); free(o->t_x0); free(o->t_y0); free(o->t_x1); free(o->t_y1); free(o->t_len);
     free(o->t_off); free(o->s_reg); free(o->s_len); free(o->link); free(o->V);
     free(o->psi); free(o->psi_next); free(o->psi_exit); free(o->qext);
+    free(o->region_cell); free(o->nbr_off); free(o->nbr); free(o->jpart); free(o->jin_bnd);
     free(o);
 }
 
@@ -550,8 +558,15 @@ void orc_set_external_source(orc_t *o, const double *q) {
 /* Pinned by: pure-absorber attenuation, per-sweep neutron balance, infinite-medium */
 /* fixed point, exact-integral agreement on a tiny input.                          */
 /* ------------------------------------------------------------------------------ */
+static int64_t coarse_slot(const orc_t *o, int i, int j) {
+    for (int64_t s = o->nbr_off[i]; s < o->nbr_off[i + 1]; s++)
+        if (o->nbr[s] == j) return s;
+    return -1;   /* cannot happen: the adjacency was built from these same segments */
+}
+
 static void sweep_group(orc_t *o, int g, const double *qhat_g /* [R] */, double *T_g /* [R] */) {
     int P = o->P, G = o->G;
+    const int *cell = o->region_cell;
     for (int t = 0; t < o->T; t++) {
         int a = o->t_angle[t];
         for (int sense = 0; sense < 2; sense++) {
@@ -560,15 +575,25 @@ static void sweep_group(orc_t *o, int g, const double *qhat_g /* [R] */, double 
                 size_t idx = (((size_t)t * 2 + sense) * P + p) * G + g;
                 double psi = o->psi[idx];
                 int64_t n = o->t_off[t + 1] - o->t_off[t];
+                int cprev = -1;
                 for (int64_t i = 0; i < n; i++) {
                     int64_t k = sense ? o->t_off[t + 1] - 1 - i : o->t_off[t] + i;
                     int r = o->s_reg[k];
+                    if (o->n_cells) {
+                        /* a coarse-cell boundary crossed with the current psi: the same   */
+                        /* weight c turns angular flux into current as Delta into tally    */
+                        int ci = cell[r];
+                        if (i == 0) o->jin_bnd[(size_t)ci * G + g] += c * psi;
+                        else if (ci != cprev) o->jpart[coarse_slot(o, cprev, ci) * G + g] += c * psi;
+                        cprev = ci;
+                    }
                     double st = o->sigt[o->region_material[r] * G + g];
                     double tau = st * o->s_len[k] / o->sinp[p];
                     double delta = (psi - qhat_g[r]) * (-expm1(-tau));
                     psi -= delta;
                     T_g[r] += c * delta;
                 }
+                if (o->n_cells && n > 0) o->jpart[coarse_slot(o, cprev, -1) * G + g] += c * psi;
                 o->psi_exit[idx] = psi;
                 int dst = o->link[2 * t + sense];
                 if (dst >= 0) {
@@ -612,6 +637,10 @@ static void swap_psi(orc_t *o) {
 void orc_sweep(orc_t *o, const double *src, double *phi_out, double *tally_out) {
     int R = o->R, G = o->G;
     double *q = xmalloc(sizeof(double) * R), *T = xmalloc(sizeof(double) * R);
+    if (o->n_cells) {
+        memset(o->jpart, 0, sizeof(double) * o->nbr_off[o->n_cells] * G);
+        memset(o->jin_bnd, 0, sizeof(double) * (size_t)o->n_cells * G);
+    }
     for (int g = 0; g < G; g++) {
         for (int r = 0; r < R; r++) { q[r] = src[(size_t)r * G + g] / (4.0 * ORC_PI * sigt_of(o, r, g)); T[r] = 0.0; }
         sweep_group(o, g, q, T);
@@ -709,4 +738,68 @@ int orc_solve(orc_t *o, double tol, int max_iter, double *phi /* [R][G] in/out *
     *dk_out = dk;
     free(phin); free(q); free(T);
     return conv ? 0 : 1;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Coarse mesh for CMFD (Sec. 2.2, Alg. MOCHFEM_CMFD: MOC supplies the currents on  */
+/* the radial coarse-cell surfaces). Each region belongs to one coarse cell. The    */
+/* surfaces are the ordered cell pairs that some track actually crosses between two */
+/* consecutive segments, plus (cell, boundary) where a track enters or leaves the   */
+/* domain; every crossing is tallied during the sweep with the flux tally's weight. */
+/* Pinned by: per-cell balance of tallies against currents, zero net current across */
+/* symmetry planes, and the CMFD fixed point equalling the plain power iteration's. */
+/* ------------------------------------------------------------------------------ */
+typedef struct { int i, j; } pair_t;
+static int cmp_pair(const void *a, const void *b) {
+    const pair_t *x = a, *y = b;
+    if (x->i != y->i) return x->i < y->i ? -1 : 1;
+    return (x->j > y->j) - (x->j < y->j);
+}
+
+int orc_set_coarse(orc_t *o, int n_cells, const int *region_cell) {
+    free(o->region_cell); free(o->nbr_off); free(o->nbr); free(o->jpart); free(o->jin_bnd);
+    o->region_cell = NULL; o->nbr_off = NULL; o->nbr = NULL; o->jpart = NULL; o->jin_bnd = NULL;
+    o->n_cells = 0;
+    if (n_cells <= 0) return 0;
+    for (int r = 0; r < o->R; r++)
+        if (region_cell[r] < 0 || region_cell[r] >= n_cells) return 1;
+    o->region_cell = xmalloc(sizeof(int) * o->R);
+    memcpy(o->region_cell, region_cell, sizeof(int) * o->R);
+    size_t cap = 1024, np = 0;
+    pair_t *pr = xmalloc(sizeof(pair_t) * cap);
+    for (int t = 0; t < o->T; t++) {
+        int64_t k0 = o->t_off[t], k1 = o->t_off[t + 1];
+        if (k1 == k0) continue;
+        for (int64_t k = k0; k <= k1; k++) {
+            int ci = k == k0 ? -1 : region_cell[o->s_reg[k - 1]];
+            int cj = k == k1 ? -1 : region_cell[o->s_reg[k]];
+            if (ci == cj) continue;
+            if (np + 2 > cap) { cap *= 2; pr = realloc(pr, sizeof(pair_t) * cap); }
+            /* both orientations: each surface is listed under both of its cells */
+            if (ci >= 0) pr[np++] = (pair_t){ci, cj};
+            if (cj >= 0) pr[np++] = (pair_t){cj, ci};
+        }
+    }
+    qsort(pr, np, sizeof(pair_t), cmp_pair);
+    size_t nu = 0;
+    for (size_t i = 0; i < np; i++)
+        if (nu == 0 || cmp_pair(&pr[i], &pr[nu - 1]) != 0) pr[nu++] = pr[i];
+    o->n_cells = n_cells;
+    o->nbr_off = xmalloc(sizeof(int64_t) * (n_cells + 1));
+    o->nbr = xmalloc(sizeof(int) * (nu ? nu : 1));
+    for (size_t i = 0; i < nu; i++) { o->nbr[i] = pr[i].j; o->nbr_off[pr[i].i + 1]++; }
+    for (int c = 0; c < n_cells; c++) o->nbr_off[c + 1] += o->nbr_off[c];
+    free(pr);
+    o->jpart = xmalloc(sizeof(double) * (nu ? nu : 1) * o->G);
+    o->jin_bnd = xmalloc(sizeof(double) * (size_t)n_cells * o->G);
+    return 0;
+}
+int64_t orc_coarse_slots(const orc_t *o) { return o->n_cells ? o->nbr_off[o->n_cells] : 0; }
+void orc_coarse_adjacency(const orc_t *o, int64_t *off, int *nbr) {
+    memcpy(off, o->nbr_off, sizeof(int64_t) * (o->n_cells + 1));
+    memcpy(nbr, o->nbr, sizeof(int) * o->nbr_off[o->n_cells]);
+}
+void orc_currents(const orc_t *o, double *jpart, double *jin_bnd) {
+    memcpy(jpart, o->jpart, sizeof(double) * o->nbr_off[o->n_cells] * o->G);
+    memcpy(jin_bnd, o->jin_bnd, sizeof(double) * (size_t)o->n_cells * o->G);
 }

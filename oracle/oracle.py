@@ -56,6 +56,12 @@ def lib():
         L.orc_set_options.argtypes = [C.c_void_p, i, i]
         L.orc_set_external_source.argtypes = [C.c_void_p, P(d)]
         L.orc_sweep.argtypes = [C.c_void_p, P(d), P(d), P(d)]
+        L.orc_set_coarse.restype = i
+        L.orc_set_coarse.argtypes = [C.c_void_p, i, P(i)]
+        L.orc_coarse_slots.restype = i64
+        L.orc_coarse_slots.argtypes = [C.c_void_p]
+        L.orc_coarse_adjacency.argtypes = [C.c_void_p, P(i64), P(i)]
+        L.orc_currents.argtypes = [C.c_void_p, P(d), P(d)]
         L.orc_solve.restype = i
         L.orc_solve.argtypes = [C.c_void_p, d, i, P(d), P(d), P(i), P(d), P(d), i]
         _lib = L
@@ -201,6 +207,32 @@ class Oracle:
         else:
             self._qext = _f64(q).reshape(self.R, self.G)
             lib().orc_set_external_source(self._h, _p(self._qext, C.c_double))
+
+    # --- coarse mesh (CMFD currents) ---------------------------------------------------
+    def set_coarse(self, n_cells, region_cell):
+        """Assign every region to a coarse cell; later sweeps tally the partial currents
+        across the coarse-cell surfaces that the tracks cross."""
+        self._cell = _i32(region_cell)
+        self.n_cells = int(n_cells)
+        if lib().orc_set_coarse(self._h, self.n_cells, _p(self._cell, C.c_int)):
+            raise ValueError("oracle: region_cell out of range")
+
+    def coarse_adjacency(self):
+        """(off [C+1], nbr [slots]): the neighbour cells of each cell, -1 = boundary."""
+        n = int(lib().orc_coarse_slots(self._h))
+        off = np.zeros(self.n_cells + 1, np.int64)
+        nbr = np.zeros(max(n, 1), np.int32)
+        lib().orc_coarse_adjacency(self._h, _p(off, C.c_int64), _p(nbr, C.c_int))
+        return off, nbr[:n]
+
+    def currents(self):
+        """Partial currents of the last sweep: jpart [slots, G] leaving each cell through
+        each slot, jin [C, G] entering each cell from outside the domain."""
+        n = int(lib().orc_coarse_slots(self._h))
+        jp = np.zeros((max(n, 1), self.G))
+        jin = np.zeros((self.n_cells, self.G))
+        lib().orc_currents(self._h, _p(jp, C.c_double), _p(jin, C.c_double))
+        return jp[:n], jin
 
     # --- compute -------------------------------------------------------------------
     def sweep(self, src, return_tally=False):

@@ -508,3 +508,22 @@ def box_problem(W: float = 1.0, H: float = 1.0, nx: int = 2, ny: int = 2, *, G: 
     return Problem(name, np.ascontiguousarray(xy), tri, tri_region, R,
                    np.zeros(R, np.int32), DOMAIN_BOX, (0.0, 0.0, W, H), 0.0,
                    np.asarray(bc, np.int32), st, ss, nsf, ch, n_azim, n_polar, spacing)
+
+
+def coarse_cells(p: Problem, nx: int, ny: int):
+    """Coarse mesh for CMFD: an nx x ny Cartesian grid over the bounding box; each region
+    goes to the cell holding its area-weighted centroid, and cells holding no region are
+    dropped. For the square lattices with nx, ny = pins per side these are the pin
+    cells. Returns (n_cells, region_cell int32 [R])."""
+    a = tri_areas(p.xy, p.tri)
+    cen = p.xy[p.tri].mean(axis=1)
+    R = p.n_regions
+    area = np.bincount(p.tri_region, weights=a, minlength=R)
+    cx = np.bincount(p.tri_region, weights=a * cen[:, 0], minlength=R) / area
+    cy = np.bincount(p.tri_region, weights=a * cen[:, 1], minlength=R) / area
+    x0, y0, x1, y1 = p.box
+    ix = np.clip(((cx - x0) / (x1 - x0) * nx).astype(np.int64), 0, nx - 1)
+    iy = np.clip(((cy - y0) / (y1 - y0) * ny).astype(np.int64), 0, ny - 1)
+    raw = iy * nx + ix
+    used, region_cell = np.unique(raw, return_inverse=True)
+    return int(len(used)), region_cell.astype(np.int32)
