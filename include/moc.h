@@ -151,6 +151,29 @@ typedef struct {
     double sweep_ms_max;  /* longest launch */
 } moc_profile;
 
+/* Convergence controls of the CMFD coarse solve (moc_set_coarse_mesh). Zero fields take
+ * the defaults. */
+typedef struct {
+    double tol;          /* relative change of k and of the coarse flux that ends the coarse
+                            power iteration; the BiCGSTAB solves stop at tol / 10 relative
+                            residual (default 1e-5) */
+    double shift;        /* Wielandt shift k_s = k (1 + shift), applied once k has settled
+                            (default 0.02; negative: never shift) */
+    int32_t max_outer;   /* coarse power iterations per CMFD step (default 20) */
+    int32_t max_inner;   /* BiCGSTAB iterations per coarse linear solve (default 200) */
+} moc_cmfd_options;
+
+/* Coarse mesh state (moc_get_coarse_info); all zero when no coarse mesh is set. */
+typedef struct {
+    int32_t n_cells;
+    int32_t n_surfaces;    /* coarse surfaces crossed by some track, boundary ones included */
+    int64_t n_crossings;   /* crossing entries in the packed segment stream */
+    double setup_ms;       /* host time of moc_set_coarse_mesh */
+    int32_t last_outer;    /* coarse power iterations of the last CMFD step */
+    int32_t last_inner;    /* BiCGSTAB iterations of the last CMFD step (all solves) */
+    double last_k;         /* coarse eigenvalue of the last CMFD step */
+} moc_coarse_info;
+
 /* Build a solver context (host setup in C++: mesh half-edge structure, cyclic track
  * laydown, ray tracing by mesh walk, segment merging, boundary links, track volumes,
  * device packing). All inputs are copied. Errors: MOC_EINVAL (inconsistent topology,
@@ -217,6 +240,33 @@ int moc_set_external_source(moc_ctx *ctx, const double *q_dev);
  * host [R] (user order); xs host arrays as in moc_create. Clears any external source and
  * pending initial guess. Errors: MOC_EINVAL (sizes differ, Sigma_t <= 0, bad material). */
 int moc_set_materials(moc_ctx *ctx, const int32_t *region_material, const moc_xs *xs);
+
+/* CMFD acceleration (Sec. 2.2, Alg. MOCHFEM_CMFD, its radial part): region_cell host
+ * int32 [R] (user region order) assigns every region to one of n_cells coarse cells;
+ * every cell must hold at least one region. From then on each sweep also tallies the net
+ * current across every coarse surface a track crosses (the packed segment stream is
+ * rebuilt with a crossing entry at every change of coarse cell and at both ends of every
+ * track), and in eigenvalue mode every power iteration is followed by a CMFD step on the
+ * device: flux-volume homogenisation onto the cells, diffusion couplings Dhat from the
+ * cell geometry and Dtilde from the sweep's currents (Dhat = 0 on the domain boundary),
+ * the coarse eigenproblem, and rescaling of the fine flux and of the incoming boundary
+ * fluxes by each cell's ratio of new to homogenised flux; k comes from the coarse
+ * problem. The converged answer is that of the plain power iteration. Fixed-source mode
+ * is not accelerated. opts may be NULL (defaults). n_cells <= 0 or region_cell NULL
+ * removes the coarse mesh. Host-only contexts set up the surfaces and packing only.
+ * Errors: MOC_EINVAL (cell index out of range, an empty cell, exp_mode other than 0 with
+ * FP32, too many regions plus surfaces for the segment key). */
+int moc_set_coarse_mesh(moc_ctx *ctx, int32_t n_cells, const int32_t *region_cell,
+                        const moc_cmfd_options *opts);
+int moc_get_coarse_info(moc_ctx *ctx, moc_coarse_info *info);
+
+/* Net currents of the last sweep across the coarse surfaces: cells host int32
+ * [n_surfaces][2] receives each surface's cells (a, b), a < b, or (a, -1) for the part of
+ * cell a's boundary on the domain boundary; current host FP64 [n_surfaces][G] the net
+ * current from a to b (out of the domain for b = -1), integrated over the surface, with
+ * the same weights as the flux tally. Either pointer may be NULL; current needs a device
+ * context. Errors: MOC_ESTATE without a coarse mesh. */
+int moc_get_surface_currents(moc_ctx *ctx, int32_t *cells, double *current);
 
 /* Region containing each of n points (host xy [n][2]; host out [n] user region ids, -1
  * outside the mesh); a point on a shared edge gets one of the adjacent regions. */

@@ -54,8 +54,17 @@ struct moc_ctx {
     double *guess_phi = nullptr;   // internal [R][G]
     double *exit_canon = nullptr;  // user buffer
     double *host_scal = nullptr;   // pinned
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, size_t>> allocs;
     std::string err;
+    // packing parameters kept for re-packing (coarse mesh on/off)
+    PackInput pin;
+    int64_t crossings = 0;
+    // CMFD coarse mesh
+    bool cmfd = false;
+    CoarseSurfaces cs;
+    DevCoarse cd;
+    int64_t tally_rows = 0, xsq_rows = 0;
+    double coarse_setup_ms = 0;
     // sweep profiling
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_pool;
@@ -68,9 +77,20 @@ struct moc_ctx {
         const size_t bytes = std::max<size_t>(n * sizeof(T), 16);
         hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess) throw Error(MOC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-        allocs.push_back(p);
+        allocs.push_back({p, bytes});
         device_bytes += (int64_t)bytes;
         return (T *)p;
+    }
+    void dfree(void *p) {
+        if (!p) return;
+        for (size_t i = 0; i < allocs.size(); ++i)
+            if (allocs[i].first == p) {
+                if (stream) hipStreamSynchronize(stream);
+                hipFree(p);
+                device_bytes -= (int64_t)allocs[i].second;
+                allocs.erase(allocs.begin() + (long)i);
+                return;
+            }
     }
     template <typename T> T *upload(const std::vector<T> &v) {
         if (host_only) return nullptr;
@@ -89,7 +109,7 @@ struct moc_ctx {
             hipEventDestroy(e.first);
             hipEventDestroy(e.second);
         }
-        for (void *p : allocs) hipFree(p);
+        for (auto &a : allocs) hipFree(a.first);
         if (host_scal) hipHostFree(host_scal);
         if (stream) hipStreamDestroy(stream);
     }
@@ -142,6 +162,46 @@ struct DumpSink : SegmentSink {
 };
 
 }  // namespace
+
+// Trace, cut into tally windows and pack every batch (two deterministic passes), then load
+// the segment stream and the window tables on the device, replacing any previous ones.
+// With `coarse`, the stream carries coarse-surface crossing entries.
+static void pack_and_upload(moc_ctx *c, const CoarseSurfaces *coarse, PackOutput &pk) {
+    DevProblem &d = c->d;
+    PackInput pin = c->pin;
+    pin.coarse = coarse;
+    for (void *p : {d.segs, (void *)d.batch_win, (void *)d.win_entry_off, (void *)d.win_nsteps, (void *)d.win_tab_off,
+                    (void *)d.win_nslots, (void *)d.win_tab, (void *)d.entry_region})
+        c->dfree(p);
+    if (d.precision == MOC_PREC_F64) {
+        std::vector<SegD> segs;
+        pack_segments_f64(pin, pk, segs);
+        d.segs = c->upload(segs);
+        if (c->host_only) c->host_segs_f64.swap(segs);
+    } else {
+        std::vector<SegF> segs;
+        pack_segments_f32(pin, pk, segs);
+        d.segs = c->upload(segs);
+        if (c->host_only) c->host_segs_f32.swap(segs);
+    }
+    c->S = pk.S;
+    c->crossings = pk.crossings;
+    c->padded_steps = pk.entries;
+    c->window_len = pin.window_len;
+    c->n_windows = (int64_t)pk.win_nsteps.size();
+    c->n_slots_total = (int64_t)pk.tab.size();
+    int max_slots = 1;
+    for (int v : pk.win_nslots) max_slots = std::max(max_slots, v);
+    d.max_slots = max_slots;
+    d.batch_win = c->upload(pk.batch_win);
+    d.win_entry_off = c->upload(pk.win_entry_off);
+    d.win_nsteps = c->upload(pk.win_nsteps);
+    d.win_tab_off = c->upload(pk.win_tab_off);
+    d.win_nslots = c->upload(pk.win_nslots);
+    d.win_tab = c->upload(pk.tab);
+    d.entry_region = c->upload(pk.entry_region);
+    if (c->host_only) c->host_pack = pk;
+}
 
 static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const moc_xs *xs, const moc_options *opt,
                         moc_ctx *c) {
@@ -265,23 +325,10 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     }
     pin.batch_first.assign(d.nb + 1, T);
     for (int t = T - 1; t >= 0; --t) pin.batch_first[batch_of_track[t]] = t;
+    c->pin = pin;
+    d.cap = pin.cap;
     PackOutput pk;
-    if (f64) {
-        std::vector<SegD> segs;
-        pack_segments_f64(pin, pk, segs);
-        d.segs = c->upload(segs);
-        if (c->host_only) c->host_segs_f64.swap(segs);
-    } else {
-        std::vector<SegF> segs;
-        pack_segments_f32(pin, pk, segs);
-        d.segs = c->upload(segs);
-        if (c->host_only) c->host_segs_f32.swap(segs);
-    }
-    c->S = pk.S;
-    c->padded_steps = pk.entries;
-    c->window_len = pin.window_len;
-    c->n_windows = (int64_t)pk.win_nsteps.size();
-    c->n_slots_total = (int64_t)pk.tab.size();
+    pack_and_upload(c, nullptr, pk);
     std::vector<double> &V_internal = pk.V;
     for (int r = 0; r < R; ++r)
         if (!(V_internal[r] > 0))
@@ -289,22 +336,8 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
                                         " is crossed by no track (refine the track spacing)");
     c->V_user.assign(R, 0.0);
     for (int r = 0; r < R; ++r) c->V_user[c->user_of_internal[r]] = V_internal[r];
-    d.cap = pin.cap;
-    int max_slots = 1;
-    for (int v : pk.win_nslots) max_slots = std::max(max_slots, v);
-    d.max_slots = max_slots;
-    d.batch_win = c->upload(pk.batch_win);
-    d.win_entry_off = c->upload(pk.win_entry_off);
-    d.win_nsteps = c->upload(pk.win_nsteps);
-    d.win_tab_off = c->upload(pk.win_tab_off);
-    d.win_nslots = c->upload(pk.win_nslots);
-    d.win_tab = c->upload(pk.tab);
     d.batch_angle = c->upload(batch_angle);
-    d.entry_region = c->upload(pk.entry_region);
-    if (c->host_only) {
-        c->host_pack = pk;
-        c->host_batch_angle = batch_angle;
-    }
+    if (c->host_only) c->host_batch_angle = batch_angle;
     d.slot_of_canon = c->upload(c->slot_of_canon);
     d.canon_of_slot = c->upload(canon_of_slot);
 
@@ -346,6 +379,7 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
         d.xsq = c->upload(xq);
     }
     d.tally = c->dalloc<double>((size_t)R * d.Gp);
+    c->tally_rows = c->xsq_rows = R;
     d.phi[0] = c->dalloc<double>((size_t)R * G);
     d.phi[1] = c->dalloc<double>((size_t)R * G);
     const size_t npsi = (size_t)2 * P * d.Gp * d.nslots;
@@ -394,7 +428,7 @@ static void need_device(const moc_ctx *c) {
 
 static void sweep_impl(moc_ctx *c, hipStream_t s) {
     DevProblem &d = c->d;
-    launch_fill_f64(d.tally, (int64_t)d.R * d.Gp, 0.0, s);
+    launch_fill_f64(d.tally, c->tally_rows * d.Gp, 0.0, s);
     SweepArgs a{};
     a.segs = d.segs;
     a.batch_win = d.batch_win;
@@ -419,6 +453,7 @@ static void sweep_impl(moc_ctx *c, hipStream_t s) {
     a.nslots = d.nslots;
     a.Gp = d.Gp;
     a.G = d.G;
+    a.n_real = d.R;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (c->profiling) {
         if (c->prof_pool.empty()) {
@@ -430,7 +465,7 @@ static void sweep_impl(moc_ctx *c, hipStream_t s) {
         }
         HIP_OK(hipEventRecord(ev.first, s));
     }
-    launch_sweep(a, d.precision, d.exp_mode, d.nb, d.P, d.gb, d.n_gb, s);
+    launch_sweep(a, d.precision, d.exp_mode, c->cmfd, d.nb, d.P, d.gb, d.n_gb, s);
     if (c->profiling) {
         HIP_OK(hipEventRecord(ev.second, s));
         c->prof_pending.push_back(ev);
@@ -538,7 +573,14 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         sweep_impl(c, s);
         ++sweeps;
         launch_finalize(d, phi_new, nullptr, d.partials, s);
-        launch_eigen_update(d, d.partials, eigen ? 1 : 2, s);
+        if (c->cmfd && eigen) {
+            // CMFD: coarse eigenvalue and rescaled fine flux / incoming boundary flux
+            launch_cmfd(d, c->cd, phi_new, d.psi[c->cur_psi], s);
+            launch_fission_partials(d, phi_new, d.partials, s);
+            launch_eigen_update(d, d.partials, 3, s);
+        } else {
+            launch_eigen_update(d, d.partials, eigen ? 1 : 2, s);
+        }
         launch_norm_residual(d, phi_new, phi_old, d.partials, s);
         if (eigen) launch_scale_real(d.psi[c->cur_psi], npsi, d.precision, d.scal + kScalF, s);
         c->cur_phi = 1 - c->cur_phi;
@@ -706,6 +748,256 @@ int moc_set_materials(moc_ctx *c, const int32_t *region_material, const moc_xs *
         c->fixed_source = false;
         d.qext = nullptr;
         c->guess_pending = false;
+    });
+}
+
+static void free_coarse(moc_ctx *c) {
+    DevCoarse &cd = c->cd;
+    for (void *p : {(void *)cd.cell_of, (void *)cd.cell_reg_off, (void *)cd.cell_reg, (void *)cd.entry_cell,
+                    (void *)cd.adj_off, (void *)cd.adj_surf, (void *)cd.adj_nbr, (void *)cd.adj_sign, (void *)cd.adj_L,
+                    (void *)cd.adj_h, (void *)cd.adj_hn, (void *)cd.hsum, (void *)cd.Bs, (void *)cd.Binv, (void *)cd.Aoff,
+                    (void *)cd.phih, (void *)cd.Dc, (void *)cd.Ldiag, (void *)cd.fchi, (void *)cd.fnsf, (void *)cd.vec,
+                    (void *)cd.ratio, (void *)cd.stats, (void *)cd.piv})
+        c->dfree(p);
+    cd = DevCoarse();
+}
+
+// Coarse mesh for CMFD: surfaces from the tracks, a re-packed segment stream with crossing
+// entries, one tally row (and a Sigma_t = 1e30, qhat = 0 row) per surface, the coarse
+// geometry for the diffusion couplings and the solver's device arrays.
+static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell, const moc_cmfd_options *opts) {
+    const auto t0 = std::chrono::steady_clock::now();
+    DevProblem &d = c->d;
+    const int R = d.R, G = d.G;
+    if (!c->host_only) {
+        HIP_OK(hipSetDevice(c->device));
+        HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    if (n_cells <= 0 || !region_cell) {
+        if (c->cmfd) {
+            PackOutput pk;
+            pack_and_upload(c, nullptr, pk);
+        }
+        c->cmfd = false;
+        free_coarse(c);
+        c->cs = CoarseSurfaces();
+        return;
+    }
+    moc_cmfd_options o{};
+    if (opts) o = *opts;
+    if (o.tol < 0 || o.max_outer < 0 || o.max_inner < 0) throw Error(MOC_EINVAL, "coarse mesh: negative option");
+    if (d.precision == MOC_PREC_F32 && d.exp_mode != MOC_EXP_POLY)
+        throw Error(MOC_EINVAL, "coarse mesh: CMFD currents need the default exponential (exp_mode 0)");
+    std::vector<int64_t> count(n_cells, 0);
+    for (int u = 0; u < R; ++u) {
+        if (region_cell[u] < 0 || region_cell[u] >= n_cells) throw Error(MOC_EINVAL, "coarse mesh: cell index out of range");
+        ++count[region_cell[u]];
+    }
+    for (int k = 0; k < n_cells; ++k)
+        if (count[k] == 0) throw Error(MOC_EINVAL, "coarse mesh: cell " + std::to_string(k) + " holds no region");
+    free_coarse(c);
+    CoarseSurfaces &cs = c->cs;
+    cs = CoarseSurfaces();
+    cs.n_cells = n_cells;
+    cs.cell_of.resize(R);
+    for (int r = 0; r < R; ++r) cs.cell_of[r] = region_cell[c->user_of_internal[r]];
+    find_coarse_surfaces(c->mesh, c->quad, c->tracks, c->internal_of_user.data(), c->n_threads, cs);
+    const int Ns = (int)cs.a.size();
+    if ((int64_t)R + Ns >= (int64_t(1) << (32 - kSlotBits)))
+        throw Error(MOC_EINVAL, "coarse mesh: too many regions plus surfaces for the packed segment key");
+    PackOutput pk;
+    pack_and_upload(c, &cs, pk);
+
+    // tally and (Sigma_t, qhat) rows of the surfaces
+    const int64_t rows = (int64_t)R + Ns;
+    const size_t rs = d.precision == MOC_PREC_F64 ? sizeof(double) : sizeof(float);
+    if (!c->host_only) {
+        if (rows > c->xsq_rows) {
+            void *nx = c->dalloc<char>((size_t)rows * d.Gp * 2 * rs);
+            HIP_OK(hipMemcpy(nx, d.xsq, (size_t)R * d.Gp * 2 * rs, hipMemcpyDeviceToDevice));
+            c->dfree(d.xsq);
+            d.xsq = nx;
+            c->xsq_rows = rows;
+        }
+        if (d.precision == MOC_PREC_F64) {
+            std::vector<double> xq((size_t)Ns * d.Gp * 2, 0.0);
+            for (size_t i = 0; i < xq.size(); i += 2) xq[i] = 1e30;
+            if (Ns) HIP_OK(hipMemcpy((double *)d.xsq + (size_t)R * d.Gp * 2, xq.data(), xq.size() * rs, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> xq((size_t)Ns * d.Gp * 2, 0.0f);
+            for (size_t i = 0; i < xq.size(); i += 2) xq[i] = 1e30f;
+            if (Ns) HIP_OK(hipMemcpy((float *)d.xsq + (size_t)R * d.Gp * 2, xq.data(), xq.size() * rs, hipMemcpyHostToDevice));
+        }
+        if (rows > c->tally_rows) {
+            c->dfree(d.tally);
+            d.tally = c->dalloc<double>((size_t)rows * d.Gp);
+            c->tally_rows = rows;
+        }
+    }
+
+    // geometry: cell centroids (area weighted), shared edge length and midpoint per surface
+    const Mesh &m = c->mesh;
+    std::vector<double> carea(n_cells, 0.0), cx(n_cells, 0.0), cy(n_cells, 0.0);
+    for (int t = 0; t < m.nt; ++t) {
+        const int *v = &m.tri[3 * (size_t)t];
+        const double *a = &m.xy[2 * (size_t)v[0]], *b = &m.xy[2 * (size_t)v[1]], *q = &m.xy[2 * (size_t)v[2]];
+        const double ar = 0.5 * std::fabs((b[0] - a[0]) * (q[1] - a[1]) - (b[1] - a[1]) * (q[0] - a[0]));
+        const int k = region_cell[m.tri_region[t]];
+        carea[k] += ar;
+        cx[k] += ar * (a[0] + b[0] + q[0]) / 3.0;
+        cy[k] += ar * (a[1] + b[1] + q[1]) / 3.0;
+    }
+    for (int k = 0; k < n_cells; ++k) {
+        cx[k] /= carea[k];
+        cy[k] /= carea[k];
+    }
+    std::vector<double> sL(Ns, 0.0), smx(Ns, 0.0), smy(Ns, 0.0);
+    for (size_t h = 0; h < m.twin.size(); ++h) {
+        const int tw = m.twin[h];
+        if (tw < 0 || (int)h > tw) continue;
+        const int ka = region_cell[m.tri_region[h / 3]], kb = region_cell[m.tri_region[tw / 3]];
+        if (ka == kb) continue;
+        const int id = cs.find(std::min(ka, kb), std::max(ka, kb));
+        if (id < 0) continue;   // an edge no track crosses
+        const int e = (int)(h % 3);
+        const double *p = &m.xy[2 * (size_t)m.tri[h]];
+        const double *q = &m.xy[2 * (size_t)m.tri[h - e + (e + 1) % 3]];
+        const double len = std::hypot(q[0] - p[0], q[1] - p[1]);
+        sL[id] += len;
+        smx[id] += len * 0.5 * (p[0] + q[0]);
+        smy[id] += len * 0.5 * (p[1] + q[1]);
+    }
+    // adjacency slots per cell
+    std::vector<std::vector<int>> slots(n_cells);
+    for (int sf = 0; sf < Ns; ++sf) {
+        slots[cs.a[sf]].push_back(2 * sf);
+        if (cs.b[sf] >= 0) slots[cs.b[sf]].push_back(2 * sf + 1);
+    }
+    std::vector<int64_t> adj_off(n_cells + 1, 0);
+    std::vector<int> adj_surf, adj_nbr;
+    std::vector<double> adj_sign, adj_L, adj_h, adj_hn;
+    for (int k = 0; k < n_cells; ++k) {
+        for (int code : slots[k]) {
+            const int sf = code / 2;
+            const bool is_a = (code & 1) == 0;
+            const int nb = is_a ? cs.b[sf] : cs.a[sf];
+            double L = 0, hs = 0, hn = 0;
+            if (nb >= 0 && sL[sf] > 0) {
+                L = sL[sf];
+                const double mx = smx[sf] / L, my = smy[sf] / L;
+                hs = std::hypot(cx[k] - mx, cy[k] - my);
+                hn = std::hypot(cx[nb] - mx, cy[nb] - my);
+            }
+            adj_surf.push_back(sf);
+            adj_nbr.push_back(nb);
+            adj_sign.push_back(is_a ? 1.0 : -1.0);
+            adj_L.push_back(L);
+            adj_h.push_back(hs);
+            adj_hn.push_back(hn);
+        }
+        adj_off[k + 1] = (int64_t)adj_surf.size();
+    }
+    // regions of each cell, entry cells of the incoming track-senses
+    std::vector<int64_t> reg_off(n_cells + 1, 0);
+    for (int r = 0; r < R; ++r) ++reg_off[cs.cell_of[r] + 1];
+    for (int k = 0; k < n_cells; ++k) reg_off[k + 1] += reg_off[k];
+    std::vector<int> cell_reg(R);
+    {
+        std::vector<int64_t> pos(reg_off.begin(), reg_off.end() - 1);
+        for (int r = 0; r < R; ++r) cell_reg[pos[cs.cell_of[r]]++] = r;
+    }
+    std::vector<int> entry_cell(pk.entry_region.size(), -1);
+    for (size_t i = 0; i < entry_cell.size(); ++i)
+        if (pk.entry_region[i] >= 0) entry_cell[i] = cs.cell_of[pk.entry_region[i]];
+
+    DevCoarse &cd = c->cd;
+    cd.C = n_cells;
+    cd.Ns = Ns;
+    cd.nadj = (int)adj_surf.size();
+    cd.tol = o.tol > 0 ? o.tol : 1e-5;
+    cd.shift = o.shift > 0 ? o.shift : (o.shift < 0 ? 0.0 : 0.02);
+    cd.max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    cd.max_inner = o.max_inner > 0 ? o.max_inner : 200;
+    if (!c->host_only) {
+        const size_t N = (size_t)n_cells * G;
+        cd.cell_of = c->upload(cs.cell_of);
+        cd.cell_reg_off = c->upload(reg_off);
+        cd.cell_reg = c->upload(cell_reg);
+        cd.entry_cell = c->upload(entry_cell);
+        cd.adj_off = c->upload(adj_off);
+        cd.adj_surf = c->upload(adj_surf);
+        cd.adj_nbr = c->upload(adj_nbr);
+        cd.adj_sign = c->upload(adj_sign);
+        cd.adj_L = c->upload(adj_L);
+        cd.adj_h = c->upload(adj_h);
+        cd.adj_hn = c->upload(adj_hn);
+        cd.hsum = c->dalloc<double>((size_t)n_cells * (2 + 4 * G + G * G));
+        cd.Bs = c->dalloc<double>(N * G);
+        cd.Binv = c->dalloc<double>(N * G);
+        cd.Aoff = c->dalloc<double>((size_t)std::max(1, cd.nadj) * G);
+        cd.phih = c->dalloc<double>(N);
+        cd.Dc = c->dalloc<double>(N);
+        cd.Ldiag = c->dalloc<double>(N);
+        cd.fchi = c->dalloc<double>(N);
+        cd.fnsf = c->dalloc<double>(N);
+        cd.vec = c->dalloc<double>(10 * N);
+        cd.ratio = c->dalloc<double>(N);
+        cd.stats = c->dalloc<double>(4);
+        cd.piv = c->dalloc<int>(N);
+        launch_fill_f64(cd.stats, 4, 0.0, c->stream);
+        HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    c->cmfd = true;
+    c->coarse_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int moc_set_coarse_mesh(moc_ctx *c, int32_t n_cells, const int32_t *region_cell, const moc_cmfd_options *opts) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] { set_coarse_impl(c, n_cells, region_cell, opts); });
+}
+
+int moc_get_coarse_info(moc_ctx *c, moc_coarse_info *info) {
+    if (!c || !info) return MOC_EINVAL;
+    return guarded(c, [&] {
+        *info = moc_coarse_info{};
+        if (!c->cmfd) return;
+        info->n_cells = c->cd.C;
+        info->n_surfaces = c->cd.Ns;
+        info->n_crossings = c->crossings;
+        info->setup_ms = c->coarse_setup_ms;
+        if (!c->host_only) {
+            double st[4];
+            HIP_OK(hipSetDevice(c->device));
+            HIP_OK(hipMemcpyAsync(st, c->cd.stats, sizeof st, hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            info->last_outer = (int32_t)st[0];
+            info->last_inner = (int32_t)st[1];
+            info->last_k = st[2];
+        }
+    });
+}
+
+int moc_get_surface_currents(moc_ctx *c, int32_t *cells, double *current) {
+    if (!c) return MOC_EINVAL;
+    return guarded(c, [&] {
+        if (!c->cmfd) throw Error(MOC_ESTATE, "surface currents: no coarse mesh set");
+        const int Ns = (int)c->cs.a.size(), G = c->d.G, Gp = c->d.Gp;
+        if (cells)
+            for (int sf = 0; sf < Ns; ++sf) {
+                cells[2 * (size_t)sf] = c->cs.a[sf];
+                cells[2 * (size_t)sf + 1] = c->cs.b[sf];
+            }
+        if (current) {
+            need_device(c);
+            HIP_OK(hipSetDevice(c->device));
+            std::vector<double> rows((size_t)Ns * Gp);
+            if (Ns)
+                HIP_OK(hipMemcpyAsync(rows.data(), c->d.tally + (size_t)c->d.R * Gp, rows.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            for (int sf = 0; sf < Ns; ++sf)
+                for (int g = 0; g < G; ++g) current[(size_t)sf * G + g] = rows[(size_t)sf * Gp + g];
+        }
     });
 }
 

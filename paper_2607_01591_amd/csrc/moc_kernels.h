@@ -40,6 +40,7 @@ struct SweepArgs {
     double *exit_canon;        // optional [T][2][P][G]
     const int *canon_of_slot;  // [nslots] canonical track or -1
     int nslots, Gp, G;
+    int n_real;                // regions; tally rows at and above it are coarse surfaces
 };
 
 struct DevProblem {
@@ -72,7 +73,33 @@ struct DevProblem {
     double *partials = nullptr, *scal = nullptr;
 };
 
-void launch_sweep(const SweepArgs &a, int precision, int exp_mode, int nb, int np, int gb, int n_gb, hipStream_t s);
+// Coarse mesh (CMFD) device state; see moc_cmfd.hip.
+struct DevCoarse {
+    int C = 0, Ns = 0, nadj = 0;
+    int *cell_of = nullptr;           // [R] internal region -> cell
+    int64_t *cell_reg_off = nullptr;  // [C + 1] internal regions of each cell
+    int *cell_reg = nullptr;          // [R]
+    int *entry_cell = nullptr;        // [2][nslots] cell of the first region per incoming track-sense, -1
+    int64_t *adj_off = nullptr;       // [C + 1] surfaces of each cell
+    int *adj_surf = nullptr, *adj_nbr = nullptr;  // [nadj] surface id, neighbour cell (-1 = boundary)
+    double *adj_sign = nullptr;       // [nadj] +1 if the surface's positive orientation leaves the cell
+    double *adj_L = nullptr, *adj_h = nullptr, *adj_hn = nullptr;  // [nadj] shared length, centroid distances
+    double *hsum = nullptr;           // [C][2 + 4 G + G^2] homogenisation sums
+    double *Bs = nullptr, *Binv = nullptr;  // [C][G][G] diagonal blocks and their inverses
+    double *Aoff = nullptr;           // [nadj][G] neighbour couplings
+    double *phih = nullptr, *Dc = nullptr, *Ldiag = nullptr, *fchi = nullptr, *fnsf = nullptr;  // [C][G]
+    double *vec = nullptr;            // [10][C G] solver vectors
+    double *ratio = nullptr;          // [C][G]
+    double *stats = nullptr;          // [4] outer, inner iterations, coarse k
+    int *piv = nullptr;               // [C][G]
+    double tol = 1e-5, shift = 0.02;
+    int max_outer = 20, max_inner = 200;
+};
+
+void launch_cmfd(const DevProblem &d, const DevCoarse &cd, double *phi, void *psi, hipStream_t s);
+
+void launch_sweep(const SweepArgs &a, int precision, int exp_mode, bool currents, int nb, int np, int gb, int n_gb,
+                  hipStream_t s);
 void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 void launch_fill_real(void *p, int64_t n, int precision, hipStream_t s);
 void launch_scale_real(void *p, int64_t n, int precision, const double *f, hipStream_t s);

@@ -82,7 +82,13 @@ template <typename Real, int MODE> __device__ __forceinline__ Real one_minus_exp
 // weights c_ap = 2 pi w_a w_p delta_a sin(theta_p) in registers, then added to the
 // window-local FP64 tally slot in LDS. At the end of each window every slot is flushed with
 // one FP64 atomic per group (consecutive lanes hit consecutive groups of a region row).
-template <typename Real, int NP, int GB, int MODE>
+//
+// CUR: the stream also holds coarse-surface crossing entries (region field >= n_real,
+// length +-1 for the surface orientation). Their tally row holds Sigma_t = 1e30 and
+// qhat = 0, so the same update gives Delta = psi; the angular flux is kept (psi -= 0 *
+// Delta) and c_ap psi is tallied with the sign of the crossing direction, which makes
+// the surface's tally row the net current across it.
+template <typename Real, int NP, int GB, int MODE, bool CUR>
 __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     using Seg = typename SegOf<Real>::type;
     extern __shared__ unsigned char smem[];
@@ -176,8 +182,19 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
         // one step: Eq. MOC_sol for every group of the batch and polar angle, polar-summed
         // increments into the window's LDS tally
         auto update = [&](const Seg &sg, const Real (&st)[GB], const Real (&q)[GB]) {
-            const Real len = sg.len;
+            Real len = sg.len;
             const int ts = int(sg.key & ((1u << kSlotBits) - 1));
+            Real cw[NP], keep = Real(1);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) cw[p] = c[p];
+            if constexpr (CUR) {
+                const bool cross = len != Real(0) && (sg.key >> kSlotBits) >= (uint32_t)args.n_real;
+                const Real sgn = (len > Real(0)) == (sense == 0) ? Real(1) : Real(-1);
+                keep = cross ? Real(0) : Real(1);
+                len = cross ? Real(1) : len;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) cw[p] = cross ? c[p] * sgn : c[p];
+            }
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
                 const Real sl = st[j] * len;
@@ -190,8 +207,11 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
                     else
                         F = one_minus_exp<Real, MODE>(sl * is[p], lut);
                     const Real d = (psi[p][j] - q[j]) * F;
-                    psi[p][j] -= d;
-                    acc += c[p] * d;
+                    if constexpr (CUR)
+                        psi[p][j] -= keep * d;
+                    else
+                        psi[p][j] -= d;
+                    acc += cw[p] * d;
                 }
                 if (len > Real(0)) atomicAdd(&tl[j * cap + ts], (double)acc);   // padding steps add nothing
             }
@@ -422,7 +442,8 @@ __global__ void k_k_estimate(const double *__restrict__ pf, const double *__rest
 
 // Single block. mode 0: initial normalisation (f = 1/sum); mode 1: eigenvalue update
 // k <- k * sum V F_new (the old iterate has sum V F = 1), f = 1/sum; mode 2: fixed source
-// (k = 1, f = 1). Partials are summed in a fixed order (deterministic).
+// (k = 1, f = 1); mode 3: k already set by the coarse-mesh solve, f = 1/sum. Partials are
+// summed in a fixed order (deterministic).
 __global__ void k_eigen_update(const double *__restrict__ partials, int nblk, double *__restrict__ scal, int mode) {
     __shared__ double sh[16];
     double acc = 0.0;
@@ -436,9 +457,11 @@ __global__ void k_eigen_update(const double *__restrict__ partials, int nblk, do
             scal[kScalKPrev] = scal[kScalK];
             scal[kScalK] = scal[kScalK] * s;
             scal[kScalF] = 1.0 / s;
-        } else {
+        } else if (mode == 2) {
             scal[kScalKPrev] = scal[kScalK];
             scal[kScalF] = 1.0;
+        } else {
+            scal[kScalF] = 1.0 / s;
         }
     }
 }
@@ -563,49 +586,58 @@ static inline int grid_for(int64_t n, int block, int cap = 4096) {
         if (e_ != hipSuccess) throw Error(MOC_EHIP, hipGetErrorString(e_));     \
     } while (0)
 
-template <typename Real, int NP, int GB, int MODE>
+template <typename Real, int NP, int GB, int MODE, bool CUR>
 static void sweep_inst(const SweepArgs &a, int nb, int n_gb, hipStream_t s) {
     if (a.cap > kMaxSlots) throw Error(MOC_EINVAL, "sweep: window slot count above the kernel maximum");
     size_t lds = (sizeof(double) * GB + sizeof(int)) * (size_t)a.cap;
     if (MODE == MOC_EXP_TABLE && sizeof(Real) == 4) lds += sizeof(float) * ExpTable::kN;
     if (lds > 64 * 1024) throw Error(MOC_EINVAL, "sweep: tally window does not fit in LDS");
-    hipLaunchKernelGGL((k_sweep<Real, NP, GB, MODE>), dim3(nb, 2, n_gb), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((k_sweep<Real, NP, GB, MODE, CUR>), dim3(nb, 2, n_gb), dim3(64), lds, s, a);
 }
 
-template <typename Real, int NP, int MODE>
+template <typename Real, int NP, int MODE, bool CUR>
 static bool sweep_gb(const SweepArgs &a, int nb, int gb, int n_gb, hipStream_t s) {
     switch (gb) {
-        case 1: sweep_inst<Real, NP, 1, MODE>(a, nb, n_gb, s); return true;
-        case 2: sweep_inst<Real, NP, 2, MODE>(a, nb, n_gb, s); return true;
-        case 4: sweep_inst<Real, NP, 4, MODE>(a, nb, n_gb, s); return true;
-        case 7: sweep_inst<Real, NP, 7, MODE>(a, nb, n_gb, s); return true;
-        case 8: sweep_inst<Real, NP, 8, MODE>(a, nb, n_gb, s); return true;
-        case 11: sweep_inst<Real, NP, 11, MODE>(a, nb, n_gb, s); return true;
+        case 1: sweep_inst<Real, NP, 1, MODE, CUR>(a, nb, n_gb, s); return true;
+        case 2: sweep_inst<Real, NP, 2, MODE, CUR>(a, nb, n_gb, s); return true;
+        case 4: sweep_inst<Real, NP, 4, MODE, CUR>(a, nb, n_gb, s); return true;
+        case 7: sweep_inst<Real, NP, 7, MODE, CUR>(a, nb, n_gb, s); return true;
+        case 8: sweep_inst<Real, NP, 8, MODE, CUR>(a, nb, n_gb, s); return true;
+        case 11: sweep_inst<Real, NP, 11, MODE, CUR>(a, nb, n_gb, s); return true;
         default: return false;
     }
 }
 
-template <typename Real, int MODE>
+template <typename Real, int MODE, bool CUR>
 static bool sweep_np(const SweepArgs &a, int nb, int np, int gb, int n_gb, hipStream_t s) {
     switch (np) {
-        case 1: return sweep_gb<Real, 1, MODE>(a, nb, gb, n_gb, s);
-        case 2: return sweep_gb<Real, 2, MODE>(a, nb, gb, n_gb, s);
-        case 3: return sweep_gb<Real, 3, MODE>(a, nb, gb, n_gb, s);
-        case 4: return sweep_gb<Real, 4, MODE>(a, nb, gb, n_gb, s);
+        case 1: return sweep_gb<Real, 1, MODE, CUR>(a, nb, gb, n_gb, s);
+        case 2: return sweep_gb<Real, 2, MODE, CUR>(a, nb, gb, n_gb, s);
+        case 3: return sweep_gb<Real, 3, MODE, CUR>(a, nb, gb, n_gb, s);
+        case 4: return sweep_gb<Real, 4, MODE, CUR>(a, nb, gb, n_gb, s);
         default: return false;
     }
 }
 
-void launch_sweep(const SweepArgs &a, int precision, int exp_mode, int nb, int np, int gb, int n_gb, hipStream_t s) {
+void launch_sweep(const SweepArgs &a, int precision, int exp_mode, bool currents, int nb, int np, int gb, int n_gb,
+                  hipStream_t s) {
     bool ok;
-    if (precision == MOC_PREC_F64) {
-        ok = sweep_np<double, MOC_EXP_POLY>(a, nb, np, gb, n_gb, s);
+    if (currents) {
+        // coarse-surface currents: FP64, or FP32 with the default exponential
+        if (precision == MOC_PREC_F64)
+            ok = sweep_np<double, MOC_EXP_POLY, true>(a, nb, np, gb, n_gb, s);
+        else if (exp_mode == MOC_EXP_POLY)
+            ok = sweep_np<float, MOC_EXP_POLY, true>(a, nb, np, gb, n_gb, s);
+        else
+            throw Error(MOC_EINVAL, "sweep: coarse-surface currents need the default exponential (exp_mode 0)");
+    } else if (precision == MOC_PREC_F64) {
+        ok = sweep_np<double, MOC_EXP_POLY, false>(a, nb, np, gb, n_gb, s);
     } else if (exp_mode == MOC_EXP_TABLE) {
-        ok = sweep_np<float, MOC_EXP_TABLE>(a, nb, np, gb, n_gb, s);
+        ok = sweep_np<float, MOC_EXP_TABLE, false>(a, nb, np, gb, n_gb, s);
     } else if (exp_mode == MOC_EXP_LIBM) {
-        ok = sweep_np<float, MOC_EXP_LIBM>(a, nb, np, gb, n_gb, s);
+        ok = sweep_np<float, MOC_EXP_LIBM, false>(a, nb, np, gb, n_gb, s);
     } else {
-        ok = sweep_np<float, MOC_EXP_POLY>(a, nb, np, gb, n_gb, s);
+        ok = sweep_np<float, MOC_EXP_POLY, false>(a, nb, np, gb, n_gb, s);
     }
     if (!ok) throw Error(MOC_EINVAL, "sweep: no kernel instance for this polar count / group batch");
     MOC_CHECK_LAUNCH();

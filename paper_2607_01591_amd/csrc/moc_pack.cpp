@@ -22,10 +22,31 @@ namespace moc {
 namespace {
 
 struct LaneSeg {
-    int reg;      // internal region
-    double len;
+    int reg;      // internal region, or n_real + surface id for a crossing entry
+    double len;   // length; +-1 (orientation) for a crossing entry
     double s0;    // distance of the segment start from the track start (sense 0)
 };
+
+// Insert the coarse-surface crossing entries into one track's segment list: entering the
+// domain, every change of coarse cell, leaving the domain.
+void add_crossings(const CoarseSurfaces &cs, int n_real, std::vector<LaneSeg> &v, std::vector<LaneSeg> &tmp) {
+    if (v.empty()) return;
+    tmp.clear();
+    int prev = -1;
+    for (size_t k = 0; k < v.size(); ++k) {
+        const int c = cs.cell_of[v[k].reg];
+        if (k == 0) {
+            tmp.push_back({n_real + cs.find(c, -1), -1.0, v[k].s0});          // into the domain
+        } else if (c != prev) {
+            const int lo = std::min(prev, c), hi = std::max(prev, c);
+            tmp.push_back({n_real + cs.find(lo, hi), prev < c ? 1.0 : -1.0, v[k].s0});
+        }
+        tmp.push_back(v[k]);
+        prev = c;
+    }
+    tmp.push_back({n_real + cs.find(prev, -1), 1.0, v.back().s0 + v.back().len});  // out of the domain
+    v.swap(tmp);
+}
 
 struct CollectSink : SegmentSink {
     std::vector<LaneSeg> *out = nullptr;
@@ -56,6 +77,7 @@ class BatchPlanner {
             sink.out = &lanes_[t - t0];
             sink.s = 0;
             trace_track(*in_.mesh, *in_.quad, *in_.tracks, t, sink);
+            if (in_.coarse) add_crossings(*in_.coarse, in_.mesh->R, lanes_[t - t0], tmp_);
         }
         windows_.clear();
         tab_.clear();
@@ -80,6 +102,12 @@ class BatchPlanner {
     int64_t n_windows() const { return (int64_t)windows_.size(); }
     int64_t n_slots() const { return (int64_t)tab_.size(); }
     int64_t n_segments() const {
+        int64_t n = 0;
+        for (const auto &v : lanes_)
+            for (const LaneSeg &s : v) n += s.reg < in_.mesh->R;
+        return n;
+    }
+    int64_t n_entries() const {
         int64_t n = 0;
         for (const auto &v : lanes_) n += (int64_t)v.size();
         return n;
@@ -188,6 +216,7 @@ class BatchPlanner {
     std::vector<std::vector<LaneSeg>> lanes_;
     std::vector<size_t> ptr_, end_;
     std::vector<int> regs_;
+    std::vector<LaneSeg> tmp_;
     std::vector<Window> windows_;
     std::vector<int> tab_;
     int64_t steps_ = 0;
@@ -200,7 +229,7 @@ void pack_impl(const PackInput &in, PackOutput &out, std::vector<Seg> &segs) {
     if ((int64_t)in.mesh->R >= (int64_t(1) << (32 - kSlotBits)))
         throw Error(MOC_EINVAL, "pack: too many regions for the packed segment key");
     // pass 1: plan every batch, keep only the sizes
-    std::vector<int64_t> b_steps(nb), b_win(nb), b_slots(nb), b_segs(nb);
+    std::vector<int64_t> b_steps(nb), b_win(nb), b_slots(nb), b_segs(nb), b_cross(nb);
     parallel_for(nb, in.n_threads, 4, [&](int64_t b0, int64_t b1, int) {
         BatchPlanner pl(in);
         for (int64_t b = b0; b < b1; ++b) {
@@ -209,11 +238,14 @@ void pack_impl(const PackInput &in, PackOutput &out, std::vector<Seg> &segs) {
             b_win[b] = pl.n_windows();
             b_slots[b] = pl.n_slots();
             b_segs[b] = pl.n_segments();
+            b_cross[b] = pl.n_entries() - b_segs[b];
         }
     });
     std::vector<int64_t> e_off(nb + 1, 0), w_off(nb + 1, 0), s_off(nb + 1, 0);
     out.S = 0;
+    out.crossings = 0;
     for (int b = 0; b < nb; ++b) {
+        out.crossings += b_cross[b];
         e_off[b + 1] = e_off[b] + b_steps[b] * kBatch;
         w_off[b + 1] = w_off[b] + b_win[b];
         s_off[b + 1] = s_off[b] + b_slots[b];
@@ -249,16 +281,21 @@ void pack_impl(const PackInput &in, PackOutput &out, std::vector<Seg> &segs) {
                 out.win_tab_off[i] = s_off[b] + ws[w].tab_off;
                 out.win_nslots[i] = ws[w].nslots;
             }
+            const int R = in.mesh->R;
             for (int t = t0; t < t1; ++t) {
                 const int l = t - t0;
                 const auto &v = pl.lane(l);
                 const int a = in.tracks->angle[t];
                 const double wgt = in.quad->wa[a] * in.quad->delta[a];
-                for (const LaneSeg &s : v) V[s.reg] += wgt * s.len;
-                if (!v.empty()) {
-                    out.entry_region[(size_t)b * kBatch + l] = v.front().reg;                       // sense 0
-                    out.entry_region[(size_t)nb * kBatch + (size_t)b * kBatch + l] = v.back().reg;  // sense 1
+                int first = -1, last = -1;
+                for (const LaneSeg &s : v) {
+                    if (s.reg >= R) continue;   // crossing entry
+                    V[s.reg] += wgt * s.len;
+                    if (first < 0) first = s.reg;
+                    last = s.reg;
                 }
+                out.entry_region[(size_t)b * kBatch + l] = first;                       // sense 0
+                out.entry_region[(size_t)nb * kBatch + (size_t)b * kBatch + l] = last;  // sense 1
             }
         }
     });
@@ -268,6 +305,53 @@ void pack_impl(const PackInput &in, PackOutput &out, std::vector<Seg> &segs) {
 }
 
 }  // namespace
+
+void find_coarse_surfaces(const Mesh &mesh, const Quadrature &quad, const Tracks &tracks,
+                          const int *internal_of_user, int n_threads, CoarseSurfaces &cs) {
+    struct CellSink : SegmentSink {
+        const int *internal_of_user = nullptr;
+        const CoarseSurfaces *cs = nullptr;
+        std::vector<int64_t> *keys = nullptr;
+        int prev = -1;
+        void emit(int r, double) override {
+            const int c = cs->cell_of[internal_of_user[r]];
+            if (prev < 0) keys->push_back(cs->key(c, -1));
+            else if (c != prev) keys->push_back(cs->key(std::min(c, prev), std::max(c, prev)));
+            prev = c;
+        }
+    };
+    const int nthr = std::max(1, n_threads);
+    std::vector<std::vector<int64_t>> keys(nthr);
+    parallel_for(tracks.T, nthr, 64, [&](int64_t t0, int64_t t1, int tid) {
+        CellSink sink;
+        sink.internal_of_user = internal_of_user;
+        sink.cs = &cs;
+        sink.keys = &keys[tid];
+        for (int64_t t = t0; t < t1; ++t) {
+            sink.prev = -1;
+            trace_track(mesh, quad, tracks, (int)t, sink);
+            if (sink.prev >= 0) keys[tid].push_back(cs.key(sink.prev, -1));
+            auto &k = keys[tid];
+            if (k.size() > (1u << 20)) {
+                std::sort(k.begin(), k.end());
+                k.erase(std::unique(k.begin(), k.end()), k.end());
+            }
+        }
+    });
+    std::vector<int64_t> all;
+    for (auto &k : keys) all.insert(all.end(), k.begin(), k.end());
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    cs.a.resize(all.size());
+    cs.b.resize(all.size());
+    cs.id.clear();
+    cs.id.reserve(all.size() * 2);
+    for (size_t i = 0; i < all.size(); ++i) {
+        cs.a[i] = int(all[i] / (cs.n_cells + 1)) - 1;
+        cs.b[i] = int(all[i] % (cs.n_cells + 1)) - 1;
+        cs.id[all[i]] = (int)i;
+    }
+}
 
 void pack_segments_f32(const PackInput &in, PackOutput &out, std::vector<SegF> &segs) { pack_impl(in, out, segs); }
 void pack_segments_f64(const PackInput &in, PackOutput &out, std::vector<SegD> &segs) { pack_impl(in, out, segs); }

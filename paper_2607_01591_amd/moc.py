@@ -68,6 +68,15 @@ class MocProfile(C.Structure):
     _fields_ = [("sweeps", _i64), ("sweep_ms", _f64), ("sweep_ms_min", _f64), ("sweep_ms_max", _f64)]
 
 
+class MocCmfdOptions(C.Structure):
+    _fields_ = [("tol", _f64), ("shift", _f64), ("max_outer", _i32), ("max_inner", _i32)]
+
+
+class MocCoarseInfo(C.Structure):
+    _fields_ = [("n_cells", _i32), ("n_surfaces", _i32), ("n_crossings", _i64), ("setup_ms", _f64),
+                ("last_outer", _i32), ("last_inner", _i32), ("last_k", _f64)]
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "moc_create": (C.c_int, [_P(MocMesh), _P(MocTracks), _P(MocXS), _P(MocOptions), _P(C.c_void_p)]),
@@ -93,6 +102,9 @@ SIGNATURES = {
     "moc_locate_points": (C.c_int, [C.c_void_p, _P(_f64), _i64, _P(_i32)]),
     "moc_get_centroids": (C.c_int, [C.c_void_p, _P(_f64)]),
     "moc_get_profile": (C.c_int, [C.c_void_p, _P(MocProfile)]),
+    "moc_set_coarse_mesh": (C.c_int, [C.c_void_p, _i32, _P(_i32), _P(MocCmfdOptions)]),
+    "moc_get_coarse_info": (C.c_int, [C.c_void_p, _P(MocCoarseInfo)]),
+    "moc_get_surface_currents": (C.c_int, [C.c_void_p, _P(_i32), _P(_f64)]),
 }
 
 _lib = None
@@ -193,11 +205,10 @@ class Solver:
         self._keep = []
         self.device = device
         self.precision = precision
-        inf = MocInfo()
-        L.moc_get_info(self._h, C.byref(inf))
-        self.info = {k: getattr(inf, k) for k, _ in MocInfo._fields_}
-        self.R, self.G, self.P = inf.n_regions, inf.n_groups, inf.n_polar
-        self.T, self.S, self.U = inf.n_tracks, inf.n_segments, inf.n_updates
+        self._refresh_info()
+        inf = self.info
+        self.R, self.G, self.P = inf["n_regions"], inf["n_groups"], inf["n_polar"]
+        self.T, self.S, self.U = inf["n_tracks"], inf["n_segments"], inf["n_updates"]
         self._exit = None
         self._qext = None
 
@@ -298,6 +309,39 @@ class Solver:
         x.n_materials, x.n_groups = arrs[0].shape
         x.sigma_t, x.sigma_s, x.nu_sigma_f, x.chi = (_ptr(a, _f64) for a in arrs)
         self._check(lib().moc_set_materials(self._h, _ptr(rm, _i32), C.byref(x)))
+
+    def _refresh_info(self):
+        inf = MocInfo()
+        lib().moc_get_info(self._h, C.byref(inf))
+        self.info = {k: getattr(inf, k) for k, _ in MocInfo._fields_}
+
+    def set_coarse_mesh(self, n_cells: int, region_cell=None, tol: float = 0.0, shift: float = 0.0,
+                        max_outer: int = 0, max_inner: int = 0):
+        """CMFD on a coarse mesh: region_cell [R] (user order) assigns regions to cells;
+        n_cells = 0 removes it. Zero options take the library defaults."""
+        o = MocCmfdOptions(float(tol), float(shift), int(max_outer), int(max_inner))
+        if n_cells <= 0 or region_cell is None:
+            self._check(lib().moc_set_coarse_mesh(self._h, 0, None, C.byref(o)))
+        else:
+            rc = np.ascontiguousarray(region_cell, np.int32)
+            if rc.shape != (self.R,):
+                raise ValueError("region_cell must have one entry per region")
+            self._check(lib().moc_set_coarse_mesh(self._h, int(n_cells), _ptr(rc, _i32), C.byref(o)))
+        self._refresh_info()
+
+    def coarse_info(self) -> dict:
+        ci = MocCoarseInfo()
+        self._check(lib().moc_get_coarse_info(self._h, C.byref(ci)))
+        return {k: getattr(ci, k) for k, _ in MocCoarseInfo._fields_}
+
+    def surface_currents(self, with_current: bool = True):
+        """(cells [Ns, 2], current [Ns, G] or None): net currents of the last sweep."""
+        ns = self.coarse_info()["n_surfaces"]
+        cells = np.zeros((ns, 2), np.int32)
+        cur = np.zeros((ns, self.G)) if with_current else None
+        self._check(lib().moc_get_surface_currents(self._h, _ptr(cells, _i32),
+                                                   _ptr(cur, _f64) if cur is not None else None))
+        return cells, cur
 
     def locate(self, xy) -> np.ndarray:
         xy = np.ascontiguousarray(xy, np.float64).reshape(-1, 2)

@@ -211,3 +211,97 @@ def _check_packing(prob, precision="f32", **kw):
 def test_packing_indices_and_sequences(name, prob, kw):
     _check_packing(prob, **kw)
     _check_packing(prob, precision="f64", **kw)
+
+
+COARSE_CASES = [
+    ("lattice3x3_vacuum2", P.square_lattice(3, 3, seed=1, n_azim=16, spacing=0.05, bc=(1, 0, 1, 0)), (3, 3), {}),
+    ("lattice4x4_cells2x2_small_cap", P.square_lattice(4, 4, seed=6, n_azim=8, spacing=0.08, bc=(0, 0, 0, 0)),
+     (2, 2), {"tally_slots": 64, "window_cm": 3.0}),
+    ("hex_small_grid4", P.hex_assembly(seed=5, rings=3, edge=0.25, G=4, spacing=0.05, n_azim=16), (4, 4), {}),
+]
+
+
+@pytest.mark.parametrize("name,prob,grid,kw", COARSE_CASES, ids=[c[0] for c in COARSE_CASES])
+def test_coarse_surfaces_and_crossing_entries(name, prob, grid, kw):
+    """The coarse surfaces are the cell pairs the oracle's own tracks cross, and every
+    track's packed entries are its segments with a crossing entry (of the right surface
+    and orientation) at both ends and at every change of coarse cell."""
+    from oracle.oracle import Oracle
+    n, rc = P.coarse_cells(prob, *grid)
+    s = moc.Solver(prob, device=-1, **kw)
+    base = dict(s.info)
+    s.set_coarse_mesh(n, rc)
+    o = Oracle.from_problem(prob)
+    o.set_coarse(n, rc)
+    off_o, nbr_o = o.coarse_adjacency()
+    ref_pairs = set()
+    for i in range(n):
+        for k in range(off_o[i], off_o[i + 1]):
+            j = int(nbr_o[k])
+            ref_pairs.add((i, -1) if j < 0 else (min(i, j), max(i, j)))
+    cells, _ = s.surface_currents(with_current=False)
+    pairs = [tuple(map(int, c)) for c in cells]
+    assert set(pairs) == ref_pairs and len(pairs) == len(ref_pairs)
+    sid = {p: i for i, p in enumerate(pairs)}
+    R = s.R
+    pk = s.packing()
+    tr = s.tracks()
+    key, ln = pk["seg_key"], pk["seg_len"]
+    reg_int = (key >> 9).astype(np.int64)
+    uoi = pk["user_of_internal"]
+    assert s.info["n_segments"] == base["n_segments"]
+    ncross = int(((reg_int >= R) & (ln != 0)).sum())
+    assert ncross == s.coarse_info()["n_crossings"]
+    ang, off = tr["angle"], tr["offset"]
+    first = [0]
+    for t in range(1, s.T):
+        if ang[t] != ang[t - 1] or t - first[-1] == 64:
+            first.append(t)
+    first.append(s.T)
+    bw = pk["batch_win"]
+    expect_total = 0
+    for b in range(len(first) - 1):
+        lanes = [[] for _ in range(64)]
+        for w in range(bw[b], bw[b + 1]):
+            e0, nst = pk["win_entry_off"][w], pk["win_nsteps"][w]
+            L = ln[e0:e0 + 64 * nst].reshape(nst, 64)
+            RG = reg_int[e0:e0 + 64 * nst].reshape(nst, 64)
+            for l in range(64):
+                for j in range(nst):
+                    if L[j, l] != 0:
+                        lanes[l].append((int(RG[j, l]), float(L[j, l])))
+        for l in range(first[b + 1] - first[b]):
+            t = first[b] + l
+            regs = tr["region"][off[t]:off[t + 1]]
+            exp = []
+            prev = -1
+            for k, r in enumerate(regs):
+                c = int(rc[r])
+                if k == 0:
+                    exp.append(("x", sid[(c, -1)], -1.0))
+                elif c != prev:
+                    exp.append(("x", sid[(min(prev, c), max(prev, c))], 1.0 if prev < c else -1.0))
+                exp.append(("r", int(r)))
+                prev = c
+            if len(regs):
+                exp.append(("x", sid[(prev, -1)], 1.0))
+            got = [("x", rg - R, lv) if rg >= R else ("r", int(uoi[rg])) for rg, lv in lanes[l]]
+            assert got == exp
+            expect_total += sum(1 for e in exp if e[0] == "x")
+    assert expect_total == ncross
+    # removing the coarse mesh restores the original packing
+    s.set_coarse_mesh(0)
+    assert s.info["n_padded_steps"] == base["n_padded_steps"]
+    assert np.array_equal(s.packing()["seg_key"], moc.Solver(prob, device=-1, **kw).packing()["seg_key"])
+
+
+def test_coarse_mesh_rejects_bad_maps():
+    prob = P.square_lattice(2, 2, seed=1, n_azim=8, spacing=0.1)
+    s = moc.Solver(prob, device=-1)
+    n, rc = P.coarse_cells(prob, 2, 2)
+    for bad_n, bad_rc in [(n, np.where(rc == 0, n, rc)), (n + 1, rc), (n, np.full_like(rc, -1))]:
+        with pytest.raises(moc.MocError) as e:
+            s.set_coarse_mesh(bad_n, bad_rc)
+        assert e.value.code == moc.MOC_EINVAL
+    s.set_coarse_mesh(n, rc)
+    assert s.coarse_info()["n_cells"] == n
