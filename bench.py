@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-hex", action="store_true")
     ap.add_argument("--solve-seeds", type=int, default=3)
+    ap.add_argument("--no-cmfd", action="store_true", help="skip the CMFD time-to-tolerance legs")
     ap.add_argument("--exp-mode", default="poly")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
@@ -207,13 +208,32 @@ def main():
         del sh
         torch.cuda.empty_cache()
 
+    cmfd3 = None
+    if not args.no_cmfd:
+        log("51x51 lattice: time to a 1e-6 residual with CMFD on the 51 x 51 pin cells (cold start)")
+        s3 = moc.Solver(prob, precision="f32", max_iter=2000, check_every=1)
+        n_cells, region_cell = P.coarse_cells(prob, 51, 51)
+        s3.set_coarse_mesh(n_cells, region_cell)
+        s3.run_iterations(1)     # first-use costs (code objects) outside the timing
+        r3 = s3.solve(1e-6)
+        ci = s3.coarse_info()
+        cmfd3 = {"workload": f"{prob.name}, FP32 sweep, CMFD on {n_cells} pin cells, residual 1e-6",
+                 "converged": r3["converged"], "iterations": r3["iterations"], "wall_ms": r3["wall_ms"],
+                 "ms_per_iteration": r3["wall_ms"] / max(1, r3["iterations"]), "k": r3["k"],
+                 "coarse_surfaces": ci["n_surfaces"], "crossing_entries": ci["n_crossings"],
+                 "last_coarse_outer": ci["last_outer"], "last_coarse_inner": ci["last_inner"]}
+        log(f"CMFD 51x51: {cmfd3}")
+        del s3
+        torch.cuda.empty_cache()
+
     solve = None
     if not args.no_solve:
         import numpy as np
         weights = os.path.join(ROOT, "paper_2607_01591_amd", "weights", "warmstart_17x17.npz")
-        log("time to 1e-6 on 17x17 lattices (held-out seeds), cold vs warm start")
+        log("time to 1e-6 on 17x17 lattices (held-out seeds): cold, CMFD, warm start, warm start + CMFD")
         base = P.config(5, seed=100000)
         s5 = moc.Solver(base, precision="f32", max_iter=20000, check_every=10)
+        n5, rc5 = P.coarse_cells(base, 17, 17)
         ws = None
         if os.path.exists(weights):
             from paper_2607_01591_amd.warmstart import CHANNELS, WarmStart
@@ -224,6 +244,7 @@ def main():
         rows = []
         for sd in range(200000, 200000 + args.solve_seeds):
             p5 = P.config(5, seed=sd)
+            s5.set_coarse_mesh(0)
             s5.set_materials(p5)
             c = s5.solve(1e-6)
             row = {"seed": sd, "cold_iterations": c["iterations"], "cold_ms": c["wall_ms"]}
@@ -231,12 +252,22 @@ def main():
                 w = ws.solve_warm(p5, 1e-6)
                 row.update(warm_sweeps=w["sweeps"], warm_iterations=w["iterations"], warm_ms=w["total_ms"],
                            warm_predict_ms=w["predict_ms"], warm_converged=w["converged"])
+            if not args.no_cmfd:
+                s5.set_coarse_mesh(n5, rc5)
+                cm = s5.solve(1e-6)
+                row.update(cmfd_iterations=cm["iterations"], cmfd_ms=cm["wall_ms"])
+                if ws is not None:
+                    wc = ws.solve_warm(p5, 1e-6)
+                    row.update(warm_cmfd_sweeps=wc["sweeps"], warm_cmfd_ms=wc["total_ms"])
             rows.append(row)
             log(f"seed {sd}: {row}")
         med = lambda k: float(np.median([r[k] for r in rows])) if rows and k in rows[0] else None
         solve = {"workload": "17x17 lattice family (31k regions), FP32 sweep, residual 1e-6",
                  "cold_iterations_median": med("cold_iterations"), "cold_ms_median": med("cold_ms"),
-                 "warm_sweeps_median": med("warm_sweeps"), "warm_ms_median": med("warm_ms"), "runs": rows}
+                 "cmfd_iterations_median": med("cmfd_iterations"), "cmfd_ms_median": med("cmfd_ms"),
+                 "warm_sweeps_median": med("warm_sweeps"), "warm_ms_median": med("warm_ms"),
+                 "warm_cmfd_sweeps_median": med("warm_cmfd_sweeps"), "warm_cmfd_ms_median": med("warm_cmfd_ms"),
+                 "runs": rows}
 
     cpu = None
     if not args.no_cpu:
@@ -265,6 +296,7 @@ def main():
         "hbm_view": hbm,
         "fp64": fp64,
         "time_to_tol": solve,
+        "cmfd_51x51": cmfd3,
         "hexagon_g33": hexa,
         "cpu_baseline": cpu,
     }
