@@ -26,20 +26,26 @@ template <> struct SegOf<double> { using type = SegD; };
 
 // ---------------------------------------------------------------- 1 - exp(-tau)
 // FP32, MOC_EXP_POLY, evaluated from x = -tau log2(e) (folded into the per-polar
-// constant, so one multiply forms x): for tau >= 0.094 use 1 - 2^x with the hardware
-// exponential (absolute error ~6e-8, relative <= 6.4e-7 there); below, the Taylor series
-// of 1 - 2^x through x^4 (truncation < tau^4/120 <= 6.5e-7 relative). Relative accuracy
-// matters because the tally takes (psi - qhat) * F directly.
+// constant, so one multiply forms x) as the larger of two lower bounds of 1 - 2^x:
+//  * P4, the degree-4 Taylor polynomial of 1 - e^-tau: the Lagrange remainder
+//    tau^5 e^-xi / 120 is positive, so P4 never exceeds the true value, and it is
+//    accurate for small tau (relative error <= tau^4 / 120);
+//  * 1 - 2^x from the hardware exponential, lowered by kExpBias (four units in the last
+//    place of 1, more than that instruction's error), so it never exceeds the true value
+//    either, with an absolute error below 3.1e-7.
+// The maximum is within min(tau^5 / 120, 3.1e-7) of 1 - e^-tau: relative error <= 2.7e-6
+// (worst near tau = 0.13, with the exponential one unit off), and 0 for tau = 0. Relative accuracy matters because the
+// tally takes (psi - qhat) * F directly.
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr float kPolyC1 = -kLn2;
 constexpr float kPolyC2 = -kLn2 * kLn2 / 2.0f;
 constexpr float kPolyC3 = -kLn2 * kLn2 * kLn2 / 6.0f;
 constexpr float kPolyC4 = -kLn2 * kLn2 * kLn2 * kLn2 / 24.0f;
-constexpr float kPolyXThreshold = -0.094f * 1.4426950408889634f;
+constexpr float kExpBias = 2.384185791015625e-7f;   // 4 * 2^-24
 __device__ __forceinline__ float one_minus_exp2_poly(float x) {
-    const float big = 1.0f - __builtin_amdgcn_exp2f(x);
     const float small = x * (kPolyC1 + x * (kPolyC2 + x * (kPolyC3 + x * kPolyC4)));
-    return x > kPolyXThreshold ? small : big;
+    const float big = (1.0f - kExpBias) - __builtin_amdgcn_exp2f(x);
+    return fmaxf(small, big);
 }
 
 // MOC_EXP_TABLE: linear interpolation of f(x) = (1 - e^-x)/x on a uniform grid held in
@@ -92,7 +98,7 @@ template <typename Real, int NP, int GB, int MODE, bool CUR>
 __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     using Seg = typename SegOf<Real>::type;
     extern __shared__ unsigned char smem[];
-    double *tl = reinterpret_cast<double *>(smem);   // tally [GB][cap], FP64 (ds_add_f64 is much
+    double *tl = reinterpret_cast<double *>(smem);   // tally [cap][GB], FP64 (ds_add_f64 is much
     // faster than ds_add_f32 on gfx950 and keeps the window sums exact to FP64 rounding)
     const int cap = args.cap;
     float *lut = reinterpret_cast<float *>(smem + (sizeof(double) * GB + sizeof(int)) * cap);
@@ -195,10 +201,11 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
 #pragma unroll
                 for (int p = 0; p < NP; ++p) cw[p] = cross ? c[p] * sgn : c[p];
             }
+            Real acc[GB];
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
                 const Real sl = st[j] * len;
-                Real acc = 0;
+                acc[j] = 0;
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
                     Real F;
@@ -211,9 +218,13 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
                         psi[p][j] -= keep * d;
                     else
                         psi[p][j] -= d;
-                    acc += cw[p] * d;
+                    acc[j] += cw[p] * d;
                 }
-                if (len > Real(0)) atomicAdd(&tl[j * cap + ts], (double)acc);   // padding steps add nothing
+            }
+            if (len > Real(0)) {   // padding steps add nothing
+                double *row = tl + ts * GB;
+#pragma unroll
+                for (int j = 0; j < GB; ++j) atomicAdd(&row[j], (double)acc[j]);
             }
         };
         if constexpr (sizeof(Real) == 4) {
@@ -269,10 +280,10 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
         // flush the window's slots: (slot, group) pairs, groups fastest
         for (int e = lane; e < ns * GB; e += 64) {
             const int sl = e / GB, j = e - sl * GB;
-            const double v = tl[j * cap + sl];
+            const double v = tl[e];
             if (v != 0.0) {
                 unsafeAtomicAdd(&tally[(int64_t)tabl[sl] * Gp + g0 + j], v);
-                tl[j * cap + sl] = 0.0;
+                tl[e] = 0.0;
             }
         }
         __syncthreads();
