@@ -113,6 +113,10 @@ typedef struct {
     int32_t group_batch; /* groups per sweep wavefront: 1, 2, 4, 7, 8 or 11 (0: chosen from G) */
     int32_t window_steps;/* > 0: tally windows of this many segments per track instead of a
                             fixed length along the tracks (lanes stay busy, slots grow) */
+    int32_t lane_stagger;/* S > 1: lane l of every tally window starts (l mod S) steps late,
+                            so lanes at one step sit at different places along their tracks
+                            and fewer of them add to the same LDS tally row at once (costs up
+                            to S - 1 padding steps per window); 1: none; 0: library default */
 } moc_options;
 
 typedef struct {

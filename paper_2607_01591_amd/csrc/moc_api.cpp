@@ -120,6 +120,9 @@ static thread_local std::string g_create_error;
 // transport sweeps with a frozen source that precede a warm start without boundary fluxes
 static constexpr int kWarmBoundarySweeps = 2;
 
+// default lane stagger of the tally windows (moc_options.lane_stagger = 0)
+static constexpr int kDefaultLaneStagger = 1;
+
 template <typename F> static int guarded(moc_ctx *ctx, F &&f) {
     try {
         f();
@@ -303,6 +306,8 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     pin.cap = o.tally_slots > 0 ? o.tally_slots : 256;
     if (o.window_steps < 0) throw Error(MOC_EINVAL, "options: window_steps must be >= 0");
     pin.window_steps = o.window_steps;
+    if (o.lane_stagger < 0 || o.lane_stagger > kBatch) throw Error(MOC_EINVAL, "options: lane_stagger must be in 0..64");
+    pin.stagger = o.lane_stagger > 0 ? o.lane_stagger : kDefaultLaneStagger;
     {
         double total_len = 0;
         for (int t = 0; t < T; ++t) total_len += c->tracks.len[t];

@@ -123,10 +123,11 @@ class BatchPlanner {
             const uint32_t pad_key = (uint32_t)wt[0] << kSlotBits;
             for (int l = 0; l < kBatch; ++l) {
                 const auto &v = lanes_[l];
+                const int o = lane_offset(l, w.count[l]);
                 for (int j = 0; j < w.nsteps; ++j) {
                     Seg &e = segs[w.entry_off + (int64_t)j * kBatch + l];
-                    if (j < w.count[l]) {
-                        const LaneSeg &s = v[p[l] + j];
+                    if (j >= o && j - o < w.count[l]) {
+                        const LaneSeg &s = v[p[l] + (j - o)];
                         const int slot = int(std::lower_bound(wt, wt + w.nslots, s.reg) - wt);
                         e.len = (decltype(e.len))s.len;
                         e.key = ((uint32_t)s.reg << kSlotBits) | (uint32_t)slot;
@@ -141,6 +142,16 @@ class BatchPlanner {
     }
 
   private:
+    // first step of lane l inside a window: staggered so that lanes at one step sit at
+    // different places along their tracks (fewer lanes adding to one LDS tally row at once)
+    int lane_offset(int l, int count) const { return count > 0 ? l % in_.stagger : 0; }
+    int window_steps_of(const std::array<int, kBatch> &count) const {
+        int n = 0;
+        for (int l = 0; l < kBatch; ++l)
+            if (count[l] > 0) n = std::max(n, lane_offset(l, count[l]) + count[l]);
+        return n;
+    }
+
     // windows by step index: lane l takes its segments [k0, k1) (no spatial alignment)
     void step_range(size_t k0, size_t k1) {
         for (int l = 0; l < kBatch; ++l) {
@@ -169,14 +180,14 @@ class BatchPlanner {
             return;
         }
         Window w;
-        w.nsteps = maxn;
         w.nslots = (int)regs_.size();
         w.entry_off = steps_ * kBatch;
         w.tab_off = (int64_t)tab_.size();
         for (int l = 0; l < kBatch; ++l) w.count[l] = int(end_[l] - ptr_[l]);
+        w.nsteps = window_steps_of(w.count);
         tab_.insert(tab_.end(), regs_.begin(), regs_.end());
         windows_.push_back(w);
-        steps_ += maxn;
+        steps_ += w.nsteps;
     }
 
     void range(double lo, double hi, bool last) {
@@ -201,14 +212,14 @@ class BatchPlanner {
             return;
         }
         Window w;
-        w.nsteps = maxn;
         w.nslots = (int)regs_.size();
         w.entry_off = steps_ * kBatch;
         w.tab_off = (int64_t)tab_.size();
         for (int l = 0; l < kBatch; ++l) w.count[l] = int(end_[l] - ptr_[l]);
+        w.nsteps = window_steps_of(w.count);
         tab_.insert(tab_.end(), regs_.begin(), regs_.end());
         windows_.push_back(w);
-        steps_ += maxn;
+        steps_ += w.nsteps;
         for (int l = 0; l < kBatch; ++l) ptr_[l] = end_[l];
     }
 

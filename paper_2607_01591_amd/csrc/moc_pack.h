@@ -46,6 +46,7 @@ struct PackInput {
     std::vector<int> batch_first;   // [nb + 1] first canonical track of each batch
     double window_len = 1.0;        // cm
     int window_steps = 0;           // > 0: windows of this many steps per lane instead of window_len
+    int stagger = 1;                // lane l of a window starts (l mod stagger) steps late
     int cap = 256;                  // maximum tally slots per window
     int n_threads = 1;
     // optional: insert a crossing entry wherever a track enters or leaves a coarse cell;

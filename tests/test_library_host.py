@@ -182,11 +182,13 @@ def _check_packing(prob, precision="f32", **kw):
             assert np.array_equal(tab[sl], rg)      # key region == slot table entry
             L = lg.reshape(n, 64)
             RG = rg.reshape(n, 64)
+            S = kw.get("lane_stagger") or 1
             for l in range(64):
                 real = L[:, l] > 0
                 k = int(real.sum())
-                assert real[:k].all()              # padding only after the real steps
-                lanes[l] += list(zip(uoi[RG[:k, l]], L[:k, l]))
+                f = l % S if k else 0               # staggered start of lane l
+                assert real[f:f + k].all()         # the real steps are one run, padding around
+                lanes[l] += list(zip(uoi[RG[f:f + k, l]], L[f:f + k, l]))
         for l in range(64):
             t = first[b] + l
             if t >= first[b + 1]:
@@ -206,6 +208,9 @@ def _check_packing(prob, precision="f32", **kw):
     ("lattice_mixed", P.square_lattice(3, 2, seed=3, n_azim=32, spacing=0.05, bc=(1, 0, 1, 0)), {}),
     ("lattice_small_cap", P.square_lattice(3, 3, seed=4, n_azim=16, spacing=0.03),
      {"tally_slots": 64, "window_cm": 5.0}),
+    ("lattice_stagger4", P.square_lattice(3, 2, seed=3, n_azim=32, spacing=0.05), {"lane_stagger": 4}),
+    ("lattice_steps_stagger3", P.square_lattice(3, 2, seed=3, n_azim=32, spacing=0.05),
+     {"lane_stagger": 3, "window_steps": 8}),
     ("hex_small", P.hex_assembly(seed=5, rings=3, edge=0.25, G=4, spacing=0.05, n_azim=16), {}),
 ])
 def test_packing_indices_and_sequences(name, prob, kw):
