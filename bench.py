@@ -174,7 +174,7 @@ def main():
     traffic, traffic_src = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_NONPACKED_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_NONPACKED_TFLOPS, "traffic": traffic,
-                "traffic_source": traffic_src, "kernel": "k_sweep<float,3,7,POLY>", "kernel_ms": sweep_ms,
+                "traffic_source": traffic_src, "kernel": "moc::k_sweep<float, 3, 7, 0, false>", "kernel_ms": sweep_ms,
                 "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": U}
     alg_bytes = algorithmic_bytes(info, "f32")
     hbm = {"algorithmic_bytes": alg_bytes, "achieved_GBs": alg_bytes / (sweep_ms * 1e-3) / 1e9,
