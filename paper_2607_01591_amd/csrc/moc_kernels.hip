@@ -136,25 +136,24 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
 #pragma unroll
         for (int j = 0; j < GB; ++j) psi[p][j] = psi_in[(int64_t)((sense * NP + p) * Gp + g0 + j) * nslots + slot];
 
-    // Sigma_t and qhat of a region's group batch: float4 loads when aligned
+    // Sigma_t and qhat of a region's group batch. One code path per instantiation: a
+    // runtime choice between load widths would join two paths right after the loads and
+    // force a wait on them, which defeats the look-ahead below. Even group batches start
+    // on a 16-byte boundary (Gp is a multiple of 4), so they take float4 loads.
     const Real *__restrict__ xsq = reinterpret_cast<const Real *>(args.xsq);
-    constexpr int NQ = (2 * GB + 3) / 4;
-    const bool vec = sizeof(Real) == 4 && ((g0 * 2) & 3) == 0 && g0 + 2 * NQ <= Gp;
     auto load_xs = [&](uint32_t key, Real (&st)[GB], Real (&q)[GB]) {
         const Real *row = xsq + ((int64_t)(key >> kSlotBits) * Gp + g0) * 2;
-        if constexpr (sizeof(Real) == 4) {
-            if (vec) {
-                float4 v[NQ];
+        if constexpr (sizeof(Real) == 4 && GB % 2 == 0) {
+            float4 v[GB / 2];
 #pragma unroll
-                for (int u = 0; u < NQ; ++u) v[u] = reinterpret_cast<const float4 *>(row)[u];
+            for (int u = 0; u < GB / 2; ++u) v[u] = reinterpret_cast<const float4 *>(row)[u];
 #pragma unroll
-                for (int j = 0; j < GB; ++j) {
-                    const float4 &w = v[j >> 1];
-                    st[j] = (j & 1) ? w.z : w.x;
-                    q[j] = (j & 1) ? w.w : w.y;
-                }
-                return;
+            for (int j = 0; j < GB; ++j) {
+                const float4 &w = v[j >> 1];
+                st[j] = (j & 1) ? w.z : w.x;
+                q[j] = (j & 1) ? w.w : w.y;
             }
+        } else if constexpr (sizeof(Real) == 4) {
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
                 const float2 w = reinterpret_cast<const float2 *>(row)[j];
