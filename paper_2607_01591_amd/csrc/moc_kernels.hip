@@ -228,27 +228,20 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
         };
         if constexpr (sizeof(Real) == 4) {
             // software pipeline: segment entries four steps ahead and cross sections two
-            // steps ahead are in flight while the current step computes
-            Seg s0 = ws[step_of(0)], s1 = ws[step_of(clampi(1))], s2 = ws[step_of(clampi(2))],
-                s3 = ws[step_of(clampi(3))];
-            Real st0[GB], q0[GB], st1[GB], q1[GB];
-            load_xs(s0.key, st0, q0);
-            load_xs(s1.key, st1, q1);
-            for (int i = 0; i < n; ++i) {
-                const Seg s4 = ws[step_of(clampi(i + 4))];
-                Real st2[GB], q2[GB];
-                load_xs(s2.key, st2, q2);
-                update(s0, st0, q0);
-                s0 = s1;
-                s1 = s2;
-                s2 = s3;
-                s3 = s4;
+            // steps ahead are in flight while the current step computes; unrolled by four
+            // so every ring slot is a fixed register set (no copies between steps)
+            Seg sg[4];
+            Real st[4][GB], q[4][GB];
 #pragma unroll
-                for (int j = 0; j < GB; ++j) {
-                    st0[j] = st1[j];
-                    q0[j] = q1[j];
-                    st1[j] = st2[j];
-                    q1[j] = q2[j];
+            for (int u = 0; u < 4; ++u) sg[u] = ws[step_of(clampi(u))];
+            load_xs(sg[0].key, st[0], q[0]);
+            load_xs(sg[1].key, st[1], q[1]);
+            for (int i = 0; i < n; i += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    load_xs(sg[(u + 2) & 3].key, st[(u + 2) & 3], q[(u + 2) & 3]);
+                    if (i + u < n) update(sg[u], st[u], q[u]);
+                    sg[u] = ws[step_of(clampi(i + u + 4))];
                 }
             }
         } else {
