@@ -28,13 +28,21 @@ def _coarse_sums(o, n, rc, T):
     return Tc, inflow, outflow
 
 
-@pytest.mark.parametrize("name,prob,grid", [
+def balance_cases():
+    """The problems of the coarse-balance pin (also used by the mutant tests)."""
+    return BALANCE_CASES
+
+
+BALANCE_CASES = [
     ("lattice3x3_vacuum2", P.square_lattice(3, 3, seed=1, n_azim=16, spacing=0.05, bc=(1, 0, 1, 0)), (3, 3)),
     ("lattice_2x2_cells_of_4x4", P.square_lattice(4, 4, seed=6, n_azim=8, spacing=0.08, bc=(0, 0, 0, 0)), (2, 2)),
     ("box_unaligned_cells", P.box_problem(1.3, 0.9, 6, 5, G=2, sigma_t=[[1.0, 2.0]], jitter=0.1,
                                           bc=(0, 1, 0, 1), n_azim=12, spacing=0.04), (3, 2)),
     ("hex_small", P.hex_assembly(seed=5, rings=3, edge=0.25, G=4, spacing=0.05, n_azim=16), (4, 4)),
-])
+]
+
+
+@pytest.mark.parametrize("name,prob,grid", BALANCE_CASES, ids=[c[0] for c in BALANCE_CASES])
 def test_coarse_balance_identity(name, prob, grid):
     """Along every track the tallied increments telescope: summed over the regions of a
     coarse cell they equal the partial current into the cell minus the partial current
