@@ -116,7 +116,7 @@ typedef struct {
     int32_t lane_stagger;/* S > 1: lane l of every tally window starts (l mod S) steps late,
                             so lanes at one step sit at different places along their tracks
                             and fewer of them add to the same LDS tally row at once (costs up
-                            to S - 1 padding steps per window); 1: none; 0: library default */
+                            to S - 1 padding steps per window); 1: none; 0: library default (2) */
 } moc_options;
 
 typedef struct {
@@ -144,15 +144,18 @@ typedef struct {
     double setup_ms;           /* host setup time of moc_create */
     int64_t device_bytes;      /* device memory held by the context */
     int32_t precision;
+    int32_t lane_stagger;      /* lane stagger of the tally windows in use */
 } moc_info;
 
-/* Device-time profile of the sweep kernel, from HIP events recorded on the stream each
- * sweep kernel is launched on (enabled by moc_set_profiling). */
+/* Device-time profile of the sweep kernel and of the CMFD steps, from HIP events recorded
+ * on the stream they are launched on (enabled by moc_set_profiling). */
 typedef struct {
     int64_t sweeps;       /* sweep kernel launches timed since profiling was enabled */
     double sweep_ms;      /* total device time of those launches */
     double sweep_ms_min;  /* shortest launch */
     double sweep_ms_max;  /* longest launch */
+    int64_t cmfd_steps;   /* CMFD steps timed (homogenisation, coarse solve, prolongation) */
+    double cmfd_ms;       /* their total device time */
 } moc_profile;
 
 /* Convergence controls of the CMFD coarse solve (moc_set_coarse_mesh). Zero fields take

@@ -67,9 +67,9 @@ struct moc_ctx {
     double coarse_setup_ms = 0;
     // sweep profiling
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_pool;
-    int64_t prof_n = 0;
-    double prof_ms = 0, prof_min = 0, prof_max = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_pool, prof_cmfd_pending;
+    int64_t prof_n = 0, prof_cmfd_n = 0;
+    double prof_ms = 0, prof_min = 0, prof_max = 0, prof_cmfd_ms = 0;
 
     template <typename T> T *dalloc(size_t n) {
         if (host_only) return nullptr;
@@ -100,11 +100,12 @@ struct moc_ctx {
     }
     ~moc_ctx() {
         if (stream) hipStreamSynchronize(stream);
-        for (auto &e : prof_pending) {
-            hipEventSynchronize(e.second);
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
-        }
+        for (auto *v : {&prof_pending, &prof_cmfd_pending})
+            for (auto &e : *v) {
+                hipEventSynchronize(e.second);
+                hipEventDestroy(e.first);
+                hipEventDestroy(e.second);
+            }
         for (auto &e : prof_pool) {
             hipEventDestroy(e.first);
             hipEventDestroy(e.second);
@@ -121,7 +122,7 @@ static thread_local std::string g_create_error;
 static constexpr int kWarmBoundarySweeps = 2;
 
 // default lane stagger of the tally windows (moc_options.lane_stagger = 0)
-static constexpr int kDefaultLaneStagger = 1;
+static constexpr int kDefaultLaneStagger = 2;
 
 template <typename F> static int guarded(moc_ctx *ctx, F &&f) {
     try {
@@ -431,6 +432,18 @@ static void need_device(const moc_ctx *c) {
     if (c->host_only) throw Error(MOC_ESTATE, "host-only context (negative device ordinal): no device state");
 }
 
+static std::pair<hipEvent_t, hipEvent_t> prof_events(moc_ctx *c) {
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (c->prof_pool.empty()) {
+        HIP_OK(hipEventCreate(&ev.first));
+        HIP_OK(hipEventCreate(&ev.second));
+    } else {
+        ev = c->prof_pool.back();
+        c->prof_pool.pop_back();
+    }
+    return ev;
+}
+
 static void sweep_impl(moc_ctx *c, hipStream_t s) {
     DevProblem &d = c->d;
     launch_fill_f64(d.tally, c->tally_rows * d.Gp, 0.0, s);
@@ -461,13 +474,7 @@ static void sweep_impl(moc_ctx *c, hipStream_t s) {
     a.n_real = d.R;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (c->profiling) {
-        if (c->prof_pool.empty()) {
-            HIP_OK(hipEventCreate(&ev.first));
-            HIP_OK(hipEventCreate(&ev.second));
-        } else {
-            ev = c->prof_pool.back();
-            c->prof_pool.pop_back();
-        }
+        ev = prof_events(c);
         HIP_OK(hipEventRecord(ev.first, s));
     }
     launch_sweep(a, d.precision, d.exp_mode, c->cmfd, d.nb, d.P, d.gb, d.n_gb, s);
@@ -569,6 +576,7 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         launch_scale_f64(d.phi[0], nphi, d.scal + kScalF, s);
         launch_scale_real(d.psi[c->cur_psi], npsi, d.precision, d.scal + kScalF, s);
     }
+    launch_fill_f64(d.scal + kScalRes, 1, 1.0, s);   // no residual yet (the CMFD step reads it)
     int it = 0;
     bool conv = false;
     double res = 1.0, dk = 1.0, k = k0;
@@ -580,7 +588,16 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         launch_finalize(d, phi_new, nullptr, d.partials, s);
         if (c->cmfd && eigen) {
             // CMFD: coarse eigenvalue and rescaled fine flux / incoming boundary flux
+            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+            if (c->profiling) {
+                ev = prof_events(c);
+                HIP_OK(hipEventRecord(ev.first, s));
+            }
             launch_cmfd(d, c->cd, phi_new, d.psi[c->cur_psi], s);
+            if (c->profiling) {
+                HIP_OK(hipEventRecord(ev.second, s));
+                c->prof_cmfd_pending.push_back(ev);
+            }
             launch_fission_partials(d, phi_new, d.partials, s);
             launch_eigen_update(d, d.partials, 3, s);
         } else {
@@ -1100,10 +1117,20 @@ int moc_get_info(const moc_ctx *c, moc_info *info) {
     info->setup_ms = c->setup_ms;
     info->device_bytes = c->device_bytes;
     info->precision = c->d.precision;
+    info->lane_stagger = c->pin.stagger;
     return MOC_OK;
 }
 
 static void drain_profile(moc_ctx *c) {
+    for (auto &e : c->prof_cmfd_pending) {
+        HIP_OK(hipEventSynchronize(e.second));
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, e.first, e.second));
+        c->prof_cmfd_ms += ms;
+        ++c->prof_cmfd_n;
+        c->prof_pool.push_back(e);
+    }
+    c->prof_cmfd_pending.clear();
     for (auto &e : c->prof_pending) {
         HIP_OK(hipEventSynchronize(e.second));
         float ms = 0;
@@ -1123,8 +1150,8 @@ int moc_set_profiling(moc_ctx *c, int enable) {
         need_device(c);
         drain_profile(c);
         c->profiling = enable != 0;
-        c->prof_n = 0;
-        c->prof_ms = c->prof_min = c->prof_max = 0;
+        c->prof_n = c->prof_cmfd_n = 0;
+        c->prof_ms = c->prof_min = c->prof_max = c->prof_cmfd_ms = 0;
     });
 }
 
@@ -1137,6 +1164,8 @@ int moc_get_profile(moc_ctx *c, moc_profile *out) {
         out->sweep_ms = c->prof_ms;
         out->sweep_ms_min = c->prof_min;
         out->sweep_ms_max = c->prof_max;
+        out->cmfd_steps = c->prof_cmfd_n;
+        out->cmfd_ms = c->prof_cmfd_ms;
     });
 }
 

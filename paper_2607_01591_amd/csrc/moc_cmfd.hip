@@ -380,6 +380,12 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
     __syncthreads();
     double k = a.scal[kScalK];
     const double fs = apply_F(a, x, nullptr, 0.0, sh);
+    // coarse accuracy follows the outer iteration: a coarse solve that stops at a fixed
+    // tolerance hands back corrections of that size forever and the outer iteration
+    // stalls short of its fixed point
+    double tol = a.tol;
+    const double res_prev = a.scal[kScalRes];
+    if (res_prev > 0 && isfinite(res_prev)) tol = fmin(tol, fmax(1e-13, 1e-2 * res_prev));
     double inv_ks = 0.0;    // 0: unshifted
     bool shifted = false;
     int outer = 0, inner_total = 0;
@@ -390,7 +396,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
         apply_F(a, x, b, lam, sh);
         for (int64_t i = threadIdx.x; i < N; i += blockDim.x) y[i] = x[i];
         __syncthreads();
-        inner_total += bicgstab(a, b, a.tol * 0.1, a.max_inner, sh);
+        inner_total += bicgstab(a, b, tol * 0.1, a.max_inner, sh);
         const double fy = apply_F(a, y, nullptr, 0.0, sh);
         if (!(fy > 0)) break;
         const double rho = fy / fs;
@@ -407,7 +413,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
         nx = wg_sum(nx, sh);
         const double dk = fabs(knew - k) / knew;
         k = knew;
-        if (dk < a.tol && dx <= a.tol * a.tol * nx) break;
+        if (dk < tol && dx <= tol * tol * nx) break;
         // Wielandt shift once k has settled well inside the shift margin
         if (!shifted && a.shift > 0 && dk < 1e-4) shifted = true;
         if (shifted) inv_ks = 1.0 / (k * (1.0 + a.shift));
@@ -423,6 +429,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
         a.stats[0] = outer > a.max_outer ? a.max_outer : outer;
         a.stats[1] = inner_total;
         a.stats[2] = k;
+        a.stats[3] = tol;
     }
 }
 

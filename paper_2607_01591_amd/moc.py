@@ -62,11 +62,12 @@ class MocInfo(C.Structure):
                 ("n_padded_steps", _i64), ("n_batches", _i32), ("n_windows", _i64),
                 ("n_window_slots", _i64), ("window_cm", _f64), ("max_window_slots", _i32),
                 ("setup_ms", _f64),
-                ("device_bytes", _i64), ("precision", _i32)]
+                ("device_bytes", _i64), ("precision", _i32), ("lane_stagger", _i32)]
 
 
 class MocProfile(C.Structure):
-    _fields_ = [("sweeps", _i64), ("sweep_ms", _f64), ("sweep_ms_min", _f64), ("sweep_ms_max", _f64)]
+    _fields_ = [("sweeps", _i64), ("sweep_ms", _f64), ("sweep_ms_min", _f64), ("sweep_ms_max", _f64),
+                ("cmfd_steps", _i64), ("cmfd_ms", _f64)]
 
 
 class MocCmfdOptions(C.Structure):
@@ -292,7 +293,7 @@ class Solver:
         p = MocProfile()
         self._check(lib().moc_get_profile(self._h, C.byref(p)))
         return dict(sweeps=p.sweeps, sweep_ms=p.sweep_ms, sweep_ms_min=p.sweep_ms_min,
-                    sweep_ms_max=p.sweep_ms_max)
+                    sweep_ms_max=p.sweep_ms_max, cmfd_steps=p.cmfd_steps, cmfd_ms=p.cmfd_ms)
 
     def run_iterations(self, n: int) -> dict:
         """Exactly n power (or source) iterations from a cold start, with one

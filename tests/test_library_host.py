@@ -182,7 +182,7 @@ def _check_packing(prob, precision="f32", **kw):
             assert np.array_equal(tab[sl], rg)      # key region == slot table entry
             L = lg.reshape(n, 64)
             RG = rg.reshape(n, 64)
-            S = kw.get("lane_stagger") or 1
+            S = info["lane_stagger"]
             for l in range(64):
                 real = L[:, l] > 0
                 k = int(real.sum())
