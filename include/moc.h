@@ -168,6 +168,10 @@ typedef struct {
                             (default 0.02; negative: never shift) */
     int32_t max_outer;   /* coarse power iterations per CMFD step (default 20) */
     int32_t max_inner;   /* BiCGSTAB iterations per coarse linear solve (default 200) */
+    int32_t coarse_blocks; /* coarse solve on one 1024-thread workgroup (1) or on a
+                              cooperative grid of this many 256-thread blocks (2..256);
+                              0: one workgroup up to 4096 unknowns (cells x groups), else
+                              one block per 256 unknowns */
 } moc_cmfd_options;
 
 /* Coarse mesh state (moc_get_coarse_info); all zero when no coarse mesh is set. */

@@ -779,7 +779,7 @@ static void free_coarse(moc_ctx *c) {
                     (void *)cd.adj_off, (void *)cd.adj_surf, (void *)cd.adj_nbr, (void *)cd.adj_sign, (void *)cd.adj_L,
                     (void *)cd.adj_h, (void *)cd.adj_hn, (void *)cd.hsum, (void *)cd.Bs, (void *)cd.Binv, (void *)cd.Aoff,
                     (void *)cd.phih, (void *)cd.Dc, (void *)cd.Ldiag, (void *)cd.fchi, (void *)cd.fnsf, (void *)cd.vec,
-                    (void *)cd.ratio, (void *)cd.stats, (void *)cd.piv})
+                    (void *)cd.ratio, (void *)cd.stats, (void *)cd.piv, (void *)cd.red})
         c->dfree(p);
     cd = DevCoarse();
 }
@@ -808,6 +808,7 @@ static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell,
     moc_cmfd_options o{};
     if (opts) o = *opts;
     if (o.tol < 0 || o.max_outer < 0 || o.max_inner < 0) throw Error(MOC_EINVAL, "coarse mesh: negative option");
+    if (o.coarse_blocks < 0 || o.coarse_blocks > 256) throw Error(MOC_EINVAL, "coarse mesh: coarse_blocks must be in 0..256");
     if (d.precision == MOC_PREC_F32 && d.exp_mode != MOC_EXP_POLY)
         throw Error(MOC_EINVAL, "coarse mesh: CMFD currents need the default exponential (exp_mode 0)");
     std::vector<int64_t> count(n_cells, 0);
@@ -940,6 +941,7 @@ static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell,
     cd.shift = o.shift > 0 ? o.shift : (o.shift < 0 ? 0.0 : 0.02);
     cd.max_outer = o.max_outer > 0 ? o.max_outer : 20;
     cd.max_inner = o.max_inner > 0 ? o.max_inner : 200;
+    cd.blocks = o.coarse_blocks;
     if (!c->host_only) {
         const size_t N = (size_t)n_cells * G;
         cd.cell_of = c->upload(cs.cell_of);
@@ -966,6 +968,10 @@ static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell,
         cd.ratio = c->dalloc<double>(N);
         cd.stats = c->dalloc<double>(4);
         cd.piv = c->dalloc<int>(N);
+        cd.red = c->dalloc<double>(3 * 2 * 256);
+        int coop = 0;
+        HIP_OK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
+        cd.grid_ok = coop != 0;
         launch_fill_f64(cd.stats, 4, 0.0, c->stream);
         HIP_OK(hipStreamSynchronize(c->stream));
     }

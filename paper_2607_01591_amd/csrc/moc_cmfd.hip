@@ -19,7 +19,11 @@
 // the coarse problem is small (cells x groups unknowns) and the solver is a chain of
 // dependent reductions, so one compute unit with workgroup barriers beats a chain of
 // grid-wide launches. All arithmetic is FP64.
+#include <algorithm>
 #include <cmath>
+#include <string>
+
+#include <hip/hip_cooperative_groups.h>
 
 #include "moc_kernels.h"
 
@@ -28,19 +32,6 @@ namespace moc {
 namespace {
 
 constexpr int kSolveThreads = 1024;
-
-// sum over the workgroup, returned to every thread
-__device__ double wg_sum(double v, double *sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    const int nw = blockDim.x >> 6;
-    for (int i = 0; i < nw; ++i) t += sh[i];
-    return t;
-}
 
 // ---------------------------------------------------------------- homogenisation
 // One workgroup per coarse cell. Thread (chunk, g) sums over every nch-th region of
@@ -121,17 +112,84 @@ struct SolveArgs {
     const double *adj_sign, *adj_L, *adj_h, *adj_hn;
     double *Bs, *Binv, *Aoff, *phih, *Dc, *Ldiag, *fchi, *fnsf, *vec, *ratio, *stats, *scal;
     int *piv;
+    double *red;               // [3 slots][2 values][kMaxGridBlocks] block partials (grid team)
     double tol, shift;
     int max_outer, max_inner;
 };
 
-// vectors of vec: x (eigenvector), y (solve), r, rh, p, v, s, t, yp, zs
-enum { kVx = 0, kVy, kVr, kVrh, kVp, kVv, kVs, kVt, kVyp, kVzs, kNumVec };
+constexpr int kMaxGridBlocks = 256;
+constexpr int64_t kGridSolveMinUnknowns = 4096;
 
-__device__ void build_blocks(const SolveArgs &a, double inv_ks) {
+// sum of v over the block, returned to every thread of the block (fixed order)
+__device__ double block_sum_all(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) t += sh[i];
+    return t;
+}
+
+// The solver runs either in one workgroup (Team = WG) or in a cooperative grid (Team =
+// GridTeam, grid-wide barriers). Both give every thread the same reduced values, in the
+// same summation order, so every thread takes the same branches.
+struct WG {
+    double *sh;
+    __device__ int64_t tid() const { return threadIdx.x; }
+    __device__ int64_t size() const { return blockDim.x; }
+    __device__ bool leader() const { return threadIdx.x == 0; }
+    __device__ void sync() const { __syncthreads(); }
+    __device__ void sum2(double &a, double &b) {
+        a = block_sum_all(a, sh);
+        b = block_sum_all(b, sh);
+    }
+};
+
+struct GridTeam {
+    double *sh;
+    double *red;
+    int slot;
+    __device__ int64_t tid() const { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+    __device__ int64_t size() const { return (int64_t)gridDim.x * blockDim.x; }
+    __device__ bool leader() const { return blockIdx.x == 0 && threadIdx.x == 0; }
+    __device__ void sync() const { cooperative_groups::this_grid().sync(); }
+    // each block's partials go to a slot, one grid barrier, then every block sums the
+    // slot in the same order; three slots rotate so a slot is rewritten only after every
+    // block has read it (two barriers later)
+    __device__ void sum2(double &a, double &b) {
+        a = block_sum_all(a, sh);
+        b = block_sum_all(b, sh);
+        double *r = red + (size_t)slot * 2 * kMaxGridBlocks;
+        if (threadIdx.x == 0) {
+            r[blockIdx.x] = a;
+            r[kMaxGridBlocks + blockIdx.x] = b;
+        }
+        slot = (slot + 1) % 3;
+        sync();
+        const int nb = gridDim.x;
+        double pa = threadIdx.x < nb ? r[threadIdx.x] : 0.0;
+        double pb = threadIdx.x < nb ? r[kMaxGridBlocks + threadIdx.x] : 0.0;
+        a = block_sum_all(pa, sh);
+        b = block_sum_all(pb, sh);
+    }
+};
+
+template <typename Team> __device__ double team_sum(Team &T, double v) {
+    double z = 0.0;
+    T.sum2(v, z);
+    return v;
+}
+
+// vectors of vec: x (eigenvector), y (solve), r, rh, p (two), v, t, yp, zs
+enum { kVx = 0, kVy, kVr, kVrh, kVp0, kVp1, kVv, kVt, kVyp, kVzs, kNumVec };
+
+template <typename Team> __device__ void build_blocks(Team &T, const SolveArgs &a, double inv_ks) {
     const int C = a.C, G = a.G, HS = 2 + 4 * G + G * G;
     const int64_t N = (int64_t)C * G;
-    for (int64_t i = threadIdx.x; i < N * G; i += blockDim.x) {
+    for (int64_t i = T.tid(); i < N * G; i += T.size()) {
         const int c = int(i / ((int64_t)G * G));
         const int g = int((i / G) % G), gp = int(i % G);
         const double *h = a.hsum + (int64_t)c * HS;
@@ -144,12 +202,13 @@ __device__ void build_blocks(const SolveArgs &a, double inv_ks) {
         v -= a.fchi[(int64_t)c * G + g] * a.fnsf[(int64_t)c * G + gp] * inv_ks;
         a.Bs[i] = v;
     }
-    __syncthreads();
-    // invert each cell's block (Gauss-Jordan, partial pivoting); one thread per cell
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        double *A = a.Bs + (int64_t)c * G * G;      // read-only copy is kept in Bs
-        double *B = a.Binv + (int64_t)c * G * G;
-        // work on B = A, then B <- A^-1 in place with a pivot record in the row order
+    T.sync();
+    // invert each cell's block (Gauss-Jordan with partial pivoting, row swaps undone as
+    // column swaps in reverse order at the end); one thread per cell
+    for (int64_t c = T.tid(); c < C; c += T.size()) {
+        const double *A = a.Bs + c * G * G;
+        double *B = a.Binv + c * G * G;
+        int *piv = a.piv + c * G;
         for (int e = 0; e < G * G; ++e) B[e] = A[e];
         int piv_ok = 1;
         for (int col = 0; col < G; ++col) {
@@ -164,15 +223,13 @@ __device__ void build_blocks(const SolveArgs &a, double inv_ks) {
                 piv_ok = 0;
                 break;
             }
-            // record the swap in the unused space by swapping rows of B only; the inverse
-            // is recovered by swapping columns back at the end (standard in-place GJ)
             if (pr != col)
                 for (int e = 0; e < G; ++e) {
                     const double tmp = B[col * G + e];
                     B[col * G + e] = B[pr * G + e];
                     B[pr * G + e] = tmp;
                 }
-            a.piv[(int64_t)c * G + col] = pr;   // pivot row of this column
+            piv[col] = pr;
             const double inv = 1.0 / B[col * G + col];
             B[col * G + col] = 1.0;
             for (int e = 0; e < G; ++e) B[col * G + e] *= inv;
@@ -186,7 +243,7 @@ __device__ void build_blocks(const SolveArgs &a, double inv_ks) {
         }
         if (piv_ok) {
             for (int col = G - 1; col >= 0; --col) {
-                const int pr = a.piv[(int64_t)c * G + col];
+                const int pr = piv[col];
                 if (pr != col)
                     for (int r = 0; r < G; ++r) {
                         const double tmp = B[r * G + col];
@@ -198,54 +255,54 @@ __device__ void build_blocks(const SolveArgs &a, double inv_ks) {
             // singular block: fall back to the inverse diagonal
             for (int e = 0; e < G * G; ++e) B[e] = 0.0;
             for (int g = 0; g < G; ++g) {
-                const double d = A[g * G + g];
-                B[g * G + g] = d != 0.0 ? 1.0 / d : 0.0;
+                const double dd = A[g * G + g];
+                B[g * G + g] = dd != 0.0 ? 1.0 / dd : 0.0;
             }
         }
     }
-    __syncthreads();
+    T.sync();
 }
 
-// out = A x (shifted coarse operator)
-__device__ void matvec(const SolveArgs &a, const double *x, double *out) {
-    const int C = a.C, G = a.G;
-    const int64_t N = (int64_t)C * G;
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-        const int c = int(i / G), g = int(i - (int64_t)c * G);
-        const double *B = a.Bs + ((int64_t)c * G + g) * G;
-        const double *xc = x + (int64_t)c * G;
-        double s = 0.0;
-        for (int gp = 0; gp < G; ++gp) s += B[gp] * xc[gp];
-        for (int64_t k = a.adj_off[c]; k < a.adj_off[c + 1]; ++k) {
-            const int j = a.adj_nbr[k];
-            if (j >= 0) s += a.Aoff[k * G + g] * x[(int64_t)j * G + g];
-        }
-        out[i] = s;
+// row i of A x (shifted coarse operator)
+__device__ __forceinline__ double row_apply(const SolveArgs &a, const double *x, int64_t i) {
+    const int G = a.G;
+    const int c = int(i / G), g = int(i - (int64_t)c * G);
+    const double *B = a.Bs + i * G;
+    const double *xc = x + (int64_t)c * G;
+    double s = 0.0;
+    for (int gp = 0; gp < G; ++gp) s += B[gp] * xc[gp];
+    for (int64_t k = a.adj_off[c]; k < a.adj_off[c + 1]; ++k) {
+        const int j = a.adj_nbr[k];
+        if (j >= 0) s += a.Aoff[k * G + g] * x[(int64_t)j * G + g];
     }
-    __syncthreads();
+    return s;
 }
 
-__device__ void precond(const SolveArgs &a, const double *x, double *out) {
-    const int C = a.C, G = a.G;
-    const int64_t N = (int64_t)C * G;
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-        const int c = int(i / G), g = int(i - (int64_t)c * G);
-        const double *B = a.Binv + ((int64_t)c * G + g) * G;
-        const double *xc = x + (int64_t)c * G;
-        double s = 0.0;
-        for (int gp = 0; gp < G; ++gp) s += B[gp] * xc[gp];
-        out[i] = s;
+// row i of the block-Jacobi preconditioner applied to u = r + beta (p - omega v) built on
+// the fly from the cell's entries (so no barrier is needed between forming u and using it)
+__device__ __forceinline__ double row_precond_lin(const SolveArgs &a, int64_t i, const double *r, const double *p,
+                                                  const double *v, double beta, double omega, double *u_out) {
+    const int G = a.G;
+    const int c = int(i / G);
+    const double *B = a.Binv + i * G;
+    const int64_t c0 = (int64_t)c * G;
+    double s = 0.0;
+    for (int gp = 0; gp < G; ++gp) {
+        const double u = r[c0 + gp] + beta * (p[c0 + gp] - omega * v[c0 + gp]);
+        s += B[gp] * u;
     }
-    __syncthreads();
+    u_out[i] = r[i] + beta * (p[i] - omega * v[i]);
+    return s;
 }
 
-// (F x)_c,g = fchi_c,g sum_g' fnsf_c,g' x_c,g'; returns sum of F x, writes it to out if given
-__device__ double apply_F(const SolveArgs &a, const double *x, double *out, double scale, double *sh) {
-    const int C = a.C, G = a.G;
-    const int64_t N = (int64_t)C * G;
+// (F x)_c,g = fchi_c,g sum_g' fnsf_c,g' x_c,g'; returns sum of F x, writes scale F x if out
+template <typename Team>
+__device__ double apply_F(Team &T, const SolveArgs &a, const double *x, double *out, double scale) {
+    const int G = a.G;
+    const int64_t N = (int64_t)a.C * G;
     double tot = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-        const int c = int(i / G), g = int(i - (int64_t)c * G);
+    for (int64_t i = T.tid(); i < N; i += T.size()) {
+        const int c = int(i / G);
         const double *fn = a.fnsf + (int64_t)c * G;
         const double *xc = x + (int64_t)c * G;
         double f = 0.0;
@@ -254,90 +311,104 @@ __device__ double apply_F(const SolveArgs &a, const double *x, double *out, doub
         if (out) out[i] = scale * v;
         tot += v;
     }
-    const double s = wg_sum(tot, sh);
-    __syncthreads();
-    return s;
+    return team_sum(T, tot);   // the reduction's barrier also publishes out
 }
 
 // BiCGSTAB (right block-Jacobi preconditioning) on A y = b, y holds the initial guess;
-// stops at ||r|| <= rtol ||b||. Returns the iterations taken.
-__device__ int bicgstab(const SolveArgs &a, const double *b, double rtol, int max_it, double *sh) {
+// stops at ||r|| <= rtol ||b||. Returns the iterations taken. Barriers: one per
+// reduction (four per iteration) plus one before each product with A.
+template <typename Team> __device__ int bicgstab(Team &T, const SolveArgs &a, const double *b, double rtol, int max_it) {
     const int64_t N = (int64_t)a.C * a.G;
     double *V = a.vec;
-    double *y = V + kVy * N, *r = V + kVr * N, *rh = V + kVrh * N, *p = V + kVp * N, *v = V + kVv * N;
-    double *s = V + kVs * N, *t = V + kVt * N, *yp = V + kVyp * N, *zs = V + kVzs * N;
-    matvec(a, y, t);
+    double *y = V + kVy * N, *r = V + kVr * N, *rh = V + kVrh * N, *v = V + kVv * N;
+    double *t = V + kVt * N, *yp = V + kVyp * N, *zs = V + kVzs * N;
+    double *pa = V + kVp0 * N, *pb = V + kVp1 * N;
     double bb = 0.0, rr = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-        const double ri = b[i] - t[i];
+    for (int64_t i = T.tid(); i < N; i += T.size()) {
+        const double ri = b[i] - row_apply(a, y, i);
         r[i] = ri;
         rh[i] = ri;
-        p[i] = 0.0;
+        pa[i] = 0.0;
         v[i] = 0.0;
         bb += b[i] * b[i];
         rr += ri * ri;
     }
-    bb = wg_sum(bb, sh);
-    rr = wg_sum(rr, sh);
+    T.sum2(bb, rr);
     const double stop = rtol * rtol * bb;
     if (rr <= stop) return 0;
     double rho = 1.0, alpha = 1.0, omega = 1.0;
+    double rn = rr;   // (rh, r) with rh = r
     int it = 0;
     for (it = 1; it <= max_it; ++it) {
-        double rn = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) rn += rh[i] * r[i];
-        rn = wg_sum(rn, sh);
         if (rn == 0.0 || omega == 0.0) break;   // breakdown: keep the current y
         const double beta = (rn / rho) * (alpha / omega);
         rho = rn;
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) p[i] = r[i] + beta * (p[i] - omega * v[i]);
-        __syncthreads();
-        precond(a, p, yp);
-        matvec(a, yp, v);
-        double rv = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) rv += rh[i] * v[i];
-        rv = wg_sum(rv, sh);
+        // p_new = r + beta (p - omega v) and yp = K^-1 p_new, cell by cell
+        for (int64_t i = T.tid(); i < N; i += T.size()) yp[i] = row_precond_lin(a, i, r, pa, v, beta, omega, pb);
+        T.sync();
+        double rv = 0.0, z0 = 0.0;
+        for (int64_t i = T.tid(); i < N; i += T.size()) {
+            const double vi = row_apply(a, yp, i);
+            v[i] = vi;
+            rv += rh[i] * vi;
+        }
+        T.sum2(rv, z0);
         if (rv == 0.0) break;
         alpha = rho / rv;
-        double ss = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-            y[i] += alpha * yp[i];
+        // s = r - alpha v (kept in r's place is not possible: zs needs the cell's s),
+        // zs = K^-1 s from the cell's entries
+        double ss = 0.0, z1 = 0.0;
+        for (int64_t i = T.tid(); i < N; i += T.size()) {
+            const int c = int(i / a.G);
+            const int64_t c0 = (int64_t)c * a.G;
+            const double *Bi = a.Binv + i * a.G;
+            double z = 0.0;
+            for (int gp = 0; gp < a.G; ++gp) z += Bi[gp] * (r[c0 + gp] - alpha * v[c0 + gp]);
+            zs[i] = z;
             const double si = r[i] - alpha * v[i];
-            s[i] = si;
             ss += si * si;
         }
-        ss = wg_sum(ss, sh);
-        if (ss <= stop) break;
-        precond(a, s, zs);
-        matvec(a, zs, t);
-        double ts = 0.0, tt = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-            ts += t[i] * s[i];
-            tt += t[i] * t[i];
+        T.sum2(ss, z1);
+        if (ss <= stop) {
+            for (int64_t i = T.tid(); i < N; i += T.size()) y[i] += alpha * yp[i];
+            T.sync();
+            break;
         }
-        ts = wg_sum(ts, sh);
-        tt = wg_sum(tt, sh);
+        double ts = 0.0, tt = 0.0;
+        for (int64_t i = T.tid(); i < N; i += T.size()) {
+            const double ti = row_apply(a, zs, i);
+            t[i] = ti;
+            const double si = r[i] - alpha * v[i];
+            ts += ti * si;
+            tt += ti * ti;
+        }
+        T.sum2(ts, tt);
         omega = tt > 0.0 ? ts / tt : 0.0;
         rr = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-            y[i] += omega * zs[i];
-            const double ri = s[i] - omega * t[i];
+        rn = 0.0;
+        for (int64_t i = T.tid(); i < N; i += T.size()) {
+            y[i] += alpha * yp[i] + omega * zs[i];
+            const double ri = r[i] - alpha * v[i] - omega * t[i];
             r[i] = ri;
             rr += ri * ri;
+            rn += rh[i] * ri;
         }
-        rr = wg_sum(rr, sh);
+        T.sum2(rr, rn);
+        // the new p lives in pb: swap the roles of the two p buffers
+        double *tmp = pa;
+        pa = pb;
+        pb = tmp;
         if (rr <= stop) break;
     }
-    __syncthreads();
+    T.sync();
     return it;
 }
 
-__global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
-    __shared__ double sh[kSolveThreads / 64];
+template <typename Team> __device__ void coarse_solve(Team &T, const SolveArgs &a) {
     const int C = a.C, G = a.G, HS = 2 + 4 * G + G * G;
     const int64_t N = (int64_t)C * G;
     // homogenised flux, diffusion coefficients, fission operator factors
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    for (int64_t i = T.tid(); i < N; i += T.size()) {
         const int c = int(i / G), g = int(i - (int64_t)c * G);
         const double *h = a.hsum + (int64_t)c * HS;
         const double Vc = h[0], Vphi = h[2 + g], Vst = h[2 + G + g];
@@ -346,9 +417,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
         a.fchi[i] = h[1] > 0 ? h[2 + 3 * G + g] / h[1] : 0.0;
         a.fnsf[i] = (Vphi > 0 && Vc > 0) ? h[2 + 2 * G + g] / (Vphi / Vc) : 0.0;
     }
-    __syncthreads();
+    T.sync();
     // surface coefficients: Dhat, Dtilde from the net currents; leakage diagonal
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    for (int64_t i = T.tid(); i < N; i += T.size()) {
         const int c = int(i / G), g = int(i - (int64_t)c * G);
         const double phc = a.phih[i], Di = a.Dc[i];
         double diag = 0.0;
@@ -371,15 +442,13 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
         }
         a.Ldiag[i] = diag;
     }
-    __syncthreads();
-
     double *V = a.vec;
     double *x = V + kVx * N, *y = V + kVy * N;
     double *b = a.ratio;   // right-hand side; the ratios are written only at the end
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) x[i] = a.phih[i];
-    __syncthreads();
+    for (int64_t i = T.tid(); i < N; i += T.size()) x[i] = a.phih[i];
+    T.sync();
     double k = a.scal[kScalK];
-    const double fs = apply_F(a, x, nullptr, 0.0, sh);
+    const double fs = apply_F(T, a, x, nullptr, 0.0);
     // coarse accuracy follows the outer iteration: a coarse solve that stops at a fixed
     // tolerance hands back corrections of that size forever and the outer iteration
     // stalls short of its fixed point
@@ -390,27 +459,25 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
     bool shifted = false;
     int outer = 0, inner_total = 0;
     for (outer = 1; outer <= a.max_outer && fs > 0; ++outer) {
-        if (outer == 1 || shifted) build_blocks(a, inv_ks);
+        if (outer == 1 || shifted) build_blocks(T, a, inv_ks);
         const double lam = 1.0 / k - inv_ks;
         // A y = lam F x from y = x
-        apply_F(a, x, b, lam, sh);
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) y[i] = x[i];
-        __syncthreads();
-        inner_total += bicgstab(a, b, tol * 0.1, a.max_inner, sh);
-        const double fy = apply_F(a, y, nullptr, 0.0, sh);
+        for (int64_t i = T.tid(); i < N; i += T.size()) y[i] = x[i];
+        apply_F(T, a, x, b, lam);
+        inner_total += bicgstab(T, a, b, tol * 0.1, a.max_inner);
+        const double fy = apply_F(T, a, y, nullptr, 0.0);
         if (!(fy > 0)) break;
         const double rho = fy / fs;
         const double knew = 1.0 / (inv_ks + lam / rho);
         double dx = 0.0, nx = 0.0;
         const double sc = fs / fy;
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+        for (int64_t i = T.tid(); i < N; i += T.size()) {
             const double yi = y[i] * sc;
             dx += (yi - x[i]) * (yi - x[i]);
             nx += yi * yi;
             x[i] = yi;
         }
-        dx = wg_sum(dx, sh);
-        nx = wg_sum(nx, sh);
+        T.sum2(dx, nx);
         const double dk = fabs(knew - k) / knew;
         k = knew;
         if (dk < tol && dx <= tol * tol * nx) break;
@@ -418,12 +485,12 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
         if (!shifted && a.shift > 0 && dk < 1e-4) shifted = true;
         if (shifted) inv_ks = 1.0 / (k * (1.0 + a.shift));
     }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    T.sync();
+    for (int64_t i = T.tid(); i < N; i += T.size()) {
         const double ph = a.phih[i];
         a.ratio[i] = ph > 0 ? x[i] / ph : 1.0;
     }
-    if (threadIdx.x == 0) {
+    if (T.leader()) {
         a.scal[kScalKPrev] = a.scal[kScalK];
         if (fs > 0 && k > 0 && isfinite(k)) a.scal[kScalK] = k;
         a.stats[0] = outer > a.max_outer ? a.max_outer : outer;
@@ -431,6 +498,19 @@ __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
         a.stats[2] = k;
         a.stats[3] = tol;
     }
+}
+
+__global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
+    __shared__ double sh[kSolveThreads / 64];
+    WG T{sh};
+    coarse_solve(T, a);
+}
+
+// the same solve over a cooperative grid (launched with hipLaunchCooperativeKernel)
+__global__ __launch_bounds__(256) void k_cmfd_solve_grid(SolveArgs a) {
+    __shared__ double sh[4];
+    GridTeam T{sh, a.red, 0};
+    coarse_solve(T, a);
 }
 
 // phi *= ratio(cell of the region); incoming psi *= ratio(cell of the track's first region)
@@ -503,13 +583,28 @@ void launch_cmfd(const DevProblem &d, const DevCoarse &cd, double *phi, void *ps
     a.ratio = cd.ratio;
     a.stats = cd.stats;
     a.piv = cd.piv;
+    a.red = cd.red;
     a.scal = d.scal;
     a.tol = cd.tol;
     a.shift = cd.shift;
     a.max_outer = cd.max_outer;
     a.max_inner = cd.max_inner;
-    hipLaunchKernelGGL(k_cmfd_solve, dim3(1), dim3(kSolveThreads), 0, s, a);
-    CMFD_CHECK_LAUNCH();
+    // large coarse problems: the same solve spread over a cooperative grid (one block of
+    // 256 threads per 256 unknowns, at most kMaxGridBlocks); small ones: one workgroup,
+    // whose barriers are cheaper than grid-wide ones
+    const int64_t N = (int64_t)cd.C * d.G;
+    int nb = cd.blocks;
+    if (nb == 0) nb = N > kGridSolveMinUnknowns ? (int)std::min<int64_t>(kMaxGridBlocks, (N + 255) / 256) : 1;
+    if (nb > 1 && !cd.grid_ok) throw Error(MOC_EINVAL, "cmfd: the device does not support cooperative launches");
+    if (nb > 1) {
+        void *args[] = {&a};
+        const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cmfd_solve_grid), dim3(nb),
+                                                        dim3(256), args, 0, s);
+        if (e != hipSuccess) throw Error(MOC_EHIP, std::string("cmfd: cooperative launch failed: ") + hipGetErrorString(e));
+    } else {
+        hipLaunchKernelGGL(k_cmfd_solve, dim3(1), dim3(kSolveThreads), 0, s, a);
+        CMFD_CHECK_LAUNCH();
+    }
     const int64_t n = (int64_t)d.R * d.G + (int64_t)2 * d.P * d.Gp * d.nslots;
     int64_t grid = (n + 255) / 256;
     if (grid > 8192) grid = 8192;

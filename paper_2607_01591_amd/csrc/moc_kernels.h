@@ -92,6 +92,9 @@ struct DevCoarse {
     double *ratio = nullptr;          // [C][G]
     double *stats = nullptr;          // [4] outer, inner iterations, coarse k
     int *piv = nullptr;               // [C][G]
+    double *red = nullptr;            // [3][2][256] block partials of the cooperative solve
+    bool grid_ok = false;             // the device supports cooperative launches
+    int blocks = 0;                   // coarse solve blocks (0 automatic, 1 one workgroup)
     double tol = 1e-5, shift = 0.02;
     int max_outer = 20, max_inner = 200;
 };

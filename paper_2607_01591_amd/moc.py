@@ -71,7 +71,8 @@ class MocProfile(C.Structure):
 
 
 class MocCmfdOptions(C.Structure):
-    _fields_ = [("tol", _f64), ("shift", _f64), ("max_outer", _i32), ("max_inner", _i32)]
+    _fields_ = [("tol", _f64), ("shift", _f64), ("max_outer", _i32), ("max_inner", _i32),
+                ("coarse_blocks", _i32)]
 
 
 class MocCoarseInfo(C.Structure):
@@ -319,10 +320,10 @@ class Solver:
         self.info = {k: getattr(inf, k) for k, _ in MocInfo._fields_}
 
     def set_coarse_mesh(self, n_cells: int, region_cell=None, tol: float = 0.0, shift: float = 0.0,
-                        max_outer: int = 0, max_inner: int = 0):
+                        max_outer: int = 0, max_inner: int = 0, coarse_blocks: int = 0):
         """CMFD on a coarse mesh: region_cell [R] (user order) assigns regions to cells;
         n_cells = 0 removes it. Zero options take the library defaults."""
-        o = MocCmfdOptions(float(tol), float(shift), int(max_outer), int(max_inner))
+        o = MocCmfdOptions(float(tol), float(shift), int(max_outer), int(max_inner), int(coarse_blocks))
         if n_cells <= 0 or region_cell is None:
             self._check(lib().moc_set_coarse_mesh(self._h, 0, None, C.byref(o)))
         else:

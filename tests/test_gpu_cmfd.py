@@ -96,15 +96,17 @@ def test_surface_currents_match_oracle(name, make, grid, precision, cuda):
     assert rel_err(phi, phi_ref) < (1e-11 if precision == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("blocks", [1, 3], ids=["one_workgroup", "grid3"])
 @pytest.mark.parametrize("name,make,grid", CASES[:2], ids=[c[0] for c in CASES[:2]])
-def test_one_cmfd_iteration_matches_oracle(name, make, grid, cuda):
-    log(f"[cmfd one iteration] {name}")
+def test_one_cmfd_iteration_matches_oracle(name, make, grid, blocks, cuda):
+    """Both coarse-solve paths (one workgroup; a cooperative grid of blocks)."""
+    log(f"[cmfd one iteration] {name} blocks={blocks}")
     prob = make()
     n, rc = P.coarse_cells(prob, *grid)
     ref = CM.solve(Oracle.from_problem(prob), prob, tol=1e-30, max_iter=2, n_cells=n, region_cell=rc,
                    history=True)
     s = moc.Solver(prob, precision="f64")
-    s.set_coarse_mesh(n, rc, tol=1e-11, max_outer=500, max_inner=500)
+    s.set_coarse_mesh(n, rc, tol=1e-11, max_outer=500, max_inner=500, coarse_blocks=blocks)
     for it in (1, 2):
         r = s.run_iterations(it)
         phi = _host(s.flux())
@@ -146,15 +148,37 @@ def test_cmfd_reaches_plain_fixed_point_in_fewer_sweeps(precision, cuda):
     assert abs(again["k"] - plain["k"]) < (1e-11 if precision == "f64" else 1e-6)
 
 
-def test_cmfd_solution_matches_oracle_fixed_point(cuda):
+@pytest.mark.parametrize("blocks", [0, 2])
+def test_cmfd_solution_matches_oracle_fixed_point(blocks, cuda):
     """FP64 CMFD solve against the oracle's plain power iteration at a tight tolerance."""
-    log("[cmfd vs oracle fixed point]")
+    log(f"[cmfd vs oracle fixed point] blocks={blocks}")
     prob = P.square_lattice(3, 3, seed=2, n_azim=16, spacing=0.05, bc=(1, 0, 1, 0))
     n, rc = P.coarse_cells(prob, 3, 3)
     ref = Oracle.from_problem(prob).solve(tol=1e-10, max_iter=5000)
     s = moc.Solver(prob, precision="f64")
-    s.set_coarse_mesh(n, rc)
+    s.set_coarse_mesh(n, rc, coarse_blocks=blocks)
     r = s.solve(1e-10)
     assert r["converged"]
     assert abs(r["k"] - ref["k"]) < 1e-8
     assert rel_err(_host(s.flux()), ref["phi"]) < 1e-7
+
+
+def test_cmfd_grid_and_workgroup_paths_agree_on_a_larger_lattice(cuda):
+    """17 x 17 pin cells (2023 coarse unknowns): the cooperative-grid coarse solve and the
+    one-workgroup solve reach the same converged answer, which is the plain iteration's."""
+    log("[cmfd grid vs workgroup] 17x17")
+    prob = P.config(2)
+    n, rc = P.coarse_cells(prob, 17, 17)
+    s = moc.Solver(prob, precision="f64", max_iter=5000)
+    out = {}
+    for blocks in (1, 8):
+        s.set_coarse_mesh(n, rc, coarse_blocks=blocks)
+        r = s.solve(1e-9)
+        assert r["converged"]
+        out[blocks] = (r, _host(s.flux()))
+        log(f"  blocks {blocks}: {r['iterations']} iterations, k {r['k']:.10f}, {r['wall_ms']:.0f} ms")
+    assert abs(out[1][0]["k"] - out[8][0]["k"]) < 1e-9
+    assert rel_err(out[8][1], out[1][1]) < 1e-7
+    s.set_coarse_mesh(0)
+    plain = s.solve(1e-9)
+    assert abs(plain["k"] - out[8][0]["k"]) < 2e-8
