@@ -576,7 +576,7 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         launch_scale_f64(d.phi[0], nphi, d.scal + kScalF, s);
         launch_scale_real(d.psi[c->cur_psi], npsi, d.precision, d.scal + kScalF, s);
     }
-    launch_fill_f64(d.scal + kScalRes, 1, 1.0, s);   // no residual yet (the CMFD step reads it)
+    launch_fill_f64(d.scal + kScalRes, 2, 1.0, s);   // no residual or dk yet (the CMFD step reads them)
     int it = 0;
     bool conv = false;
     double res = 1.0, dk = 1.0, k = k0;

@@ -455,8 +455,12 @@ template <typename Team> __device__ void coarse_solve(Team &T, const SolveArgs &
     double tol = a.tol;
     const double res_prev = a.scal[kScalRes];
     if (res_prev > 0 && isfinite(res_prev)) tol = fmin(tol, fmax(1e-13, 1e-2 * res_prev));
-    double inv_ks = 0.0;    // 0: unshifted
-    bool shifted = false;
+    // Wielandt shift from the start once the outer iteration's k has settled (|dk| of the
+    // last power iteration well inside the shift margin); otherwise after the first
+    // coarse iterations have settled it
+    const double dk_prev = a.scal[kScalDk];
+    bool shifted = a.shift > 0 && isfinite(dk_prev) && dk_prev < 1e-4 * k;
+    double inv_ks = shifted ? 1.0 / (k * (1.0 + a.shift)) : 0.0;    // 0: unshifted
     int outer = 0, inner_total = 0;
     for (outer = 1; outer <= a.max_outer && fs > 0; ++outer) {
         if (outer == 1 || shifted) build_blocks(T, a, inv_ks);
