@@ -74,6 +74,11 @@ int cnn_gather_rows(const float *table, const int32_t *idx, int64_t npix, int32_
 int cnn_gather_log(const double *table, const int32_t *idx, int64_t npix, int32_t C, int32_t Cp,
                    float *out, void *stream);
 
+/* Training targets as a shape: for each of n_images images FP32 [npix][Cp] (in place),
+ * subtract the mean over its pixels and channels [0, C) from those entries. The solver
+ * rescales any guess, so only the shape of log(phi) is worth learning. */
+int cnn_center(float *img, int64_t n_images, int64_t npix, int32_t C, int32_t Cp, void *stream);
+
 /* De-rasterise: for each of n points with pixel coordinates (u, v) (x then y, pixel
  * centres at integers), bilinear interpolation of img FP32 [H][W][Cs] channels [0, C),
  * clamped at the border; out FP64 [n][C] = exp(value) if apply_exp else value. */

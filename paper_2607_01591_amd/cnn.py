@@ -25,6 +25,7 @@ SIGNATURES = {
     "cnn_gather_rows": [_vp, _vp, _i64, _i32, _i32, _vp, _vp],
     "cnn_gather_log": [_vp, _vp, _i64, _i32, _i32, _vp, _vp],
     "cnn_bilinear_sample": [_vp, _i32, _i32, _i32, _i32, _vp, _i64, _i32, _vp, _vp],
+    "cnn_center": [_vp, _i64, _i64, _i32, _i32, _vp],
 }
 
 _lib = None
@@ -112,6 +113,13 @@ def gather_rows(table, idx, Cp, out, stream=None):
 def gather_log(table, idx, Cp, out, stream=None):
     _ok(lib().cnn_gather_log(_p(table), _p(idx), idx.numel(), table.shape[-1], Cp, _p(out), _s(stream)),
         "cnn_gather_log")
+
+
+def center(img, C_used, stream=None):
+    """In place: subtract each image's mean over pixels and channels [0, C_used)."""
+    n = img.shape[0]
+    npix = img.numel() // (n * img.shape[-1])
+    _ok(lib().cnn_center(_p(img), n, npix, C_used, img.shape[-1], _s(stream)), "cnn_center")
 
 
 def bilinear(img, C_used, uv, out, apply_exp=True, stream=None):

@@ -224,6 +224,29 @@ __global__ void k_gather_log(const double *__restrict__ table, const int32_t *__
     }
 }
 
+// subtract, per image, the mean over its pixels and channels [0, C) from those entries
+// (one 1024-thread block per image, fixed summation order)
+__global__ __launch_bounds__(1024) void k_center(float *__restrict__ img, int64_t npix, int C, int Cp) {
+    __shared__ double sh[16];
+    float *x = img + (int64_t)blockIdx.x * npix * Cp;
+    const int64_t n = npix * C;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t p = i / C;
+        acc += (double)x[p * Cp + (i - p * C)];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    double tot = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += sh[w];
+    const float mean = (float)(tot / (double)n);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t p = i / C;
+        x[p * Cp + (i - p * C)] -= mean;
+    }
+}
+
 __global__ void k_bilinear(const float *__restrict__ img, int H, int W, int Cs, int C, const float *__restrict__ uv, int64_t n,
                            int apply_exp, double *__restrict__ out) {
     const int64_t tot = n * C;
@@ -328,6 +351,12 @@ int cnn_gather_log(const double *table, const int32_t *idx, int64_t npix, int32_
     if (!table || !idx || !out || npix <= 0 || C <= 0 || Cp < C) return MOC_EINVAL;
     hipLaunchKernelGGL(k_gather_log, dim3(grid_for(npix * Cp, 256)), dim3(256), 0, (hipStream_t)stream, table, idx, npix, C, Cp,
                        out);
+    return launched();
+}
+
+int cnn_center(float *img, int64_t n_images, int64_t npix, int32_t C, int32_t Cp, void *stream) {
+    if (!img || n_images <= 0 || npix <= 0 || C <= 0 || Cp < C || n_images > 65535) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_center, dim3((unsigned)n_images), dim3(1024), 0, (hipStream_t)stream, img, npix, C, Cp);
     return launched();
 }
 

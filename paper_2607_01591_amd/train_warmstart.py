@@ -78,6 +78,7 @@ def main(argv=None):
             iters.append(r["iterations"])
             ws.rasterize(p, out=X[i:i + 1])
             ws.target(solver.flux(), out=T[i:i + 1])
+            cnn.center(T[i:i + 1], base.n_groups)
             if i % 8 == 0 or i == len(seeds) - 1:
                 log(f"{tag} {i + 1}/{len(seeds)} seed {sd}: {r['iterations']} it, k={r['k']:.5f}, "
                     f"{time.perf_counter() - t0:.0f} s")

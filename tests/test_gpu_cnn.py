@@ -154,3 +154,19 @@ def test_gather_and_bilinear(cuda):
         return ((1 - fy) * ((1 - fx) * img[y0, x0] + fx * img[y0, x0 + 1])
                 + fy * ((1 - fx) * img[y0 + 1, x0] + fx * img[y0 + 1, x0 + 1]))[:3]
     np.testing.assert_allclose(o.cpu().numpy(), np.array([bil(*p) for p in uv]), rtol=1e-6, atol=1e-6)
+
+
+def test_center_matches_numpy(cuda):
+    """cnn_center: per image, the mean over pixels and used channels is removed from
+    those entries; padded channels are left alone."""
+    import torch
+    from paper_2607_01591_amd import cnn
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(3, 20, 17, 8)).astype(np.float32)
+    t = torch.as_tensor(x, device=cuda)
+    cnn.center(t, 7)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    ref = x.astype(np.float64)
+    ref[..., :7] -= ref[..., :7].reshape(3, -1).mean(axis=1)[:, None, None, None]
+    np.testing.assert_allclose(got, ref, rtol=0, atol=2e-6)
