@@ -454,7 +454,7 @@ template <typename Team> __device__ void coarse_solve(Team &T, const SolveArgs &
     // stalls short of its fixed point
     double tol = a.tol;
     const double res_prev = a.scal[kScalRes];
-    if (res_prev > 0 && isfinite(res_prev)) tol = fmin(tol, fmax(1e-13, 1e-2 * res_prev));
+    if (res_prev > 0 && isfinite(res_prev)) tol = fmin(tol, fmax(1e-13, 0.1 * res_prev));
     // Wielandt shift from the start once the outer iteration's k has settled (|dk| of the
     // last power iteration well inside the shift margin); otherwise after the first
     // coarse iterations have settled it

@@ -129,6 +129,17 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     for (int p = 0; p < NP; ++p) {
         c[p] = coef[a * NP + p];
         is[p] = kX ? Real(-1.4426950408889634) * inv_sin[p] : inv_sin[p];
+        // Keep these wave-uniform constants in vector registers. Left in the scalar
+        // registers their loads fill, their first use inside the step loop makes the
+        // compiler wait on the counter that scalar loads share with LDS operations at
+        // every step, which also waits for the previous step's LDS tally atomics.
+        if constexpr (sizeof(Real) == 4) {
+            asm volatile("v_mov_b32 %0, %1" : "=v"(c[p]) : "s"(c[p]));
+            asm volatile("v_mov_b32 %0, %1" : "=v"(is[p]) : "s"(is[p]));
+        } else {
+            asm volatile("v_mov_b64 %0, %1" : "=v"(c[p]) : "s"(c[p]));
+            asm volatile("v_mov_b64 %0, %1" : "=v"(is[p]) : "s"(is[p]));
+        }
     }
     Real psi[NP][GB];
 #pragma unroll
