@@ -144,6 +144,26 @@ template <typename F> static int guarded(moc_ctx *ctx, F &&f) {
     }
 }
 
+// Workgroups are handed to the chip's 8 XCDs round robin by their linear index, and each
+// XCD has its own L2. Order 0 gives XCD x (the workgroup columns x, x + 8, ...) one
+// contiguous range of batches, i.e. neighbouring tracks whose segments gather the same
+// regions' cross sections; order 1 keeps batch = column.
+static constexpr int kXcds = 8;
+static std::vector<int> make_batch_order(int nb, int order) {
+    std::vector<int> b(nb);
+    if (order == 1) {
+        for (int i = 0; i < nb; ++i) b[i] = i;
+        return b;
+    }
+    int start = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        const int count = nb > x ? (nb - x + kXcds - 1) / kXcds : 0;   // columns i = x mod 8
+        for (int k = 0; k < count; ++k) b[x + kXcds * k] = start + k;
+        start += count;
+    }
+    return b;
+}
+
 static int choose_group_batch(int G) {
     if (G == 1 || G == 2 || G == 4 || G == 7 || G == 8) return G;
     if (G == 3) return 4;
@@ -308,6 +328,7 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     if (o.window_steps < 0) throw Error(MOC_EINVAL, "options: window_steps must be >= 0");
     pin.window_steps = o.window_steps;
     if (o.lane_stagger < 0 || o.lane_stagger > kBatch) throw Error(MOC_EINVAL, "options: lane_stagger must be in 0..64");
+    if (o.batch_order < 0 || o.batch_order > 1) throw Error(MOC_EINVAL, "options: batch_order must be 0 or 1");
     pin.stagger = o.lane_stagger > 0 ? o.lane_stagger : kDefaultLaneStagger;
     {
         double total_len = 0;
@@ -343,6 +364,7 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     c->V_user.assign(R, 0.0);
     for (int r = 0; r < R; ++r) c->V_user[c->user_of_internal[r]] = V_internal[r];
     d.batch_angle = c->upload(batch_angle);
+    d.batch_of_block = c->upload(make_batch_order(d.nb, o.batch_order));
     if (c->host_only) c->host_batch_angle = batch_angle;
     d.slot_of_canon = c->upload(c->slot_of_canon);
     d.canon_of_slot = c->upload(canon_of_slot);
@@ -457,6 +479,7 @@ static void sweep_impl(moc_ctx *c, hipStream_t s) {
     a.win_tab = d.win_tab;
     a.cap = d.max_slots;
     a.batch_angle = d.batch_angle;
+    a.batch_of_block = d.batch_of_block;
     a.xsq = d.xsq;
     a.psi_in = d.psi[c->cur_psi];
     a.psi_out = d.psi[1 - c->cur_psi];

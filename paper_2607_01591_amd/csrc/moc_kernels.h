@@ -28,6 +28,7 @@ struct SweepArgs {
     const int *win_tab;           // slot -> internal region
     int cap;                      // LDS tally rows per group (>= every window's slot count)
     const int *batch_angle;       // [nb]
+    const int *batch_of_block;    // [nb] batch swept by workgroup column blockIdx.x
     const void *xsq;           // Real [R][Gp][2] (Sigma_t, qhat)
     const void *psi_in;        // Real [2][P][Gp][nslots]
     void *psi_out;
@@ -61,6 +62,7 @@ struct DevProblem {
     int64_t *batch_win = nullptr, *win_entry_off = nullptr, *win_tab_off = nullptr;
     int *win_nsteps = nullptr, *win_nslots = nullptr, *win_tab = nullptr;
     int *batch_angle = nullptr;
+    int *batch_of_block = nullptr;   // [nb] see make_batch_order
     int cap = 256, max_slots = 1;
     void *psi[2] = {nullptr, nullptr};
     int *link = nullptr;

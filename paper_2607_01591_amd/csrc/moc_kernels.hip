@@ -108,7 +108,7 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     for (int i = threadIdx.x; i < GB * cap; i += 64) tl[i] = 0.0;
     __syncthreads();
 
-    const int b = blockIdx.x, sense = blockIdx.y, gb = blockIdx.z, lane = threadIdx.x;
+    const int b = args.batch_of_block[blockIdx.x], sense = blockIdx.y, gb = blockIdx.z, lane = threadIdx.x;
     const int nslots = args.nslots;
     const int slot = b * 64 + lane;
     const int g0 = gb * GB;

@@ -48,7 +48,7 @@ class MocOptions(C.Structure):
     _fields_ = [("precision", _i32), ("exp_mode", _i32), ("max_iter", _i32), ("device", _i32),
                 ("check_every", _i32), ("n_threads", _i32), ("window_cm", _f64),
                 ("tally_slots", _i32), ("group_batch", _i32), ("window_steps", _i32),
-                ("lane_stagger", _i32)]
+                ("lane_stagger", _i32), ("batch_order", _i32)]
 
 
 class MocResult(C.Structure):
@@ -162,7 +162,7 @@ class Solver:
     def __init__(self, prob, precision: str = "f32", exp_mode: str = "poly", device: int = 0,
                  max_iter: int = 10000, check_every: int = 1, n_threads: int = 0,
                  polar: Optional[tuple] = None, window_cm: float = 0.0, tally_slots: int = 0,
-                 group_batch: int = 0, window_steps: int = 0, lane_stagger: int = 0):
+                 group_batch: int = 0, window_steps: int = 0, lane_stagger: int = 0, batch_order: int = 0):
         L = lib()
         self._keep = []
 
@@ -200,7 +200,7 @@ class Solver:
                                                      _ptr(nsf, _f64), _ptr(chi, _f64))
         o = MocOptions(PREC[precision], EXP[exp_mode], max_iter, device, check_every, n_threads,
                        float(window_cm), int(tally_slots), int(group_batch), int(window_steps),
-                       int(lane_stagger))
+                       int(lane_stagger), int(batch_order))
         h = C.c_void_p()
         rc = L.moc_create(C.byref(m), C.byref(t), C.byref(x), C.byref(o), C.byref(h))
         if rc != MOC_OK:

@@ -4,10 +4,10 @@ it to the regions and hand it to moc_set_initial_guess. The plain iteration stil
 decides convergence; a rejected guess falls back to the cold start.
 
 Image: 128 x 128 pixels over the lattice's bounding box. Input channels (per pixel,
-from the material of the region containing the pixel centre): Sigma_t, out-scatter
-Sigma_s, nuSigma_f and chi for each of the 7 groups (28, padded to 32). Output:
-log(phi) per group (7, padded to 32) with phi normalised as the solver normalises it
-(sum V nuSigma_f phi = 1).
+from the material of the region containing the pixel centre): the log of the material's
+infinite-medium spectrum, Sigma_t, Sigma_a and nuSigma_f for each of the 7 groups (28,
+padded to 32). Output: log(phi) per group (7, padded to 32) up to one additive constant
+per image (the solver rescales the guess).
 """
 from __future__ import annotations
 
@@ -25,10 +25,23 @@ CHANNELS = [C_IN_PAD, 64, 64, 64, 64, 64, C_OUT_PAD]   # 6 layers, 64 channels
 
 
 def material_features(prob) -> np.ndarray:
-    """Per-material input features [M, 4 G] (float32)."""
-    st = prob.sigma_t
-    sout = prob.sigma_s.sum(axis=2)
-    return np.concatenate([st, sout, prob.nu_sigma_f, prob.chi], axis=1).astype(np.float32)
+    """Per-material input features [M, 4 G] (float32): the log of the material's
+    infinite-medium spectrum (the solution of (Sigma_t - Sigma_s^T) phi = chi, with the
+    lattice's mean fission spectrum for materials that do not fission; normalised to sum
+    1), then Sigma_t, Sigma_a = Sigma_t - sum_g' Sigma_s,g->g' and nuSigma_f. The
+    spectrum is the part of the flux a few pixels of context cannot infer from raw cross
+    sections."""
+    G = prob.n_groups
+    st, ss, nsf, chi = prob.sigma_t, prob.sigma_s, prob.nu_sigma_f, prob.chi
+    fiss = nsf.sum(axis=1) > 0
+    chi_mean = chi[fiss].mean(axis=0) if fiss.any() else np.full(G, 1.0 / G)
+    feats = []
+    for m in range(prob.n_materials):
+        src = chi[m] if fiss[m] else chi_mean
+        spec = np.linalg.solve(np.diag(st[m]) - ss[m].T, src)
+        spec = np.maximum(np.abs(spec), 1e-30)
+        feats.append(np.concatenate([np.log(spec / spec.sum()), st[m], st[m] - ss[m].sum(axis=1), nsf[m]]))
+    return np.asarray(feats, dtype=np.float32)
 
 
 class WarmStart:
