@@ -117,8 +117,8 @@ typedef struct {
                             so lanes at one step sit at different places along their tracks
                             and fewer of them add to the same LDS tally row at once (costs up
                             to S - 1 padding steps per window); 1: none; 0: library default (2) */
-    int32_t batch_order; /* 0: each of the 8 XCDs (own L2) sweeps one contiguous range of
-                            batches; 1: workgroups in batch order */
+    int32_t batch_order; /* 0: workgroups in batch order; 1: each of the 8 XCDs (own L2)
+                            sweeps one contiguous range of batches */
 } moc_options;
 
 typedef struct {

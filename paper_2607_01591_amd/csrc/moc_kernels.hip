@@ -240,13 +240,16 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
         if constexpr (sizeof(Real) == 4) {
             // software pipeline: segment entries four steps ahead and cross sections two
             // steps ahead are in flight while the current step computes; unrolled by four
-            // so every ring slot is a fixed register set (no copies between steps)
+            // so every ring slot is a fixed register set (no copies between steps), and the
+            // block of four twice more, which halves the drains of the load counter that
+            // the compiler places at the loop's back edge
             Seg sg[4];
             Real st[4][GB], q[4][GB];
 #pragma unroll
             for (int u = 0; u < 4; ++u) sg[u] = ws[step_of(clampi(u))];
             load_xs(sg[0].key, st[0], q[0]);
             load_xs(sg[1].key, st[1], q[1]);
+#pragma unroll 2
             for (int i = 0; i < n; i += 4) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
