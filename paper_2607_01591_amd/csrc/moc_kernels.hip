@@ -211,18 +211,21 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
 #pragma unroll
                 for (int p = 0; p < NP; ++p) cw[p] = cross ? c[p] * sgn : c[p];
             }
-            Real acc[GB];
+            // length times the per-polar factor once per step; the exponent of each update
+            // is then Sigma_t times that
+            Real lp[NP], acc[GB];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) lp[p] = len * is[p];
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
-                const Real sl = st[j] * len;
                 acc[j] = 0;
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
                     Real F;
                     if constexpr (kX)
-                        F = one_minus_exp2_poly(sl * is[p]);
+                        F = one_minus_exp2_poly(st[j] * lp[p]);
                     else
-                        F = one_minus_exp<Real, MODE>(sl * is[p], lut);
+                        F = one_minus_exp<Real, MODE>(st[j] * lp[p], lut);
                     const Real d = (psi[p][j] - q[j]) * F;
                     if constexpr (CUR)
                         psi[p][j] -= keep * d;
