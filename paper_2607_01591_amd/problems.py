@@ -467,6 +467,67 @@ def config(cfg: int, seed: Optional[int] = None) -> Problem:
     raise ValueError(f"unknown config {cfg}")
 
 
+@dataclasses.dataclass
+class Extruded:
+    """An axially extruded 3D problem (both of the paper's MOC-based 3D methods need
+    extruded geometry, Sec. 2.1): the planar problem's mesh, tracking and cross sections
+    in every plane, a material per (plane, region), and a boundary condition at the
+    bottom and at the top (BC_VACUUM or BC_REFLECTIVE)."""
+    name: str
+    base: Problem
+    dz: np.ndarray              # float64 [Nz] plane heights (cm), bottom to top
+    plane_material: np.ndarray  # int32 [Nz, R]
+    bc_bottom: int
+    bc_top: int
+
+    @property
+    def n_planes(self) -> int:
+        return int(len(self.dz))
+
+
+def extrude(p: Problem, dz, plane_material=None, bc_bottom: int = BC_REFLECTIVE,
+            bc_top: int = BC_VACUUM, name: Optional[str] = None) -> Extruded:
+    """Stack len(dz) planes of the planar problem ``p``. Without ``plane_material`` every
+    plane takes the planar material map."""
+    dz = np.ascontiguousarray(np.asarray(dz, float).reshape(-1))
+    if plane_material is None:
+        plane_material = np.tile(p.region_material, (len(dz), 1))
+    pm = np.ascontiguousarray(np.asarray(plane_material, np.int32).reshape(len(dz), p.n_regions))
+    return Extruded(name or f"{p.name}_x{len(dz)}", p, dz, pm, int(bc_bottom), int(bc_top))
+
+
+def lattice_with_reflector(p: Problem, n_core: int, n_reflector: int, height: float,
+                           bc_bottom: int = BC_REFLECTIVE, bc_top: int = BC_VACUUM,
+                           name: Optional[str] = None) -> Extruded:
+    """A square lattice extruded into ``n_core`` core planes topped by ``n_reflector``
+    planes of moderator (every region takes the moderator, the first non-fuel material),
+    all planes of equal height ``height / (n_core + n_reflector)``; the shape of a 3D
+    C5G7-type core with an axial water reflector."""
+    nz = n_core + n_reflector
+    fissile = np.any(p.nu_sigma_f > 0, axis=1)
+    moderator = int(np.flatnonzero(~fissile)[0])
+    pm = np.tile(p.region_material, (nz, 1))
+    pm[n_core:] = moderator
+    return extrude(p, np.full(nz, height / nz), pm, bc_bottom, bc_top,
+                   name or f"{p.name}_core{n_core}_refl{n_reflector}")
+
+
+def config_3d(cfg: int) -> Extruded:
+    """Extruded workloads for DGMOC.
+
+    6: the config-2 lattice (17 x 17 pins, ~31k regions, 7 groups, A = 64, P = 3,
+       0.02 cm) in 12 core planes under 4 moderator-reflector planes, 1.785 cm each
+       (28.56 cm), reflective at the bottom and vacuum at the top.
+    7: the config-1 pin cell in 4 core planes under 2 reflector planes, 0.5 cm each,
+       reflective at the bottom, vacuum at the top (small parity case).
+    """
+    if cfg == 6:
+        return lattice_with_reflector(config(2), 12, 4, 16 * 1.785, name="cfg6_17x17_z16")
+    if cfg == 7:
+        return lattice_with_reflector(config(1), 4, 2, 3.0, name="cfg7_pin_z6")
+    raise ValueError(f"unknown 3D config {cfg}")
+
+
 def box_problem(W: float = 1.0, H: float = 1.0, nx: int = 2, ny: int = 2, *, G: int = 1,
                 sigma_t=None, sigma_s=None, nu_sigma_f=None, chi=None, one_region: bool = False,
                 bc=(1, 1, 1, 1), n_azim: int = 16, n_polar: int = 3, spacing: float = 0.05,
