@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--no-hex", action="store_true")
     ap.add_argument("--solve-seeds", type=int, default=3)
     ap.add_argument("--no-cmfd", action="store_true", help="skip the CMFD time-to-tolerance legs")
+    ap.add_argument("--no-dg", action="store_true", help="skip the DGMOC (extruded 3D) leg")
+    ap.add_argument("--dg-only", action="store_true", help="run only the DGMOC leg (profiling)")
+    ap.add_argument("--dg-steps", type=int, default=5)
     ap.add_argument("--exp-mode", default="poly")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
@@ -138,6 +141,29 @@ def cpu_baseline(workload):
             "sample": f"{sample}; {n} sweeps, U={U:.3e} per sweep, {dt:.2f} s per sweep"}
 
 
+def dg_leg(args):
+    """DGMOC on the extruded 17 x 17 workload: FP32 (and FP64) iteration and sweep times."""
+    import torch
+    from paper_2607_01591_amd import dgmoc
+    from paper_2607_01591_amd import problems as P
+    ext = P.config_3d(6)
+    out = {"workload": f"{ext.name}: {ext.base.n_regions} regions x {ext.n_planes} planes, "
+                       f"{ext.base.n_groups} groups, A={ext.base.n_azim} x P={ext.base.n_polar} per hemisphere, "
+                       f"spacing {ext.base.spacing} cm, linear axial DG; bottom reflective, top vacuum"}
+    for prec in ("f32",) if args.no_f64 else ("f32", "f64"):
+        log(f"DGMOC {prec}: creating context")
+        s = dgmoc.DGSolver(ext, precision=prec, check_every=1 << 30)
+        steps = args.dg_steps if prec == "f32" else max(2, args.dg_steps // 2)
+        ms, prof, r = time_iterations(s, steps, 1)
+        sw = prof["sweep_ms"] / max(1, prof["sweeps"])
+        out[prec] = {"updates_per_sweep": s.U, "updates_per_s": s.U / (ms * 1e-3), "ms_per_iteration": ms,
+                     "sweep_ms": sw, "device_GiB": s.info["device_bytes"] / 2**30, "k_after": r["k"]}
+        log(f"DGMOC {prec}: {ms:.2f} ms/iteration, sweep {sw:.2f} ms, {s.U / (ms * 1e-3):.3e} updates/s")
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -149,6 +175,9 @@ def main():
     from paper_2607_01591_amd import problems as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.dg_only:
+        print(json.dumps({"dgmoc": dg_leg(args)}), flush=True)
+        return
     log(f"generating workload {args.workload}")
     prob = P.config(args.workload)
     log("creating FP32 context (host tracking + upload)")
@@ -274,6 +303,10 @@ def main():
                  "warm_cmfd_sweeps_median": med("warm_cmfd_sweeps"), "warm_cmfd_ms_median": med("warm_cmfd_ms"),
                  "runs": rows}
 
+    dg = None
+    if not args.no_dg:
+        dg = dg_leg(args)
+
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -303,6 +336,7 @@ def main():
         "time_to_tol": solve,
         "cmfd_51x51": cmfd3,
         "hexagon_g33": hexa,
+        "dgmoc_3d": dg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

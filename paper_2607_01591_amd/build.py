@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmoc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["moc_setup.cpp", "moc_pack.cpp", "moc_api.cpp", "moc_kernels.hip", "moc_cmfd.hip", "cnn_kernels.hip"]
+SOURCES = ["moc_setup.cpp", "moc_pack.cpp", "moc_api.cpp", "moc_kernels.hip", "moc_cmfd.hip", "dg_api.cpp",
+           "dg_kernels.hip", "cnn_kernels.hip"]
 
 # Packed FP32 instructions are disabled for all device code: hipcc would otherwise form
 # them from ordinary float arithmetic.

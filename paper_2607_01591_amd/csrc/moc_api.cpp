@@ -7,114 +7,9 @@
 #include <memory>
 #include <thread>
 
-#include "moc_kernels.h"
-#include "moc_pack.h"
+#include "moc_ctx.h"
 
 using namespace moc;
-
-#define HIP_OK(call)                                                                                  \
-    do {                                                                                              \
-        hipError_t e_ = (call);                                                                       \
-        if (e_ != hipSuccess) throw Error(MOC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-struct moc_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    Mesh mesh;
-    Quadrature quad;
-    Tracks tracks;
-    DevProblem d;
-    std::vector<int> internal_of_user, user_of_internal;
-    std::vector<int> slot_of_canon;
-    std::vector<double> V_user;
-    std::vector<double> sigt_m_host, nsf_m_host;
-    int64_t S = 0, padded_steps = 0, n_windows = 0, n_slots_total = 0;
-    double window_len = 0;
-    // host-only contexts keep the packed layout for inspection
-    PackOutput host_pack;
-    std::vector<SegF> host_segs_f32;
-    std::vector<SegD> host_segs_f64;
-    std::vector<int> host_batch_angle;
-    // point-location buckets (moc_locate_points)
-    int loc_nx = 0, loc_ny = 0;
-    std::vector<int64_t> loc_off;
-    std::vector<int> loc_tri;
-    int64_t device_bytes = 0;
-    double setup_ms = 0;
-    int max_iter = 10000, check_every = 1, n_threads = 1;
-    bool host_only = false;   // negative device ordinal: tracking only, no device state
-    int cur_psi = 0, cur_phi = 0;
-    bool fissile = false;
-    bool fixed_source = false;
-    // initial guess
-    bool guess_pending = false;
-    double guess_k = 1.0;
-    bool guess_has_psi = false;
-    double *guess_phi = nullptr;   // internal [R][G]
-    double *exit_canon = nullptr;  // user buffer
-    double *host_scal = nullptr;   // pinned
-    std::vector<std::pair<void *, size_t>> allocs;
-    std::string err;
-    // packing parameters kept for re-packing (coarse mesh on/off)
-    PackInput pin;
-    int64_t crossings = 0;
-    // CMFD coarse mesh
-    bool cmfd = false;
-    CoarseSurfaces cs;
-    DevCoarse cd;
-    int64_t tally_rows = 0, xsq_rows = 0;
-    double coarse_setup_ms = 0;
-    // sweep profiling
-    bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_pool, prof_cmfd_pending;
-    int64_t prof_n = 0, prof_cmfd_n = 0;
-    double prof_ms = 0, prof_min = 0, prof_max = 0, prof_cmfd_ms = 0;
-
-    template <typename T> T *dalloc(size_t n) {
-        if (host_only) return nullptr;
-        void *p = nullptr;
-        const size_t bytes = std::max<size_t>(n * sizeof(T), 16);
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) throw Error(MOC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-        allocs.push_back({p, bytes});
-        device_bytes += (int64_t)bytes;
-        return (T *)p;
-    }
-    void dfree(void *p) {
-        if (!p) return;
-        for (size_t i = 0; i < allocs.size(); ++i)
-            if (allocs[i].first == p) {
-                if (stream) hipStreamSynchronize(stream);
-                hipFree(p);
-                device_bytes -= (int64_t)allocs[i].second;
-                allocs.erase(allocs.begin() + (long)i);
-                return;
-            }
-    }
-    template <typename T> T *upload(const std::vector<T> &v) {
-        if (host_only) return nullptr;
-        T *p = dalloc<T>(v.size());
-        if (!v.empty()) HIP_OK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-        return p;
-    }
-    ~moc_ctx() {
-        if (stream) hipStreamSynchronize(stream);
-        for (auto *v : {&prof_pending, &prof_cmfd_pending})
-            for (auto &e : *v) {
-                hipEventSynchronize(e.second);
-                hipEventDestroy(e.first);
-                hipEventDestroy(e.second);
-            }
-        for (auto &e : prof_pool) {
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
-        }
-        for (auto &a : allocs) hipFree(a.first);
-        if (host_scal) hipHostFree(host_scal);
-        if (stream) hipStreamDestroy(stream);
-    }
-};
 
 static thread_local std::string g_create_error;
 
@@ -229,7 +124,7 @@ static void pack_and_upload(moc_ctx *c, const CoarseSurfaces *coarse, PackOutput
     if (c->host_only) c->host_pack = pk;
 }
 
-static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const moc_xs *xs, const moc_options *opt,
+void moc::create_context(const moc_mesh *mesh_in, const moc_tracks *tr_in, const moc_xs *xs, const moc_options *opt,
                         moc_ctx *c) {
     const auto t0 = std::chrono::steady_clock::now();
     if (!mesh_in || !tr_in || !xs) throw Error(MOC_EINVAL, "create: null argument");
@@ -367,7 +262,7 @@ static void create_impl(const moc_mesh *mesh_in, const moc_tracks *tr_in, const 
     for (int r = 0; r < R; ++r) c->V_user[c->user_of_internal[r]] = V_internal[r];
     d.batch_angle = c->upload(batch_angle);
     d.batch_of_block = c->upload(make_batch_order(d.nb, o.batch_order));
-    if (c->host_only) c->host_batch_angle = batch_angle;
+    c->host_batch_angle = batch_angle;
     d.slot_of_canon = c->upload(c->slot_of_canon);
     d.canon_of_slot = c->upload(canon_of_slot);
 
@@ -523,7 +418,7 @@ int moc_create(const moc_mesh *mesh, const moc_tracks *tracks, const moc_xs *xs,
         g_create_error = "host allocation failed";
         return MOC_ENOMEM;
     }
-    const int rc = guarded(c, [&] { create_impl(mesh, tracks, xs, opts, c); });
+    const int rc = guarded(c, [&] { create_context(mesh, tracks, xs, opts, c); });
     if (rc != MOC_OK) {
         g_create_error = c->err;
         delete c;
@@ -1288,3 +1183,5 @@ int moc_get_quadrature(const moc_ctx *c, double *phi, double *delta, double *w_a
 const char *moc_last_error(const moc_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"
+
+int moc::guarded_call(moc_ctx *c, const std::function<void()> &f) { return guarded(c, f); }

@@ -35,6 +35,31 @@ def test_library_exports_every_cnn_symbol():
     assert declared == set(cnn.SIGNATURES), declared ^ set(cnn.SIGNATURES)
 
 
+def test_library_exports_every_dgmoc_symbol():
+    from paper_2607_01591_amd import dgmoc
+    hdr = open(os.path.join(ROOT, "include", "dgmoc.h")).read()
+    declared = set(re.findall(r"\b(moc_dg_[a-z_]+)\s*\(", hdr))
+    assert {"moc_dg_create", "moc_dg_sweep", "moc_dg_solve"} <= declared
+    L = dgmoc.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(dgmoc.SIGNATURES), declared ^ set(dgmoc.SIGNATURES)
+
+
+def test_dgmoc_create_rejects_bad_axial_input():
+    """Host-side validation of moc_dg_create: no HIP call is made before it fails."""
+    from paper_2607_01591_amd import dgmoc
+    ext = P.config_3d(7)
+    bad = [dict(dz=[0.5, -1.0]), dict(bc_top=3), dict(pm=-1)]
+    for b in bad:
+        e = P.extrude(ext.base, b.get("dz", ext.dz), None, bc_bottom=ext.bc_bottom, bc_top=b.get("bc_top", ext.bc_top))
+        if "pm" in b:
+            e.plane_material[0, 0] = 99
+        with pytest.raises(moc.MocError) as ei:
+            dgmoc.DGSolver(e, device=0)
+        assert ei.value.code == moc.MOC_EINVAL
+
+
 def _compare_tracking(prob):
     s = moc.Solver(prob, device=-1)
     o = Oracle.from_problem(prob)
