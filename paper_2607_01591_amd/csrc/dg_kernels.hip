@@ -60,6 +60,20 @@ __device__ __forceinline__ void dg_sincos(float x, float &sn, float &cs) {
 }
 __device__ __forceinline__ void dg_sincos(double x, double &sn, double &cs) { sincos(x, &sn, &cs); }
 
+// The same for a whole wavefront: when every lane has x <= pi/4 (the usual case: c / 2
+// is below that for segments shorter than about 1.1 h sin(theta) / mu) the reduction is
+// the identity and the polynomials alone give the result; otherwise the full reduction.
+__device__ __forceinline__ void dg_sincos_wave(float x, float &sn, float &cs) {
+    if (__all(x <= 0.78539816f)) {
+        const float r2 = x * x;
+        sn = x * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
+        cs = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320 + r2 * (-1.0f / 3628800)))));
+    } else {
+        dg_sincos(x, sn, cs);
+    }
+}
+__device__ __forceinline__ void dg_sincos_wave(double x, double &sn, double &cs) { sincos(x, &sn, &cs); }
+
 // 1 - e^-a for a >= 0 with relative accuracy
 __device__ __forceinline__ float dg_one_minus_exp(float a) { return one_minus_exp2_poly(a * -1.4426950408889634f); }
 __device__ __forceinline__ double dg_one_minus_exp(double a) { return -expm1(-a); }
@@ -182,10 +196,14 @@ template <typename Real, int NP, int GB> __global__ __launch_bounds__(64) void k
         Real st[GB];
         Real d[NP][GB][2];
     };
+    // per-wave bases; a region's rows are then 32-bit offsets from them
+    const Real *__restrict__ sigt_w = sigt + g0;
+    const Real *__restrict__ drv_w = drv + ((int64_t)dirb * R * n_gb + gbi) * (NP * GB * 2);
+    const uint32_t drv_rs = (uint32_t)n_gb * (NP * GB * 2);
     auto load = [&](uint32_t key, Data &x) {
-        const int r = int(key >> kSlotBits);
-        const Real *srow = sigt + (int64_t)r * Gp + g0;
-        const Real *drow = drv + (((int64_t)dirb * R + r) * n_gb + gbi) * (NP * GB * 2);
+        const uint32_t r = key >> kSlotBits;
+        const Real *srow = sigt_w + r * (uint32_t)Gp;
+        const Real *drow = drv_w + r * drv_rs;
         if constexpr (sizeof(Real) == 4 && GB == 4) {
             const float4 v = *reinterpret_cast<const float4 *>(srow);
             x.st[0] = v.x; x.st[1] = v.y; x.st[2] = v.z; x.st[3] = v.w;
@@ -222,11 +240,16 @@ template <typename Real, int NP, int GB> __global__ __launch_bounds__(64) void k
         auto step_of = [&](int i) { return (int64_t)(sense ? n - 1 - i : i) * 64 + lane; };
         auto clampi = [&](int i) { return i < n ? i : n - 1; };
 
+        // one step. Psi_in - Psi_out = (I - e^-M) X = N1 X + N2 / sqrt(2) J X, and the segment
+        // average is D + M^-1 (Psi_in - Psi_out) with M^-1 = (a I - b J) / (a^2 + c^2).
+        // Padding steps (length 0) leave psi unchanged and add exact zeros; their lanes add
+        // them to the window's slots spread by lane (one shared row would serialise them),
+        // which keeps the tally atomics free of per-lane branches.
+        double *pad_row = tl + (lane % (ns > 0 ? ns : 1)) * (GB * NV);
         auto update = [&](const Seg &sg, const Data &x) {
             const Real len = sg.len;
             const int ts = int(sg.key & ((1u << kSlotBits) - 1));
-            double *row = tl + ts * (GB * NV);
-            const bool real = len > Real(0);   // padding steps change nothing and add nothing
+            double *row = len > Real(0) ? tl + ts * (GB * NV) : pad_row;
             Real acc0[GB], acc1[GB];
 #pragma unroll
             for (int j = 0; j < GB; ++j) acc0[j] = acc1[j] = Real(0);
@@ -237,8 +260,9 @@ template <typename Real, int NP, int GB> __global__ __launch_bounds__(64) void k
                 const Real bt = kp[p] * lp;
                 const Real c = Real(1.4142135623730951) * bt;
                 Real sh, ch;
-                dg_sincos(Real(kInvSqrt2) * bt, sh, ch);   // sin and cos of c / 2
-                const Real sc = Real(2) * sh * ch, omc = Real(2) * sh * sh;
+                dg_sincos_wave(Real(kInvSqrt2) * bt, sh, ch);   // sin and cos of c / 2
+                const Real scs = Real(1.4142135623730951) * sh * ch;   // sin(c) / sqrt(2)
+                const Real omc = Real(2) * sh * sh;                     // 1 - cos(c)
                 const Real c2 = c * c, b2 = bt + bt;
                 const Real w0p = cw0[p] * len, w1p = cw1[p] * len;
 #pragma unroll
@@ -246,45 +270,44 @@ template <typename Real, int NP, int GB> __global__ __launch_bounds__(64) void k
                     const Real aa = x.st[j] * lp + b2;
                     const Real F = dg_one_minus_exp(aa);
                     const Real e = Real(1) - F;
-                    const Real N1 = e * omc + F, N2 = e * sc;
+                    const Real N1 = e * omc + F, N2s = e * scs;
+                    const Real X0 = ps[p][j][0] - x.d[p][j][0], X1 = ps[p][j][1] - x.d[p][j][1];
+                    const Real D0 = N1 * X0 + N2s * (X1 - X0);
+                    const Real D1 = N1 * X1 + N2s * (X1 - Real(3) * X0);
+                    ps[p][j][0] -= D0;
+                    ps[p][j][1] -= D1;
                     Real den = aa * aa + c2;
                     den = den > Real(1e-30) ? den : Real(1e-30);
                     const Real rd = dg_rcp(den);
-                    const Real gr = (aa * N1 + c * N2) * rd;
-                    const Real gi = (aa * N2 - c * N1) * rd * Real(kInvSqrt2);
-                    const Real n2s = N2 * Real(kInvSqrt2);
-                    const Real X0 = ps[p][j][0] - x.d[p][j][0], X1 = ps[p][j][1] - x.d[p][j][1];
-                    const Real J0 = X1 - X0, J1 = X1 - Real(3) * X0;
-                    ps[p][j][0] -= N1 * X0 + n2s * J0;
-                    ps[p][j][1] -= N1 * X1 + n2s * J1;
-                    const Real b0 = x.d[p][j][0] + gr * X0 + gi * J0;
-                    const Real b1 = x.d[p][j][1] + gr * X1 + gi * J1;
+                    const Real b0 = x.d[p][j][0] + rd * (aa * D0 - bt * (D1 - D0));
+                    const Real b1 = x.d[p][j][1] + rd * (aa * D1 - bt * (D1 - Real(3) * D0));
                     acc0[j] += w0p * b0;
                     acc1[j] += w1p * b1;
-                    if (real) atomicAdd(&row[j * NV + 2 + p], (double)(dll * (b0 + b1)));
+                    atomicAdd(&row[j * NV + 2 + p], (double)(dll * (b0 + b1)));
                 }
             }
-            if (real) {
 #pragma unroll
-                for (int j = 0; j < GB; ++j) {
-                    atomicAdd(&row[j * NV], (double)acc0[j]);
-                    atomicAdd(&row[j * NV + 1], (double)acc1[j]);
-                }
+            for (int j = 0; j < GB; ++j) {
+                atomicAdd(&row[j * NV], (double)acc0[j]);
+                atomicAdd(&row[j * NV + 1], (double)acc1[j]);
             }
         };
-        // software pipeline: segment entries two steps ahead, cross sections and driven
-        // flux one step ahead
+        // software pipeline, unrolled by two so that the two data sets alternate without
+        // copies: segment entries two steps ahead, cross sections and driven flux one
         Seg s0 = ws[step_of(0)], s1 = ws[step_of(clampi(1))];
-        Data x0;
+        Data x0, x1;
         load(s0.key, x0);
-        for (int i = 0; i < n; ++i) {
+        for (int i = 0; i < n; i += 2) {
             const Seg s2 = ws[step_of(clampi(i + 2))];
-            Data x1;
             load(s1.key, x1);
             update(s0, x0);
-            s0 = s1;
-            s1 = s2;
-            x0 = x1;
+            if (i + 1 < n) {
+                const Seg s3 = ws[step_of(clampi(i + 3))];
+                load(s2.key, x0);
+                update(s1, x1);
+                s0 = s2;
+                s1 = s3;
+            }
         }
         __syncthreads();
 #pragma unroll

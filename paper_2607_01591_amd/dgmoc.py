@@ -65,7 +65,7 @@ class DGSolver:
 
     def __init__(self, ext, precision: str = "f32", device: int = 0, max_iter: int = 10000,
                  check_every: int = 1, n_threads: int = 0, angle_block: int = 0, tally_slots: int = 0,
-                 group_batch: int = 0, window_cm: float = 0.0):
+                 group_batch: int = 0, window_cm: float = 0.0, lane_stagger: int = 0):
         L = lib()
         prob = ext.base
         keep = []
@@ -97,7 +97,7 @@ class DGSolver:
         pm = k(ext.plane_material, np.int32)
         ax = MocAxial(len(dz), _ptr(dz, _f64), _ptr(pm, _i32), int(ext.bc_bottom), int(ext.bc_top), int(angle_block))
         o = MocOptions(PREC[precision], 0, max_iter, device, check_every, n_threads, float(window_cm),
-                       int(tally_slots), int(group_batch), 0, 0, 0)
+                       int(tally_slots), int(group_batch), 0, int(lane_stagger), 0)
         h = C.c_void_p()
         rc = L.moc_dg_create(C.byref(m), C.byref(t), C.byref(x), C.byref(ax), C.byref(o), C.byref(h))
         if rc != MOC_OK:
