@@ -53,7 +53,7 @@ typedef struct {
 /* Create a DGMOC context. mesh, tracks and xs are as for moc_create (Sec. 3.1 tracking;
  * the mesh's region_material must be valid and is the default plane map); axial adds
  * the planes. opts as for moc_create, with these DGMOC defaults when left 0:
- * tally_slots 64, group_batch 4 (allowed: 1, 2, 4). exp_mode, window_steps,
+ * tally_slots 256, group_batch 2 (allowed: 1, 2, 4). exp_mode, window_steps,
  * lane_stagger and batch_order apply to the shared track packing only. The context
  * starts cold: scalar flux moments (1, 0), k = 1, zero boundary and face fluxes.
  * Errors: MOC_EINVAL (as moc_create; n_planes < 1, dz <= 0, a plane material out of

@@ -64,7 +64,8 @@ CASES = [
     ("box_g3_p2_vac_vac_gb2", lambda: box3(3, 2, P.BC_VACUUM, P.BC_VACUUM), dict(group_batch=2)),
     ("box_g5_p4_refl_refl_block3", lambda: box3(5, 4, P.BC_REFLECTIVE, P.BC_REFLECTIVE), dict(angle_block=3)),
     ("box_g2_p1_vac_refl_gb1", lambda: box3(2, 1, P.BC_VACUUM, P.BC_REFLECTIVE), dict(group_batch=1)),
-    ("box_g7_p3_refl_vac_gb4", lambda: box3(7, 3, P.BC_REFLECTIVE, P.BC_VACUUM, seed=3), dict()),
+    ("box_g7_p3_refl_vac_gb4_slots64", lambda: box3(7, 3, P.BC_REFLECTIVE, P.BC_VACUUM, seed=3),
+     dict(group_batch=4, tally_slots=64)),
 ]
 
 
