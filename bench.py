@@ -20,10 +20,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and derived ALU peak
+# MI355X published HBM peak; FP32 vector peak from 256 CUs x 64 lanes x FMA at 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 N_CU, CLOCK_GHZ = 256, 2.4
 FP32_NONPACKED_TFLOPS = N_CU * 64 * 2 * CLOCK_GHZ / 1000.0      # FMA = 2 flops, no packed FP32
+DG_FLOPS_PER_UPDATE = 55   # DGMOC segment solution per (segment, polar, group), exp and reciprocal as one each
 FLOPS_PER_UPDATE = 7     # tau mul, 1 - e^-tau (1), psi - q, * F, psi -= d, tally fma (2)
 COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_f32_lattice51x51_counters.txt")
 
@@ -158,6 +159,11 @@ def dg_leg(args):
         sw = prof["sweep_ms"] / max(1, prof["sweeps"])
         out[prec] = {"updates_per_sweep": s.U, "updates_per_s": s.U / (ms * 1e-3), "ms_per_iteration": ms,
                      "sweep_ms": sw, "device_GiB": s.info["device_bytes"] / 2**30, "k_after": r["k"]}
+        if prec == "f32":
+            ach = s.U * DG_FLOPS_PER_UPDATE / (sw * 1e-3) / 1e12
+            out["roofline"] = {"bound": "alu", "achieved": ach, "peak": FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                               "frac": ach / FP32_NONPACKED_TFLOPS, "flops_per_update": DG_FLOPS_PER_UPDATE,
+                               "note": "whole sweep (driven-flux and plane-sweep kernels) from HIP events"}
         log(f"DGMOC {prec}: {ms:.2f} ms/iteration, sweep {sw:.2f} ms, {s.U / (ms * 1e-3):.3e} updates/s")
         del s
         torch.cuda.empty_cache()
@@ -167,8 +173,8 @@ def dg_leg(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding by azimuthal "
+              "angle across GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2607_01591_amd import moc

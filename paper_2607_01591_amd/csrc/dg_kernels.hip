@@ -87,37 +87,39 @@ __device__ __forceinline__ double dg_rcp(double x) { return 1.0 / x; }
 // per-angle track area, or the bottom buffer) and D = A^-1 Q. The face tallies are
 // cleared for the plane's own sweep.
 template <typename Real> __global__ void k_dg_driven(DgDrivenArgs a) {
-    const int64_t n = (int64_t)2 * a.nab * a.P * a.R * a.Gp;
+    // grid: x over the (region, group) entries of one row, y = direction * P + polar
+    const int rowlen = a.R * a.Gp;
+    const int p = blockIdx.y % a.P, dirb = blockIdx.y / a.P;
+    const int ang = a.a0 + (dirb >> 1);
     const Real *__restrict__ sigt = reinterpret_cast<const Real *>(a.sigt);
     const Real *__restrict__ q = reinterpret_cast<const Real *>(a.q);
     Real *__restrict__ face = reinterpret_cast<Real *>(a.face);
     const Real *__restrict__ bot = reinterpret_cast<const Real *>(a.bot);
     const Real *__restrict__ inv_va = reinterpret_cast<const Real *>(a.inv_va);
     Real *__restrict__ drv = reinterpret_cast<Real *>(a.drv);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int g = int(i % a.Gp);
-        const int r = int((i / a.Gp) % a.R);
-        const int p = int((i / ((int64_t)a.Gp * a.R)) % a.P);
-        const int dirb = int(i / ((int64_t)a.Gp * a.R * a.P));
-        const int ang = a.a0 + (dirb >> 1);
-        double pf = 0.0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rowlen; e += gridDim.x * blockDim.x) {
+        const int r = e / a.Gp, g = e - r * a.Gp;
+        const int64_t i = (int64_t)blockIdx.y * rowlen + e;
+        // arithmetic in the sweep precision (the result is stored in it); every term of
+        // det is positive
+        Real pf = 0;
         if (a.mode == 1)
-            pf = (double)face[i] * (double)inv_va[(int64_t)ang * a.R + r];
+            pf = face[i] * inv_va[(int64_t)ang * a.R + r];
         else if (a.mode == 2)
-            pf = (double)bot[(((int64_t)(a.a0 * 2 + dirb) * a.P + p) * a.R + r) * a.Gp + g];
+            pf = bot[(((int64_t)(a.a0 * 2 + dirb) * a.P + p) * a.R + r) * a.Gp + g];
         face[i] = Real(0);
-        const double st = (double)sigt[(int64_t)r * a.Gp + g];
-        const double k = a.kap[p];
-        const double q0 = (double)q[((int64_t)r * a.Gp + g) * 2] + k * pf;
-        const double q1 = a.sgn * (double)q[((int64_t)r * a.Gp + g) * 2 + 1] - 3.0 * k * pf;
-        const double det = st * st + 4.0 * st * k + 6.0 * k * k;
-        const double d0 = ((st + 3.0 * k) * q0 - k * q1) / det;
-        const double d1 = (3.0 * k * q0 + (st + k) * q1) / det;
+        const Real st = sigt[(int64_t)r * a.Gp + g];
+        const Real k = (Real)a.kap[p];
+        const Real q0 = q[((int64_t)r * a.Gp + g) * 2] + k * pf;
+        const Real q1 = (Real)a.sgn * q[((int64_t)r * a.Gp + g) * 2 + 1] - Real(3) * k * pf;
+        const Real rdet = dg_rcp(st * st + Real(4) * st * k + Real(6) * k * k);
+        const Real d0 = ((st + Real(3) * k) * q0 - k * q1) * rdet;
+        const Real d1 = (Real(3) * k * q0 + (st + k) * q1) * rdet;
         const int gbi = g / a.gb, j = g - gbi * a.gb;
         const int64_t o = ((((int64_t)dirb * a.R + r) * a.n_gb + gbi) * a.P + p) * a.gb + j;
         if (gbi < a.n_gb) {
-            drv[2 * o] = (Real)d0;
-            drv[2 * o + 1] = (Real)d1;
+            drv[2 * o] = d0;
+            drv[2 * o + 1] = d1;
         }
     }
 }
@@ -126,15 +128,16 @@ template <typename Real> __global__ void k_dg_driven(DgDrivenArgs a) {
 // track area are the flux leaving through the bottom, kept for the next sweep's upward
 // ward (reflective bottom).
 template <typename Real> __global__ void k_dg_store_bottom(DgDrivenArgs a) {
-    const int64_t n = (int64_t)2 * a.nab * a.P * a.R * a.Gp;
+    const int rowlen = a.R * a.Gp;
+    const int dirb = blockIdx.y / a.P;
+    const int ang = a.a0 + (dirb >> 1);
     const Real *__restrict__ face = reinterpret_cast<const Real *>(a.face);
     Real *__restrict__ bot = const_cast<Real *>(reinterpret_cast<const Real *>(a.bot));
     const Real *__restrict__ inv_va = reinterpret_cast<const Real *>(a.inv_va);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int r = int((i / a.Gp) % a.R);
-        const int dirb = int(i / ((int64_t)a.Gp * a.R * a.P));
-        const int ang = a.a0 + (dirb >> 1);
-        bot[(int64_t)a.a0 * 2 * a.P * a.R * a.Gp + i] = face[i] * inv_va[(int64_t)ang * a.R + r];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rowlen; e += gridDim.x * blockDim.x) {
+        const int r = e / a.Gp;
+        const int64_t i = (int64_t)blockIdx.y * rowlen + e;
+        bot[(int64_t)a.a0 * 2 * a.P * rowlen + i] = face[i] * inv_va[(int64_t)ang * a.R + r];
     }
 }
 
@@ -546,21 +549,25 @@ static int grid_for(int64_t n, int block = 256) {
     return (int)(b < 1 ? 1 : (b > 65535 * 4 ? 65535 * 4 : b));
 }
 
+static dim3 row_grid(const DgDrivenArgs &a) {
+    const int64_t rowlen = (int64_t)a.R * a.Gp;
+    const int64_t bx = (rowlen + 255) / 256;
+    return dim3((unsigned)(bx < 1 ? 1 : (bx > 4096 ? 4096 : bx)), (unsigned)(2 * a.nab * a.P));
+}
+
 void launch_dg_driven(const DgDrivenArgs &a, int precision, hipStream_t s) {
-    const int64_t n = (int64_t)2 * a.nab * a.P * a.R * a.Gp;
     if (precision == MOC_PREC_F64)
-        k_dg_driven<double><<<grid_for(n), 256, 0, s>>>(a);
+        k_dg_driven<double><<<row_grid(a), 256, 0, s>>>(a);
     else
-        k_dg_driven<float><<<grid_for(n), 256, 0, s>>>(a);
+        k_dg_driven<float><<<row_grid(a), 256, 0, s>>>(a);
     dg_check_launch();
 }
 
 void launch_dg_store_bottom(const DgDrivenArgs &a, int precision, hipStream_t s) {
-    const int64_t n = (int64_t)2 * a.nab * a.P * a.R * a.Gp;
     if (precision == MOC_PREC_F64)
-        k_dg_store_bottom<double><<<grid_for(n), 256, 0, s>>>(a);
+        k_dg_store_bottom<double><<<row_grid(a), 256, 0, s>>>(a);
     else
-        k_dg_store_bottom<float><<<grid_for(n), 256, 0, s>>>(a);
+        k_dg_store_bottom<float><<<row_grid(a), 256, 0, s>>>(a);
     dg_check_launch();
 }
 

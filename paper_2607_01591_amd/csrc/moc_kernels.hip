@@ -327,24 +327,32 @@ __global__ void k_prep_user(const double *__restrict__ src_user, const int *__re
 
 // Source update (Eq. MGNTE, isotropic): s_g = sum_g' Sigma_s,g'->g phi_g' + chi_g F / k
 // (+ external), F = sum_g nuSigma_f,g phi_g; qhat = s / (4 pi Sigma_t). FP64 arithmetic.
+// One thread per (region, group), consecutive threads on consecutive groups of a region
+// (the fission sum is formed by each of them): G-fold more parallelism than a thread per
+// region, which matters for many groups. Region and group indices fit 32 bits (regions
+// are below 2^23 by the packed segment key).
 template <typename Real>
 __global__ void k_source(const double *__restrict__ phi, const double *__restrict__ scal, const int *__restrict__ mat,
                          const double *__restrict__ sigt_m, const double *__restrict__ sigs_m,
                          const double *__restrict__ nsf_m, const double *__restrict__ chi_m,
                          const double *__restrict__ qext, Real *__restrict__ xsq, int R, int G, int Gp) {
     const double inv_k = 1.0 / scal[kScalK];
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+    const uint32_t n = (uint32_t)R * (uint32_t)G;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t r = i / (uint32_t)G, g = i - r * (uint32_t)G;
         const int m = mat[r];
         const double *ph = phi + (int64_t)r * G;
-        double F = 0.0;
-        for (int gp = 0; gp < G; ++gp) F += nsf_m[m * G + gp] * ph[gp];
-        for (int g = 0; g < G; ++g) {
-            double s = chi_m[m * G + g] * F * inv_k;
-            const double *col = sigs_m + (int64_t)m * G * G + g;
-            for (int gp = 0; gp < G; ++gp) s += col[(int64_t)gp * G] * ph[gp];
-            if (qext) s += qext[(int64_t)r * G + g];
-            xsq[((int64_t)r * Gp + g) * 2 + 1] = (Real)(s / (kFourPi * sigt_m[m * G + g]));
+        const double *col = sigs_m + (int64_t)m * G * G + g;
+        const double *nsf = nsf_m + m * G;
+        double F = 0.0, s = 0.0;
+        for (int gp = 0; gp < G; ++gp) {
+            const double f = ph[gp];
+            F += nsf[gp] * f;
+            s += col[(int64_t)gp * G] * f;
         }
+        s += chi_m[m * G + g] * F * inv_k;
+        if (qext) s += qext[i];
+        xsq[((int64_t)r * Gp + g) * 2 + 1] = (Real)(s / (kFourPi * sigt_m[m * G + g]));
     }
 }
 
@@ -362,6 +370,7 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 // phi = 4 pi qhat + T / (Sigma_t V) (angular integration of segment averages; FP64);
 // either to the internal phi with per-block partials of sum V F, or to a user buffer.
+// One thread per (region, group); the partial sums run over (region, group) pairs.
 template <typename Real>
 __global__ void k_finalize(const Real *__restrict__ xsq, const double *__restrict__ tally, const double *__restrict__ V,
                            const int *__restrict__ mat, const double *__restrict__ sigt_m,
@@ -370,18 +379,16 @@ __global__ void k_finalize(const Real *__restrict__ xsq, const double *__restric
                            int R, int G, int Gp) {
     __shared__ double sh[16];
     double acc = 0.0;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+    const uint32_t n = (uint32_t)R * (uint32_t)G;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t r = i / (uint32_t)G, g = i - r * (uint32_t)G;
         const int m = mat[r];
         const double v = V[r];
-        double F = 0.0;
-        for (int g = 0; g < G; ++g) {
-            const double st = sigt_m[m * G + g];
-            const double ph = kFourPi * (double)xsq[((int64_t)r * Gp + g) * 2 + 1] + tally[(int64_t)r * Gp + g] / (st * v);
-            if (phi_internal) phi_internal[(int64_t)r * G + g] = ph;
-            if (phi_user) phi_user[(int64_t)user_of[r] * G + g] = ph;
-            F += nsf_m[m * G + g] * ph;
-        }
-        acc += v * F;
+        const double st = sigt_m[m * G + g];
+        const double ph = kFourPi * (double)xsq[((int64_t)r * Gp + g) * 2 + 1] + tally[(int64_t)r * Gp + g] / (st * v);
+        if (phi_internal) phi_internal[i] = ph;
+        if (phi_user) phi_user[(int64_t)user_of[r] * G + g] = ph;
+        acc += v * nsf_m[m * G + g] * ph;
     }
     if (partials) {
         const double t = block_sum(acc, sh);
@@ -463,23 +470,22 @@ __global__ void k_eigen_update(const double *__restrict__ partials, int nblk, do
     }
 }
 
-// phi_new *= f; partials of sum V (phi_new - phi_old)^2 and sum V phi_new^2
+// phi_new *= f; partials of sum V (phi_new - phi_old)^2 and sum V phi_new^2 (one thread
+// per (region, group))
 __global__ void k_norm_residual(double *__restrict__ phi_new, const double *__restrict__ phi_old,
                                 const double *__restrict__ V, const double *__restrict__ scal,
                                 double *__restrict__ partials, int R, int G) {
     __shared__ double sh[16];
     const double f = scal[kScalF];
     double num = 0.0, den = 0.0;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
-        const double v = V[r];
-        for (int g = 0; g < G; ++g) {
-            const int64_t i = (int64_t)r * G + g;
-            const double x = phi_new[i] * f;
-            phi_new[i] = x;
-            const double d = x - phi_old[i];
-            num += v * d * d;
-            den += v * x * x;
-        }
+    const uint32_t n = (uint32_t)R * (uint32_t)G;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double v = V[i / (uint32_t)G];
+        const double x = phi_new[i] * f;
+        phi_new[i] = x;
+        const double d = x - phi_old[i];
+        num += v * d * d;
+        den += v * x * x;
     }
     const double a = block_sum(num, sh);
     const double b = block_sum(den, sh);
@@ -678,7 +684,7 @@ void launch_prep_user(const DevProblem &d, const double *src_user, hipStream_t s
 }
 
 void launch_source(const DevProblem &d, const double *phi, hipStream_t s) {
-    const int grid = grid_for(d.R, 256, 8192);
+    const int grid = grid_for((int64_t)d.R * d.G, 256, 8192);
     if (d.precision == MOC_PREC_F64)
         hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(256), 0, s, phi, d.scal, d.mat, d.sigt_m, d.sigs_m, d.nsf_m,
                            d.chi_m, d.qext, (double *)d.xsq, d.R, d.G, d.Gp);
