@@ -254,7 +254,7 @@ int moc_set_external_source(moc_ctx *ctx, const double *q_dev);
  * pending initial guess. Errors: MOC_EINVAL (sizes differ, Sigma_t <= 0, bad material). */
 int moc_set_materials(moc_ctx *ctx, const int32_t *region_material, const moc_xs *xs);
 
-/* CMFD acceleration (Sec. 2.2, Alg. MOCHFEM_CMFD, its radial part): region_cell host
+/* CMFD acceleration (Sec. 2.1.2, Alg. MOCHFEM_CMFD, its radial part): region_cell host
  * int32 [R] (user region order) assigns every region to one of n_cells coarse cells;
  * every cell must hold at least one region. From then on each sweep also tallies the net
  * current across every coarse surface a track crosses (the packed segment stream is

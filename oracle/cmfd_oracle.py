@@ -6,7 +6,7 @@ TEST INFRASTRUCTURE ONLY: used by the test suite (and nothing in the product pac
 What it follows. The paper accelerates its planar MOC with CMFD: each outer iteration
 runs MOC on the fine mesh, homogenises the fine solution onto a coarse mesh, solves the
 coarse-mesh problem with the MOC currents on the radial coarse surfaces, and updates the
-fine-mesh solution with the accelerated result (Sec. 2.2, Alg. MOCHFEM_CMFD). In 2D
+fine-mesh solution with the accelerated result (Sec. 2.1.2, Alg. MOCHFEM_CMFD). In 2D
 there is no axial (HFEM) part. The paper does not write out the coarse equations; the
 reading used here is the standard nonlinear-diffusion form of CMFD:
 

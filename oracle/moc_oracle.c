@@ -741,7 +741,7 @@ int orc_solve(orc_t *o, double tol, int max_iter, double *phi /* [R][G] in/out *
 }
 
 /* ------------------------------------------------------------------------------ */
-/* Coarse mesh for CMFD (Sec. 2.2, Alg. MOCHFEM_CMFD: MOC supplies the currents on  */
+/* Coarse mesh for CMFD (Sec. 2.1.2, Alg. MOCHFEM_CMFD: MOC supplies the currents on  */
 /* the radial coarse-cell surfaces). Each region belongs to one coarse cell. The    */
 /* surfaces are the ordered cell pairs that some track actually crosses between two */
 /* consecutive segments, plus (cell, boundary) where a track enters or leaves the   */

@@ -1,4 +1,4 @@
-// CMFD acceleration of the power iteration on a coarse mesh of cells (Sec. 2.2, Alg.
+// CMFD acceleration of the power iteration on a coarse mesh of cells (Sec. 2.1.2, Alg.
 // MOCHFEM_CMFD, radial part): after each transport sweep the fine scalar flux is
 // homogenised onto the coarse cells, the coarse-mesh eigenproblem is solved with the
 // sweep's net surface currents, and the fine flux and the incoming boundary fluxes are
