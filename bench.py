@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--no-dg", action="store_true", help="skip the DGMOC (extruded 3D) leg")
     ap.add_argument("--dg-only", action="store_true", help="run only the DGMOC leg (profiling)")
     ap.add_argument("--dg-steps", type=int, default=5)
+    ap.add_argument("--no-sn", action="store_true", help="skip the DFEM-SN leg")
+    ap.add_argument("--sn-only", action="store_true", help="run only the DFEM-SN leg (profiling)")
     ap.add_argument("--exp-mode", default="poly")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
@@ -170,6 +172,31 @@ def dg_leg(args):
     return out
 
 
+def sn_leg(args):
+    """DFEM-SN on the 17 x 17 lattice mesh: sweep time and local solves per second."""
+    import torch
+    from paper_2607_01591_amd import dfem
+    from paper_2607_01591_amd import problems as P
+    prob = P.config(2)
+    out = {"workload": f"{prob.name}: {len(prob.tri)} triangles (linear elements), {prob.n_groups} groups, "
+                       f"{prob.n_azim} azimuths x {prob.n_polar} polar = {prob.n_azim * prob.n_polar} directions, reflective"}
+    for prec in ("f32",) if args.no_f64 else ("f32", "f64"):
+        log(f"DFEM-SN {prec}: creating context")
+        s = dfem.SNSolver(prob, precision=prec, check_every=1 << 30)
+        ms, prof, r = time_iterations(s, 5, 1)
+        sw = prof["sweep_ms"] / max(1, prof["sweeps"])
+        n_solves = s.info["n_tasks"] * prob.n_groups
+        out[prec] = {"local_solves_per_sweep": n_solves, "solves_per_s": n_solves / (sw * 1e-3),
+                     "ms_per_iteration": ms, "sweep_ms": sw, "levels": s.info["n_levels"],
+                     "slots": s.info["n_slots"], "tasks": s.info["n_tasks"],
+                     "device_GiB": s.info["device_bytes"] / 2**30, "k_after": r["k"]}
+        log(f"DFEM-SN {prec}: {ms:.2f} ms/iteration, sweep {sw:.2f} ms, {n_solves / (sw * 1e-3):.3e} solves/s, "
+            f"{s.info['n_levels']} levels, {s.info['n_slots']} slots of {s.info['n_tasks']} tasks")
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -183,6 +210,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.dg_only:
         print(json.dumps({"dgmoc": dg_leg(args)}), flush=True)
+        return
+    if args.sn_only:
+        print(json.dumps({"dfem_sn": sn_leg(args)}), flush=True)
         return
     log(f"generating workload {args.workload}")
     prob = P.config(args.workload)
@@ -313,6 +343,10 @@ def main():
     if not args.no_dg:
         dg = dg_leg(args)
 
+    sn = None
+    if not args.no_sn:
+        sn = sn_leg(args)
+
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -343,6 +377,7 @@ def main():
         "cmfd_51x51": cmfd3,
         "hexagon_g33": hexa,
         "dgmoc_3d": dg,
+        "dfem_sn": sn,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
