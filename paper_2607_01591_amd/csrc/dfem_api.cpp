@@ -30,6 +30,7 @@ struct moc_sn_ctx {
     bool fissile = false, fixed_source = false;
     bool host_only = false;   // negative device ordinal: host setup and its checks only
     int cur_phi = 0, cur_bnd = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // the sweep's launches, one per boundary-buffer parity
     double setup_ms = 0;
     int64_t device_bytes = 0;
     double *host_scal = nullptr;
@@ -55,6 +56,8 @@ struct moc_sn_ctx {
     }
     ~moc_sn_ctx() {
         if (stream) (void)hipStreamSynchronize(stream);
+        for (auto &g : graph)
+            if (g) (void)hipGraphExecDestroy(g);
         for (auto *v : {&prof_pending, &prof_pool})
             for (auto &e : *v) {
                 (void)hipEventDestroy(e.first);
@@ -418,16 +421,11 @@ static std::pair<hipEvent_t, hipEvent_t> sn_prof_events(moc_sn_ctx *c) {
     return ev;
 }
 
-// One sweep with the emission in d.q: the scalar-flux accumulator is cleared, then one
-// launch per dependency level (every direction's elements of that level, all groups);
-// reflective inflow reads the boundary buffer of the previous sweep.
-static void sn_sweep_impl(moc_sn_ctx *c, hipStream_t s) {
+// The launches of one sweep with the emission in d.q: the scalar-flux accumulator is
+// cleared, then one launch per dependency level (every direction's elements of that level,
+// all groups); reflective inflow reads boundary buffer `parity`, outflow writes the other.
+static void sn_enqueue_sweep(moc_sn_ctx *c, int parity, hipStream_t s) {
     DevSN &d = c->d;
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    if (c->profiling) {
-        ev = sn_prof_events(c);
-        SN_HIP(hipEventRecord(ev.first, s));
-    }
     launch_sn_fill_f64(d.phi_acc, (int64_t)d.T * d.G * 3, 0.0, s);
     SnStepArgs a{};
     a.mass = d.mass;
@@ -445,8 +443,8 @@ static void sn_sweep_impl(moc_sn_ctx *c, hipStream_t s) {
     a.inflow = d.inflow;
     a.bwrite = d.bwrite;
     a.psi = d.psi;
-    a.bnd_in = d.bnd[c->cur_bnd];
-    a.bnd_out = d.bnd[1 - c->cur_bnd];
+    a.bnd_in = d.bnd[parity];
+    a.bnd_out = d.bnd[1 - parity];
     a.phi_acc = d.phi_acc;
     a.G = d.G;
     for (int st = 0; st < d.nsteps; ++st) {
@@ -454,6 +452,34 @@ static void sn_sweep_impl(moc_sn_ctx *c, hipStream_t s) {
         a.k1 = d.step_off[st + 1];
         launch_sn_step(a, d.precision, s);
     }
+}
+
+// One sweep. The hundreds of small per-level launches are recorded once per parity into
+// a HIP graph (kernel nodes only; the accumulator is cleared by a kernel) and replayed,
+// which removes most of the per-launch cost.
+static void sn_sweep_impl(moc_sn_ctx *c, hipStream_t s) {
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    const int parity = c->cur_bnd;
+    if (!c->graph[parity]) {
+        hipGraph_t g = nullptr;
+        SN_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        try {
+            sn_enqueue_sweep(c, parity, c->stream);
+        } catch (...) {
+            (void)hipStreamEndCapture(c->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        SN_HIP(hipStreamEndCapture(c->stream, &g));
+        const hipError_t ie = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) throw Error(MOC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    if (c->profiling) {
+        ev = sn_prof_events(c);
+        SN_HIP(hipEventRecord(ev.first, s));
+    }
+    SN_HIP(hipGraphLaunch(c->graph[parity], s));
     c->cur_bnd = 1 - c->cur_bnd;
     if (c->profiling) {
         SN_HIP(hipEventRecord(ev.second, s));

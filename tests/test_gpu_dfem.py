@@ -1,7 +1,8 @@
 """DFEM-SN on the GPU against the FP64 DFEM-SN oracle, through the C ABI.
 
-* Two consecutive sweeps from the cold state with random emission moments (slopes
-  included; the second sweep takes its reflective inflow from the first), over problems
+* Four consecutive sweeps from the cold state with random emission moments (slopes
+  included; each takes its reflective inflow from the one before; the last two replay
+  the recorded sweep graphs), over problems
   with vacuum, reflective and mixed sides, 1 to 4 polar angles and 1 to 7 groups. FP64
   to 1e-11, FP32 to 1e-5, relative to the largest element average of the group.
 * Converged eigenvalue and fixed-source solves against the oracle's.
@@ -62,14 +63,14 @@ CASES = [
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
-def test_two_sweeps_match_oracle(name, make, precision, cuda):
+def test_sweeps_match_oracle(name, make, precision, cuda):
     log(f"[dfem sweeps] {name} {precision}")
     prob = make()
     o = SN.SNOracle(prob)
     s = dfem.SNSolver(prob, precision=precision)
     rng = np.random.default_rng(8)
     tol = 1e-11 if precision == "f64" else 1e-5
-    for k in range(2):
+    for k in range(4):   # sweeps 3 and 4 replay the recorded sweep graphs
         src = rng.uniform(0.1, 2.0, o.shape())
         src[..., 1:] = rng.uniform(-0.5, 0.5, src[..., 1:].shape)
         ref = o.sweep(src)
