@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--dg-steps", type=int, default=5)
     ap.add_argument("--no-sn", action="store_true", help="skip the DFEM-SN leg")
     ap.add_argument("--sn-only", action="store_true", help="run only the DFEM-SN leg (profiling)")
+    ap.add_argument("--no-hfem", action="store_true", help="skip the HFEM leg")
+    ap.add_argument("--hfem-only", action="store_true", help="run only the HFEM leg (profiling)")
+    ap.add_argument("--hfem-max-iter", type=int, default=5000, help="iteration cap of the HFEM solve")
     ap.add_argument("--exp-mode", default="poly")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
@@ -197,6 +200,48 @@ def sn_leg(args):
     return out
 
 
+def hfem_leg(args):
+    """Diffusion HFEM on the 51 x 51 x 32 pin-cell core (7 groups, volume order 2, face
+    order 1): device preassembly time, red-black sweep time against the HBM roofline, and
+    the eigenvalue solve to 1e-6."""
+    import torch
+    from paper_2607_01591_amd import hfem
+    from paper_2607_01591_amd import problems as P
+    g = P.brick_core()
+    log("HFEM: creating context (host checks, uploads, device preassembly)")
+    s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2, check_every=1 << 30)
+    inf = s.info
+    N, G, Np, Nft = inf["n_nodes"], inf["n_groups"], inf["n_moments"], inf["n_face_dofs"]
+    ms, prof, r = time_iterations(s, 20, 2)
+    rb_ms = prof["sweep_ms"] / max(1, prof["sweeps"])
+    # per node-group and red-black iteration: R once, B s once, the gathered J- and the
+    # written J+ (FP64)
+    per_pg = 8 * (Nft * Nft + 3 * Nft)
+    alg = N * G * per_pg
+    gbs = alg / (rb_ms * 1e-3) / 1e9
+    out = {"workload": f"{g.name}: {N} pin-cell nodes ({len(g.edges[0]) - 1} x {len(g.edges[1]) - 1} x "
+                       f"{len(g.edges[2]) - 1}), {G} groups, volume order 2 ({Np} moments), face order 1 "
+                       f"({Nft} face DoFs), per-node cross sections, 2 red-black iterations per outer iteration",
+           "setup_ms": inf["setup_ms"], "assemble_ms": inf["assemble_ms"], "device_GiB": inf["device_bytes"] / 2**30,
+           "ms_per_iteration": ms, "rb_iteration_ms": rb_ms, "dof_updates_per_s": N * G * Nft / (rb_ms * 1e-3),
+           "roofline": {"bound": "hbm", "kernel": "moc::k_hf_rb", "algorithmic_bytes": alg, "bytes_per_node_group": per_pg,
+                        "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}}
+    log(f"HFEM: preassembly {inf['assemble_ms']:.1f} ms, {ms:.3f} ms/iteration, red-black iteration {rb_ms:.3f} ms "
+        f"= {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.2f} of HBM peak)")
+    del s
+    torch.cuda.empty_cache()
+    s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2, max_iter=args.hfem_max_iter,
+                        check_every=10)
+    r = s.solve(1e-6)
+    out["solve"] = {"tol": 1e-6, "k": r["k"], "iterations": r["iterations"], "converged": r["converged"],
+                    "wall_ms": r["wall_ms"]}
+    log(f"HFEM: solve to 1e-6: k = {r['k']:.6f}, {r['iterations']} iterations, {r['wall_ms']:.0f} ms, "
+        f"converged {r['converged']}")
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -213,6 +258,9 @@ def main():
         return
     if args.sn_only:
         print(json.dumps({"dfem_sn": sn_leg(args)}), flush=True)
+        return
+    if args.hfem_only:
+        print(json.dumps({"hfem": hfem_leg(args)}), flush=True)
         return
     log(f"generating workload {args.workload}")
     prob = P.config(args.workload)
@@ -347,6 +395,10 @@ def main():
     if not args.no_sn:
         sn = sn_leg(args)
 
+    hf = None
+    if not args.no_hfem:
+        hf = hfem_leg(args)
+
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -378,6 +430,7 @@ def main():
         "hexagon_g33": hexa,
         "dgmoc_3d": dg,
         "dfem_sn": sn,
+        "hfem": hf,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -258,6 +258,8 @@ class HFEMOracle:
 
     # ------------------------------------------------------------------ outer iteration
     def solve(self, tol=1e-8, max_iter=5000):
+        """Outer iterations from a cold start (phi_0 = 1, currents 0, k = 1)."""
+        self.reset()
         fixed = self.qext is not None
         it, res, dk = 0, np.inf, np.inf
         while it < max_iter:
@@ -283,6 +285,8 @@ class HFEMOracle:
         return dict(k=self.k, phi=self.phi.copy(), iterations=it, residual=res, converged=False)
 
     def run_iterations(self, n):
+        """Exactly n outer iterations from a cold start."""
+        self.reset()
         fixed = self.qext is not None
         for _ in range(n):
             phi_old, k_old = self.phi, self.k

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libmoc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["moc_setup.cpp", "moc_pack.cpp", "moc_api.cpp", "moc_kernels.hip", "moc_cmfd.hip", "dg_api.cpp",
-           "dg_kernels.hip", "dfem_api.cpp", "dfem_kernels.hip", "cnn_kernels.hip"]
+           "dg_kernels.hip", "dfem_api.cpp", "dfem_kernels.hip", "hfem_api.cpp", "hfem_kernels.hip", "cnn_kernels.hip"]
 
 # Packed FP32 instructions are disabled for all device code: hipcc would otherwise form
 # them from ordinary float arithmetic.

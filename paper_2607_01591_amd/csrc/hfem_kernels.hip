@@ -1,0 +1,559 @@
+// HIP kernels of libmoc's diffusion HFEM solver for gfx950 (CDNA4): the batched
+// preassembly of every node's response matrices, the source update, the red-black
+// response-matrix sweep, the flux reconstruction and the FP64 reductions of the power
+// iteration (Sec. 2.1.2, Eq. HFEM_flux_response; Sec. 3.1).
+//
+// Per node and group, with the Legendre bases of hfem.h (volume u_i with
+// (u_i, u_j) = V delta_ij, face v_m with <v_m, v_n>_f = A_f delta_mn):
+//   A_ij  = D (grad u_i, grad u_j) + Sigma_r V delta_ij            (reaction matrix)
+//   M_ri  = <v_m, u_i>_f = A_f t_ri,  r = (f, m)                    (face coupling)
+//   C     = Lambda^-1 M A^-1,  Y = C M^T
+//   J+    = R J- + B s,  R = (2I + Y)^-1 (Y - 2I) = I - 4 (2I + Y)^-1,  B = (2I + Y)^-1 C
+//   phi   = A^-1 s - P (J+ - J-),  P = A^-1 M^T
+// The Legendre integrals are closed forms: on [-1, 1] with p_a = sqrt(2a+1) P_a,
+// int p_a p_b = 2 delta_ab, int p_a' p_b' = sqrt((2a+1)(2b+1)) min(a,b) (min(a,b)+1) when
+// a + b is even (else 0), and p_a(+-1) = sqrt(2a+1) (+-1)^a; so
+// (d_x u_i, d_x u_j) = (2 V / hx^2) k(a_i, a_j) delta(b) delta(c), and the face factor
+// t_ri = p_(a_d)(+-1) when the transverse degrees of u_i equal those of v_m, else 0.
+#include <cmath>
+
+#include "hfem_kernels.h"
+#include "moc.h"
+#include "moc_internal.h"
+
+namespace moc {
+
+__device__ __forceinline__ double hf_stiff1d(int a, int b) {
+    if ((a + b) & 1) return 0.0;
+    const int m = a < b ? a : b;
+    return sqrt((double)((2 * a + 1) * (2 * b + 1))) * (double)(m * (m + 1));
+}
+
+// face factor t of face DoF r and volume mode i (0 when the transverse degrees differ)
+__device__ __forceinline__ double hf_face_factor(const int *__restrict__ vmode, const int *__restrict__ fmode, int Nfb,
+                                                 int r, int i) {
+    const int f = r / Nfb, mm = r - f * Nfb;
+    const int d = f >> 1;
+    const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+    const int *vi = vmode + 3 * i;
+    if (vi[t0] != fmode[2 * mm] || vi[t1] != fmode[2 * mm + 1]) return 0.0;
+    const int a = vi[d];
+    const double v = sqrt((double)(2 * a + 1));
+    return (f & 1) ? v : ((a & 1) ? -v : v);
+}
+
+__device__ __forceinline__ double hf_face_area(const double *h, int r, int Nfb) {
+    const int d = (r / Nfb) >> 1;
+    return d == 0 ? h[1] * h[2] : (d == 1 ? h[0] * h[2] : h[0] * h[1]);
+}
+
+// In-place Gauss-Jordan elimination with partial pivoting of the n x 2n augmented matrix
+// W (row stride 2n, in LDS) by one wavefront: on return the right half holds the inverse
+// of the left half. Lane r eliminates row r; the pivot row is chosen by lane 0.
+__device__ void hf_gauss_jordan(double *W, int n, int *piv_sh, int *status) {
+    const int lane = threadIdx.x;
+    const int w = 2 * n;
+    for (int c = 0; c < n; ++c) {
+        if (lane == 0) {
+            int piv = c;
+            double best = fabs(W[c * w + c]);
+            for (int r = c + 1; r < n; ++r) {
+                const double v = fabs(W[r * w + c]);
+                if (v > best) {
+                    best = v;
+                    piv = r;
+                }
+            }
+            *piv_sh = piv;
+            if (!(best > 0.0)) *status = 1;
+        }
+        __syncthreads();
+        const int piv = *piv_sh;
+        if (piv != c)
+            for (int j = lane; j < w; j += 64) {
+                const double t = W[c * w + j];
+                W[c * w + j] = W[piv * w + j];
+                W[piv * w + j] = t;
+            }
+        __syncthreads();
+        const double inv = 1.0 / W[c * w + c];
+        __syncthreads();
+        for (int j = lane; j < w; j += 64) W[c * w + j] *= inv;
+        __syncthreads();
+        if (lane < n && lane != c) {
+            const double f = W[lane * w + c];
+            for (int j = 0; j < w; ++j) W[lane * w + j] -= f * W[c * w + j];
+        }
+        __syncthreads();
+    }
+}
+
+struct HfAsmArgs {
+    const int *perm, *mat, *vmode, *fmode;
+    const double *hdim, *diff, *sigr;
+    double *R, *B, *Ainv, *P;
+    int *status;
+    int G, Np, Nfb, Nft, wsize;
+};
+
+// Preassembly: one wavefront per (colour-sorted node, group). Builds A and inverts it,
+// forms C and 2I + Y and inverts that, and writes R, B, A^-1 and P column-major.
+__global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
+    extern __shared__ double lds[];
+    __shared__ int piv_sh;
+    const int pg = blockIdx.x;
+    const int G = a.G, Np = a.Np, Nfb = a.Nfb, Nft = a.Nft;
+    const int p = pg / G, g = pg - p * G;
+    const int lane = threadIdx.x;
+    const int m = a.mat[a.perm[p]];
+    const double h[3] = {a.hdim[3 * p], a.hdim[3 * p + 1], a.hdim[3 * p + 2]};
+    const double V = h[0] * h[1] * h[2];
+    const double D = a.diff[m * G + g], sr = a.sigr[m * G + g];
+    double *W = lds;              // [n][2n] work
+    double *Ai = W + a.wsize;     // [Np][Np] row-major
+    double *Cm = Ai + Np * Np;    // [Nft][Np] row-major
+    // reaction matrix | identity
+    for (int idx = lane; idx < Np * Np; idx += 64) {
+        const int i = idx / Np, j = idx - i * Np;
+        const int *vi = a.vmode + 3 * i, *vj = a.vmode + 3 * j;
+        double k = 0.0;
+        if (vi[1] == vj[1] && vi[2] == vj[2]) k += hf_stiff1d(vi[0], vj[0]) / (h[0] * h[0]);
+        if (vi[0] == vj[0] && vi[2] == vj[2]) k += hf_stiff1d(vi[1], vj[1]) / (h[1] * h[1]);
+        if (vi[0] == vj[0] && vi[1] == vj[1]) k += hf_stiff1d(vi[2], vj[2]) / (h[2] * h[2]);
+        W[i * 2 * Np + j] = D * 2.0 * V * k + (i == j ? sr * V : 0.0);
+        W[i * 2 * Np + Np + j] = i == j ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    hf_gauss_jordan(W, Np, &piv_sh, a.status);
+    for (int idx = lane; idx < Np * Np; idx += 64) {
+        const int i = idx / Np, j = idx - i * Np;
+        Ai[idx] = W[i * 2 * Np + Np + j];
+    }
+    __syncthreads();
+    // C = Lambda^-1 M A^-1: C_rj = sum_i t_ri Ainv_ij
+    for (int idx = lane; idx < Nft * Np; idx += 64) {
+        const int r = idx / Np, j = idx - r * Np;
+        double acc = 0.0;
+        for (int i = 0; i < Np; ++i) {
+            const double t = hf_face_factor(a.vmode, a.fmode, Nfb, r, i);
+            if (t != 0.0) acc += t * Ai[i * Np + j];
+        }
+        Cm[idx] = acc;
+    }
+    __syncthreads();
+    // 2I + Y | identity, Y_rc = C_r . M_c = A_c sum_i C_ri t_ci
+    for (int idx = lane; idx < Nft * Nft; idx += 64) {
+        const int r = idx / Nft, c = idx - r * Nft;
+        double acc = 0.0;
+        for (int i = 0; i < Np; ++i) {
+            const double t = hf_face_factor(a.vmode, a.fmode, Nfb, c, i);
+            if (t != 0.0) acc += Cm[r * Np + i] * t;
+        }
+        W[r * 2 * Nft + c] = hf_face_area(h, c, Nfb) * acc + (r == c ? 2.0 : 0.0);
+        W[r * 2 * Nft + Nft + c] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    hf_gauss_jordan(W, Nft, &piv_sh, a.status);
+    const int64_t base = (int64_t)pg;
+    // R = I - 4 K^-1 (K = 2I + Y), column-major
+    for (int idx = lane; idx < Nft * Nft; idx += 64) {
+        const int j = idx / Nft, i = idx - j * Nft;
+        a.R[base * Nft * Nft + idx] = (i == j ? 1.0 : 0.0) - 4.0 * W[i * 2 * Nft + Nft + j];
+    }
+    // B = K^-1 C, column-major
+    for (int idx = lane; idx < Np * Nft; idx += 64) {
+        const int k = idx / Nft, i = idx - k * Nft;
+        double acc = 0.0;
+        for (int r = 0; r < Nft; ++r) acc += W[i * 2 * Nft + Nft + r] * Cm[r * Np + k];
+        a.B[base * Np * Nft + idx] = acc;
+    }
+    // A^-1, column-major (symmetric up to rounding; stored as computed)
+    for (int idx = lane; idx < Np * Np; idx += 64) {
+        const int k = idx / Np, i = idx - k * Np;
+        a.Ainv[base * Np * Np + idx] = Ai[i * Np + k];
+    }
+    // P = A^-1 M^T: P_ic = A_c sum_k Ainv_ik t_ck, column-major
+    for (int idx = lane; idx < Nft * Np; idx += 64) {
+        const int c = idx / Np, i = idx - c * Np;
+        double acc = 0.0;
+        for (int k = 0; k < Np; ++k) {
+            const double t = hf_face_factor(a.vmode, a.fmode, Nfb, c, k);
+            if (t != 0.0) acc += Ai[i * Np + k] * t;
+        }
+        a.P[base * Nft * Np + idx] = hf_face_area(h, c, Nfb) * acc;
+    }
+}
+
+// Source moments s = V Q in colour-sorted order, Q_g,i = chi_g F_i / k
+// + sum_{g' != g} Sigma_s,g'->g phi_g',i (+ external); one thread per (node, group).
+__global__ void k_hf_source(const double *__restrict__ phi, const double *__restrict__ scal, const int *__restrict__ mat,
+                            const int *__restrict__ pos, const double *__restrict__ vol, const double *__restrict__ sigs,
+                            const double *__restrict__ nsf, const double *__restrict__ chi,
+                            const double *__restrict__ qext, double *__restrict__ s, int N, int G, int Np) {
+    const double inv_k = 1.0 / scal[kHfK];
+    const int64_t n = (int64_t)N * G;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int e = int(t / G), g = int(t - (int64_t)e * G);
+        const int m = mat[e];
+        const double *ph = phi + (int64_t)e * G * Np;
+        const double cg = chi[m * G + g] * inv_k;
+        double *out = s + ((int64_t)pos[e] * G + g) * Np;
+        for (int i = 0; i < Np; ++i) {
+            double q = 0.0;
+            for (int gp = 0; gp < G; ++gp) {
+                const double x = ph[gp * Np + i];
+                q += cg * nsf[m * G + gp] * x;
+                if (gp != g) q += sigs[((int64_t)m * G + gp) * G + g] * x;
+            }
+            if (qext) q += qext[t * Np + i];
+            out[i] = vol[e] * q;
+        }
+    }
+}
+
+// s = V src (caller's emission moments), colour-sorted
+__global__ void k_hf_user_source(const double *__restrict__ src, const int *__restrict__ pos,
+                                 const double *__restrict__ vol, double *__restrict__ s, int N, int G, int Np) {
+    const int64_t n = (int64_t)N * G * Np;
+    const int64_t per_node = (int64_t)G * Np;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int e = int(t / per_node);
+        s[(int64_t)pos[e] * per_node + (t - e * per_node)] = vol[e] * src[t];
+    }
+}
+
+// bq = B s; one thread per (node-group, face DoF); columns of B are contiguous.
+__global__ void k_hf_bq(const double *__restrict__ B, const double *__restrict__ s, double *__restrict__ bq, int64_t npg,
+                        int Np, int Nft) {
+    const int64_t n = npg * Nft;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pg = t / Nft;
+        const int i = int(t - pg * Nft);
+        const double *Bc = B + pg * Np * Nft + i;
+        const double *sv = s + pg * Np;
+        double acc = 0.0;
+        for (int k = 0; k < Np; ++k) acc += Bc[(int64_t)k * Nft] * sv[k];
+        bq[t] = acc;
+    }
+}
+
+// Incoming partial current of face DoF i of colour-sorted node p, group g.
+__device__ __forceinline__ double hf_incoming(const double *__restrict__ jp, const int *__restrict__ nbr, int p, int g,
+                                              int i, int G, int Nfb, int Nft) {
+    const int f = i / Nfb, mm = i - f * Nfb;
+    const int code = nbr[6 * p + f];
+    if (code >= 0) return jp[((int64_t)code * G + g) * Nft + (f ^ 1) * Nfb + mm];
+    if (code == kHfReflect) return jp[((int64_t)p * G + g) * Nft + i];
+    return 0.0;
+}
+
+// Red-black half sweep over the nodes [p0, p0 + count) of one colour (Eq. HFEM_flux_response):
+// J+ = R J- + B s. Each block holds whole node-groups: the incoming currents of its
+// node-groups are gathered into LDS first (a node's own outgoing currents feed its
+// reflective faces, so they are read before any is overwritten), then thread (node-group,
+// i) forms row i of R J- from the contiguous columns of R.
+__global__ void __launch_bounds__(256) k_hf_rb(const double *__restrict__ R, const double *__restrict__ bq,
+                                               double *__restrict__ jp, const int *__restrict__ nbr, int p0, int count,
+                                               int G, int Nfb, int Nft, int npg_blk) {
+    __shared__ double jm[256];
+    const int64_t pg0 = (int64_t)p0 * G + (int64_t)blockIdx.x * npg_blk;
+    const int64_t pg_end = (int64_t)(p0 + count) * G;
+    const int t = threadIdx.x;
+    const int pl = t / Nft, i = t - pl * Nft;
+    const int64_t pg = pg0 + pl;
+    const bool active = pl < npg_blk && pg < pg_end;
+    if (active) {
+        const int p = int(pg / G), g = int(pg - (int64_t)p * G);
+        jm[t] = hf_incoming(jp, nbr, p, g, i, G, Nfb, Nft);
+    }
+    __syncthreads();
+    if (active) {
+        const double *Rc = R + pg * Nft * Nft + i;
+        const double *x = jm + pl * Nft;
+        double acc = bq[pg * Nft + i];
+        for (int j = 0; j < Nft; ++j) acc += Rc[(int64_t)j * Nft] * x[j];
+        jp[pg * Nft + i] = acc;
+    }
+}
+
+// phi = A^-1 s - P (J+ - J-), written in node order; each block holds whole node-groups.
+__global__ void __launch_bounds__(256) k_hf_reconstruct(const double *__restrict__ Ainv, const double *__restrict__ P,
+                                                        const double *__restrict__ s, const double *__restrict__ jp,
+                                                        const int *__restrict__ nbr, const int *__restrict__ perm,
+                                                        double *__restrict__ phi, int N, int G, int Np, int Nfb, int Nft,
+                                                        int npg_blk) {
+    __shared__ double net[256];
+    const int64_t pg0 = (int64_t)blockIdx.x * npg_blk;
+    const int64_t npg = (int64_t)N * G;
+    for (int t = threadIdx.x; t < npg_blk * Nft; t += blockDim.x) {
+        const int pl = t / Nft, i = t - pl * Nft;
+        const int64_t pg = pg0 + pl;
+        if (pg < npg) {
+            const int p = int(pg / G), g = int(pg - (int64_t)p * G);
+            net[t] = jp[pg * Nft + i] - hf_incoming(jp, nbr, p, g, i, G, Nfb, Nft);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < npg_blk * Np; t += blockDim.x) {
+        const int pl = t / Np, i = t - pl * Np;
+        const int64_t pg = pg0 + pl;
+        if (pg >= npg) continue;
+        const int p = int(pg / G), g = int(pg - (int64_t)p * G);
+        const double *Ac = Ainv + pg * Np * Np + i;
+        const double *Pc = P + pg * Nft * Np + i;
+        const double *sv = s + pg * Np;
+        const double *nv = net + pl * Nft;
+        double acc = 0.0;
+        for (int k = 0; k < Np; ++k) acc += Ac[(int64_t)k * Np] * sv[k];
+        for (int j = 0; j < Nft; ++j) acc -= Pc[(int64_t)j * Np] * nv[j];
+        phi[((int64_t)perm[p] * G + g) * Np + i] = acc;
+    }
+}
+
+__device__ __forceinline__ double hf_block_sum(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// partials of sum_e V nuSigma_f phi_0 for the new and the old iterate
+__global__ void k_hf_fission(const double *__restrict__ phi_new, const double *__restrict__ phi_old,
+                             const double *__restrict__ vol, const int *__restrict__ mat, const double *__restrict__ nsf,
+                             double *__restrict__ partials, int N, int G, int Np) {
+    __shared__ double sh[16];
+    double fn = 0.0, fo = 0.0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x) {
+        const int m = mat[e];
+        double xn = 0.0, xo = 0.0;
+        for (int g = 0; g < G; ++g) {
+            xn += nsf[m * G + g] * phi_new[((int64_t)e * G + g) * Np];
+            xo += nsf[m * G + g] * phi_old[((int64_t)e * G + g) * Np];
+        }
+        fn += vol[e] * xn;
+        fo += vol[e] * xo;
+    }
+    fn = hf_block_sum(fn, sh);
+    fo = hf_block_sum(fo, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = fn;
+        partials[2 * blockIdx.x + 1] = fo;
+    }
+}
+
+// Single block: k <- k F_new / F_old (eigen) or k kept (fixed source).
+__global__ void k_hf_eigen(const double *__restrict__ partials, int nblk, double *__restrict__ scal, int fixed_source) {
+    __shared__ double sh[16];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
+    }
+    a = hf_block_sum(a, sh);
+    b = hf_block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        const double k = scal[kHfK];
+        scal[kHfKPrev] = k;
+        scal[kHfFnew] = a;
+        scal[kHfFold] = b;
+        if (!fixed_source) {
+            scal[kHfK] = k * a / b;
+            scal[kHfDk] = fabs(scal[kHfK] - k);
+        } else {
+            scal[kHfDk] = 0.0;
+        }
+    }
+}
+
+// partials of the residual norms: eigen, the normalised fission-rate shapes
+// a = nuSigma_f phi_0 / F_new, b = ... / F_old: sum V (a - b)^2, sum V a^2; fixed source:
+// sum over nodes and groups of V (phi_0,new - phi_0,old)^2 and V phi_0,new^2.
+__global__ void k_hf_residual_partials(const double *__restrict__ phi_new, const double *__restrict__ phi_old,
+                                       const double *__restrict__ vol, const int *__restrict__ mat,
+                                       const double *__restrict__ nsf, const double *__restrict__ scal,
+                                       double *__restrict__ partials, int N, int G, int Np, int fixed_source) {
+    __shared__ double sh[16];
+    const double rn = fixed_source ? 1.0 : 1.0 / scal[kHfFnew];
+    const double ro = fixed_source ? 1.0 : 1.0 / scal[kHfFold];
+    double num = 0.0, den = 0.0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x) {
+        const int m = mat[e];
+        if (fixed_source) {
+            for (int g = 0; g < G; ++g) {
+                const double a = phi_new[((int64_t)e * G + g) * Np], b = phi_old[((int64_t)e * G + g) * Np];
+                num += vol[e] * (a - b) * (a - b);
+                den += vol[e] * a * a;
+            }
+        } else {
+            double xn = 0.0, xo = 0.0;
+            for (int g = 0; g < G; ++g) {
+                xn += nsf[m * G + g] * phi_new[((int64_t)e * G + g) * Np];
+                xo += nsf[m * G + g] * phi_old[((int64_t)e * G + g) * Np];
+            }
+            const double a = xn * rn, b = xo * ro;
+            num += vol[e] * (a - b) * (a - b);
+            den += vol[e] * a * a;
+        }
+    }
+    num = hf_block_sum(num, sh);
+    den = hf_block_sum(den, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = num;
+        partials[2 * blockIdx.x + 1] = den;
+    }
+}
+
+__global__ void k_hf_residual_final(const double *__restrict__ partials, int nblk, double *__restrict__ scal) {
+    __shared__ double sh[16];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
+    }
+    a = hf_block_sum(a, sh);
+    b = hf_block_sum(b, sh);
+    if (threadIdx.x == 0) scal[kHfRes] = sqrt(a / (b > 1e-300 ? b : 1e-300));
+}
+
+// outgoing currents from colour-sorted to node order
+__global__ void k_hf_currents_to_nodes(const double *__restrict__ jp, const int *__restrict__ perm,
+                                       double *__restrict__ out, int N, int64_t per_node) {
+    const int64_t n = (int64_t)N * per_node;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int p = int(t / per_node);
+        out[(int64_t)perm[p] * per_node + (t - p * per_node)] = jp[t];
+    }
+}
+
+// cold flux: phi_0 = 1, higher moments 0
+__global__ void k_hf_cold(double *__restrict__ phi, int64_t n, int Np) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        phi[t] = (t % Np) == 0 ? 1.0 : 0.0;
+}
+
+__global__ void k_hf_fill(double *__restrict__ p, int64_t n, double v) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+// ----------------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------------
+
+static void hf_check_launch() {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(MOC_EHIP, hipGetErrorString(e));
+}
+
+static int hf_grid(int64_t n, int block = 256, int cap = 16384) {
+    const int64_t b = (n + block - 1) / block;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+void launch_hf_assemble(const DevHF &d, hipStream_t s) {
+    HfAsmArgs a{};
+    a.perm = d.perm;
+    a.mat = d.mat;
+    a.vmode = d.vmode;
+    a.fmode = d.fmode;
+    a.hdim = d.hdim;
+    a.diff = d.diff;
+    a.sigr = d.sigr;
+    a.R = d.R;
+    a.B = d.B;
+    a.Ainv = d.Ainv;
+    a.P = d.P;
+    a.status = d.status;
+    a.G = d.G;
+    a.Np = d.Np;
+    a.Nfb = d.Nfb;
+    a.Nft = d.Nft;
+    a.wsize = 2 * (d.Np > d.Nft ? d.Np * d.Np : d.Nft * d.Nft);
+    const size_t lds = sizeof(double) * ((size_t)a.wsize + (size_t)d.Np * d.Np + (size_t)d.Nft * d.Np);
+    const int64_t npg = (int64_t)d.N * d.G;
+    if (npg <= 0) return;
+    k_hf_assemble<<<(unsigned)npg, 64, lds, s>>>(a);
+    hf_check_launch();
+}
+
+void launch_hf_source(const DevHF &d, const double *phi, hipStream_t s) {
+    const int64_t n = (int64_t)d.N * d.G;
+    k_hf_source<<<hf_grid(n), 256, 0, s>>>(phi, d.scal, d.mat, d.pos, d.vol, d.sigs, d.nsf, d.chi, d.qext, d.s, d.N,
+                                           d.G, d.Np);
+    hf_check_launch();
+}
+
+void launch_hf_user_source(const DevHF &d, const double *src, hipStream_t s) {
+    const int64_t n = (int64_t)d.N * d.G * d.Np;
+    k_hf_user_source<<<hf_grid(n), 256, 0, s>>>(src, d.pos, d.vol, d.s, d.N, d.G, d.Np);
+    hf_check_launch();
+}
+
+void launch_hf_bq(const DevHF &d, hipStream_t s) {
+    const int64_t npg = (int64_t)d.N * d.G;
+    k_hf_bq<<<hf_grid(npg * d.Nft), 256, 0, s>>>(d.B, d.s, d.bq, npg, d.Np, d.Nft);
+    hf_check_launch();
+}
+
+void launch_hf_rb(const DevHF &d, int colour, hipStream_t s) {
+    const int p0 = colour == 0 ? 0 : d.n_red;
+    const int count = colour == 0 ? d.n_red : d.N - d.n_red;
+    if (count <= 0) return;
+    const int npg_blk = 256 / d.Nft;
+    const int64_t npg = (int64_t)count * d.G;
+    const int64_t blocks = (npg + npg_blk - 1) / npg_blk;
+    k_hf_rb<<<(unsigned)blocks, 256, 0, s>>>(d.R, d.bq, d.jp, d.nbr, p0, count, d.G, d.Nfb, d.Nft, npg_blk);
+    hf_check_launch();
+}
+
+void launch_hf_reconstruct(const DevHF &d, double *phi_out, hipStream_t s) {
+    const int npg_blk = 256 / d.Nft;
+    const int64_t npg = (int64_t)d.N * d.G;
+    const int64_t blocks = (npg + npg_blk - 1) / npg_blk;
+    k_hf_reconstruct<<<(unsigned)blocks, 256, 0, s>>>(d.Ainv, d.P, d.s, d.jp, d.nbr, d.perm, phi_out, d.N, d.G, d.Np,
+                                                      d.Nfb, d.Nft, npg_blk);
+    hf_check_launch();
+}
+
+void launch_hf_fission(const DevHF &d, const double *phi_new, const double *phi_old, hipStream_t s) {
+    k_hf_fission<<<kHfReduceBlocks, 256, 0, s>>>(phi_new, phi_old, d.vol, d.mat, d.nsf, d.partials, d.N, d.G, d.Np);
+    hf_check_launch();
+}
+
+void launch_hf_eigen(const DevHF &d, int fixed_source, hipStream_t s) {
+    k_hf_eigen<<<1, 256, 0, s>>>(d.partials, kHfReduceBlocks, d.scal, fixed_source);
+    hf_check_launch();
+}
+
+void launch_hf_residual(const DevHF &d, const double *phi_new, const double *phi_old, int fixed_source,
+                        hipStream_t s) {
+    k_hf_residual_partials<<<kHfReduceBlocks, 256, 0, s>>>(phi_new, phi_old, d.vol, d.mat, d.nsf, d.scal, d.partials,
+                                                           d.N, d.G, d.Np, fixed_source);
+    k_hf_residual_final<<<1, 256, 0, s>>>(d.partials, kHfReduceBlocks, d.scal);
+    hf_check_launch();
+}
+
+void launch_hf_currents_to_nodes(const DevHF &d, double *out, hipStream_t s) {
+    const int64_t per_node = (int64_t)d.G * d.Nft;
+    k_hf_currents_to_nodes<<<hf_grid((int64_t)d.N * per_node), 256, 0, s>>>(d.jp, d.perm, out, d.N, per_node);
+    hf_check_launch();
+}
+
+void launch_hf_cold(const DevHF &d, double *phi, hipStream_t s) {
+    const int64_t n = (int64_t)d.N * d.G * d.Np;
+    k_hf_cold<<<hf_grid(n), 256, 0, s>>>(phi, n, d.Np);
+    hf_check_launch();
+}
+
+void launch_hf_fill(double *p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return;
+    k_hf_fill<<<hf_grid(n), 256, 0, s>>>(p, n, v);
+    hf_check_launch();
+}
+
+}  // namespace moc

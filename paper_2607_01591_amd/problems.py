@@ -588,3 +588,84 @@ def coarse_cells(p: Problem, nx: int, ny: int):
     raw = iy * nx + ix
     used, region_cell = np.unique(raw, return_inverse=True)
     return int(len(used)), region_cell.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------------
+# coarse brick grids (diffusion HFEM)
+# ----------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class BrickGrid:
+    """Rectilinear grid of brick nodes with one material per node; node e = (k ny + j) nx + i.
+    bc per side x-, x+, y-, y+, z-, z+."""
+    name: str
+    edges: tuple            # (x_edges, y_edges, z_edges)
+    node_material: np.ndarray
+    sigma_t: np.ndarray
+    sigma_s: np.ndarray
+    nu_sigma_f: np.ndarray
+    chi: np.ndarray
+    bc: tuple
+
+    @property
+    def n_nodes(self) -> int:
+        return int(np.prod([len(e) - 1 for e in self.edges]))
+
+    @property
+    def n_groups(self) -> int:
+        return int(self.sigma_t.shape[1])
+
+
+def brick_box(nx: int, ny: int, nz: int, *, G: int, n_fuel: int, n_other: int, seed: int, bc=(1, 1, 1, 1, 1, 1),
+              size=(3.0, 2.5, 4.0), jitter: float = 0.3, upscatter: bool = True) -> BrickGrid:
+    """Small test grid. Draw order: cross sections (draw_xs), then per axis the node
+    widths size / n * U[1 - jitter, 1 + jitter] rescaled to the axis length, then the node
+    materials U{0..M-1}."""
+    rng = np.random.default_rng(seed)
+    st, ss, nsf, chi = draw_xs(rng, n_fuel, n_other, G, upscatter=upscatter)
+    edges = []
+    for n, L in zip((nx, ny, nz), size):
+        w = rng.uniform(1 - jitter, 1 + jitter, n)
+        edges.append(np.concatenate([[0.0], np.cumsum(w / w.sum() * L)]))
+    mat = rng.integers(0, n_fuel + n_other, nx * ny * nz).astype(np.int32)
+    return BrickGrid(f"box{nx}x{ny}x{nz}_g{G}", tuple(edges), mat, st, ss, nsf, chi, tuple(int(b) for b in bc))
+
+
+def brick_core(n_pins: int = 51, n_fuel_pins: int = 34, pitch: float = 1.26, n_planes: int = 32,
+               height: float = 85.68, fuel_height: float = 64.26, G: int = 7, seed: int = 5,
+               perturb: float = 0.02) -> BrickGrid:
+    """C5G7-like 3D quarter core on pin-cell nodes: n_pins x n_pins pin cells of the given
+    pitch, the first n_fuel_pins x n_fuel_pins of them (2 x 2 assemblies of 17 x 17 for the
+    defaults) fuel up to fuel_height, the rest moderator; reflective on x-, y-, z- and
+    vacuum on x+, y+, z+. Every node carries its own homogenised-like cross sections: the
+    base set of its material scaled by 1 + U[-perturb, perturb] (one factor for Sigma_t and
+    Sigma_s, one for nuSigma_f), so no two nodes share response matrices.
+    Draw order: draw_xs(3 fuel types, moderator, guide tube), fuel type per 17 x 17
+    assembly U{0..2}, then the per-node factors; guide tubes sit at the 25 usual
+    guide/instrument positions of a 17 x 17 assembly (fixed, not drawn)."""
+    rng = np.random.default_rng(seed)
+    st0, ss0, nsf0, chi0 = draw_xs(rng, 3, 2, G)
+    moderator, guide = 3, 4
+    n_asm = max(1, n_fuel_pins // 17)
+    asm_type = rng.integers(0, 3, (n_asm, n_asm))
+    gt = {(2, 5), (2, 8), (2, 11), (5, 2), (5, 14), (8, 2), (8, 8), (8, 14), (11, 2), (11, 14), (14, 5), (14, 8),
+          (14, 11), (3, 3), (3, 13), (13, 3), (13, 13), (5, 5), (5, 11), (11, 5), (11, 11), (5, 8), (8, 5),
+          (8, 11), (11, 8)}
+    ez = np.linspace(0.0, height, n_planes + 1)
+    zc = 0.5 * (ez[:-1] + ez[1:])
+    base = np.full((n_planes, n_pins, n_pins), moderator, np.int64)
+    for j in range(min(n_fuel_pins, n_pins)):
+        for i in range(min(n_fuel_pins, n_pins)):
+            m = guide if (i % 17, j % 17) in gt else int(asm_type[min(j // 17, n_asm - 1), min(i // 17, n_asm - 1)])
+            base[zc < fuel_height, j, i] = m
+    base = base.ravel()
+    N = base.size
+    f_t = 1.0 + rng.uniform(-perturb, perturb, N)
+    f_f = 1.0 + rng.uniform(-perturb, perturb, N)
+    st = st0[base] * f_t[:, None]
+    ss = ss0[base] * f_t[:, None, None]
+    nsf = nsf0[base] * f_f[:, None]
+    chi = chi0[base].copy()
+    edges = (np.arange(n_pins + 1) * pitch, np.arange(n_pins + 1) * pitch, ez)
+    return BrickGrid(f"core{n_pins}x{n_pins}x{n_planes}_g{G}", edges, np.arange(N, dtype=np.int32), st, ss, nsf, chi,
+                     (BC_REFLECTIVE, BC_VACUUM, BC_REFLECTIVE, BC_VACUUM, BC_REFLECTIVE, BC_VACUUM))

@@ -1,0 +1,173 @@
+"""Diffusion HFEM on the GPU against the FP64 HFEM oracle, through the C ABI.
+
+* Four consecutive sweeps (red-black iterations + reconstruction) for random source
+  moments, the currents carried from one sweep to the next: flux moments and outgoing
+  partial currents element by element, on grids with vacuum, reflective and mixed sides,
+  volume orders 0..4, face orders 0..2, 1 to 7 groups, a single node (no black nodes) and
+  a one-node-wide column.
+* Exactly n power iterations (eigenvalue and flux after each full outer loop), a
+  converged eigenvalue solve and a fixed-source solve against the oracle's.
+* The 51 x 51 x 32 pin-cell core (7 groups, per-node cross sections) in the timed
+  configuration: after two sweeps, sampled nodes satisfy the response relation of
+  Eq. HFEM_flux_response (black nodes, whose last update saw the final red currents) and
+  the reconstruction, with the node matrices built by the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import hfem_oracle as H
+from paper_2607_01591_amd import hfem
+from paper_2607_01591_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a, cuda):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=cuda)
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _oracle(g, nv, nf, n_inner):
+    return H.HFEMOracle(*g.edges, g.node_material, g.sigma_t, g.sigma_s, g.nu_sigma_f, g.chi, bc=g.bc, nv=nv, nf=nf,
+                        n_inner=n_inner)
+
+
+CASES = [
+    ("box_g2_v2f1_mixed", lambda: P.brick_box(3, 4, 5, G=2, n_fuel=1, n_other=1, seed=1, bc=(1, 0, 0, 1, 1, 0)), 2, 1, 2),
+    ("box_g1_v1f0_vacuum", lambda: P.brick_box(4, 3, 3, G=1, n_fuel=1, n_other=1, seed=2, bc=(0,) * 6), 1, 0, 3),
+    ("box_g3_v3f2_reflective", lambda: P.brick_box(3, 3, 3, G=3, n_fuel=1, n_other=2, seed=3), 3, 2, 2),
+    ("box_g2_v4f2_mixed", lambda: P.brick_box(2, 3, 2, G=2, n_fuel=1, n_other=1, seed=4, bc=(0, 1, 1, 0, 0, 1)), 4, 2, 1),
+    ("box_g7_v0f0_mixed", lambda: P.brick_box(5, 4, 3, G=7, n_fuel=2, n_other=1, seed=5, bc=(1, 0, 1, 0, 1, 0)), 0, 0, 2),
+    ("single_node_g2", lambda: P.brick_box(1, 1, 1, G=2, n_fuel=1, n_other=0, seed=6, bc=(0, 1, 1, 0, 0, 1)), 2, 1, 2),
+    ("column_g2_v2f1", lambda: P.brick_box(1, 1, 9, G=2, n_fuel=1, n_other=1, seed=7, bc=(1, 1, 1, 1, 0, 1)), 2, 1, 3),
+]
+
+
+@pytest.mark.parametrize("name,make,nv,nf,n_inner", CASES, ids=[c[0] for c in CASES])
+def test_sweeps_match_oracle(name, make, nv, nf, n_inner, cuda):
+    log(f"[hfem sweeps] {name}")
+    g = make()
+    o = _oracle(g, nv, nf, n_inner)
+    s = hfem.HFEMSolver(g, volume_order=nv, face_order=nf, inner_iterations=n_inner)
+    rng = np.random.default_rng(9)
+    for k in range(4):
+        q = rng.uniform(0.1, 2.0, o.shape())
+        q[..., 1:] = rng.uniform(-0.3, 0.3, q[..., 1:].shape)
+        ref = o.sweep(q)
+        got = _host(s.sweep(_dev(q, cuda)))
+        err = float(np.abs(got - ref).max() / np.abs(ref[..., 0]).max())
+        jerr = float(np.abs(_host(s.currents()) - o.jp).max() / max(np.abs(o.jp).max(), 1e-300))
+        log(f"  sweep {k + 1}: flux error {err:.2e}, current error {jerr:.2e} ({s.info['n_red']} red, "
+            f"{s.info['n_black']} black nodes)")
+        assert err < 1e-11 and jerr < 1e-11
+
+
+def test_power_iterations_match_oracle(cuda):
+    log("[hfem power iterations]")
+    g = P.brick_box(4, 3, 4, G=7, n_fuel=2, n_other=1, seed=11, bc=(1, 0, 1, 0, 1, 0))
+    o = _oracle(g, 2, 1, 2)
+    s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2)
+    for n in (1, 3, 10):
+        k_ref, phi_ref = o.run_iterations(n)
+        r = s.run_iterations(n)
+        phi = _host(s.flux())
+        err = float(np.abs(phi - phi_ref).max() / np.abs(phi_ref[..., 0]).max())
+        log(f"  {n} iterations: k {r['k']:.15f} vs {k_ref:.15f}, flux error {err:.2e}")
+        assert abs(r["k"] - k_ref) < 1e-12 and err < 1e-11
+
+
+def test_eigen_solve_matches_oracle(cuda):
+    log("[hfem eigen solve]")
+    g = P.brick_box(4, 4, 4, G=7, n_fuel=2, n_other=1, seed=12, bc=(1, 0, 1, 0, 1, 0))
+    ref = _oracle(g, 2, 1, 2).solve(tol=1e-10, max_iter=20000)
+    s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2, max_iter=20000)
+    r = s.solve(1e-10)
+    phi = _host(s.flux())
+    dx, dy, dz = (np.diff(e) for e in g.edges)
+    vol = (dz[:, None, None] * dy[None, :, None] * dx[None, None, :]).ravel()
+    fr = lambda ph: np.sum(vol * np.einsum("ng,ng->n", g.nu_sigma_f[g.node_material], ph[..., 0]))  # noqa: E731
+    err = float(np.abs(phi / fr(phi) - ref["phi"] / fr(ref["phi"])).max() / np.abs(ref["phi"][..., 0] / fr(ref["phi"])).max())
+    log(f"  k {r['k']:.12f} vs {ref['k']:.12f}; {r['iterations']} vs {ref['iterations']} iterations; flux error {err:.2e}")
+    assert r["converged"] and ref["converged"]
+    assert abs(r["iterations"] - ref["iterations"]) <= 1
+    assert abs(r["k"] - ref["k"]) < 1e-10 and err < 1e-8
+
+
+def test_fixed_source_solve_matches_oracle(cuda):
+    log("[hfem fixed source]")
+    g = P.brick_box(4, 3, 5, G=2, n_fuel=0, n_other=2, seed=13, bc=(0, 1, 0, 1, 0, 0))
+    o = _oracle(g, 3, 1, 2)
+    rng = np.random.default_rng(4)
+    q = np.zeros(o.shape())
+    q[..., 0] = rng.uniform(0.0, 1.0, q[..., 0].shape)
+    q[..., 1:] = rng.uniform(-0.2, 0.2, q[..., 1:].shape)
+    o.set_external_source(q)
+    ref = o.solve(tol=1e-12, max_iter=20000)
+    s = hfem.HFEMSolver(g, volume_order=3, face_order=1, inner_iterations=2, max_iter=20000)
+    s.set_external_source(_dev(q, cuda))
+    r = s.solve(1e-12)
+    err = float(np.abs(_host(s.flux()) - ref["phi"]).max() / np.abs(ref["phi"][..., 0]).max())
+    log(f"  {r['iterations']} vs {ref['iterations']} iterations, flux error {err:.2e}")
+    assert r["converged"] and ref["converged"] and err < 1e-10
+
+
+def test_full_size_core_sampled_nodes(cuda):
+    """51 x 51 x 32 pin-cell nodes, 7 groups, volume order 2, face order 1."""
+    g = P.brick_core()
+    s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2)
+    log(f"[hfem full-size core] {s.info}")
+    nx, ny, nz = (len(e) - 1 for e in g.edges)
+    rng = np.random.default_rng(21)
+    q = rng.uniform(0.1, 1.0, s.shape())
+    q[..., 1:] = rng.uniform(-0.1, 0.1, q[..., 1:].shape)
+    qd = _dev(q, cuda)
+    s.sweep(qd)
+    phi = _host(s.sweep(qd))
+    jp = _host(s.currents())
+    Nfb, nft = len(H.face_modes(1)), s.Nft
+    stride = (1, nx, nx * ny)
+    dims = (nx, ny, nz)
+    checked = 0
+    worst_r, worst_phi = 0.0, 0.0
+    for e in rng.choice(g.n_nodes, 160, replace=False):
+        ijk = (e % nx, (e // nx) % ny, e // (nx * ny))
+        h = [g.edges[d][ijk[d] + 1] - g.edges[d][ijk[d]] for d in range(3)]
+        V = float(np.prod(h))
+        jm = np.zeros((s.G, nft))
+        own_reflective = False
+        for f in range(6):
+            d, side = f // 2, f % 2
+            inside = ijk[d] > 0 if side == 0 else ijk[d] < dims[d] - 1
+            sl = slice(f * Nfb, (f + 1) * Nfb)
+            if inside:
+                nb = e + (-stride[d] if side == 0 else stride[d])
+                jm[:, sl] = jp[nb, :, (f ^ 1) * Nfb:((f ^ 1) + 1) * Nfb]
+            elif g.bc[f] == H.BC_REFLECTIVE:
+                jm[:, sl] = jp[e, :, sl]
+                own_reflective = True
+        m = g.node_material[e]
+        for gg in range(s.G):
+            A, M, Lam = H.node_matrices(h, 1.0 / (3.0 * g.sigma_t[m, gg]), g.sigma_t[m, gg] - g.sigma_s[m, gg, gg], 2, 1)
+            R, B, Ainv, Pm = H.response(A, M, Lam)
+            sv = V * q[e, gg]
+            if sum(ijk) % 2 == 1 and not own_reflective:
+                want = R @ jm[gg] + B @ sv
+                worst_r = max(worst_r, float(np.abs(jp[e, gg] - want).max() / max(np.abs(want).max(), 1e-300)))
+            want_phi = Ainv @ sv - Pm @ (jp[e, gg] - jm[gg])
+            worst_phi = max(worst_phi, float(np.abs(phi[e, gg] - want_phi).max() / abs(want_phi[0])))
+            checked += 1
+    log(f"  {checked} node-groups: response relation {worst_r:.2e}, reconstruction {worst_phi:.2e}")
+    assert worst_r < 1e-11 and worst_phi < 1e-11

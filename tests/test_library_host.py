@@ -95,6 +95,47 @@ def test_dfem_host_schedule(case):
     assert dfem.lib().moc_sn_solve(s._h, 1e-6, ctypes.byref(r)) == moc.MOC_ESTATE
 
 
+def test_library_exports_every_hfem_symbol():
+    from paper_2607_01591_amd import hfem
+    hdr = open(os.path.join(ROOT, "include", "hfem.h")).read()
+    declared = set(re.findall(r"\b(moc_hfem_[a-z_]+)\s*\(", hdr))
+    assert {"moc_hfem_create", "moc_hfem_sweep", "moc_hfem_solve"} <= declared
+    L = hfem.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(hfem.SIGNATURES), declared ^ set(hfem.SIGNATURES)
+
+
+def test_hfem_host_context_and_validation():
+    """Host-only HFEM contexts: sizes and colour counts of a valid grid, MOC_ESTATE on device
+    calls, and MOC_EINVAL for each kind of bad input (no HIP call is made before it fails)."""
+    import ctypes
+    import dataclasses
+    from paper_2607_01591_amd import hfem
+    g = P.brick_box(3, 4, 5, G=3, n_fuel=1, n_other=2, seed=2, bc=(0, 1, 1, 0, 1, 0))
+    s = hfem.HFEMSolver(g, volume_order=3, face_order=2, device=-1)
+    red = sum((i + j + k) % 2 == 0 for k in range(5) for j in range(4) for i in range(3))
+    assert (s.info["n_nodes"], s.info["n_groups"], s.info["n_moments"], s.info["n_face_dofs"]) == (60, 3, 20, 36)
+    assert (s.info["n_red"], s.info["n_black"]) == (red, 60 - red)
+    r = moc.MocResult()
+    assert hfem.lib().moc_hfem_solve(s._h, 1e-6, ctypes.byref(r)) == moc.MOC_ESTATE
+    ss_bad = g.sigma_s.copy()
+    ss_bad[0, 0, 0] = g.sigma_t[0, 0]
+    bad = [dict(edges=(g.edges[0][::-1], g.edges[1], g.edges[2])),
+           dict(node_material=np.full_like(g.node_material, 7)),
+           dict(bc=(0, 1, 3, 0, 1, 0)),
+           dict(sigma_s=ss_bad),
+           dict(sigma_t=-g.sigma_t)]
+    for b in bad:
+        with pytest.raises(moc.MocError) as ei:
+            hfem.HFEMSolver(dataclasses.replace(g, **b), device=-1)
+        assert ei.value.code == moc.MOC_EINVAL, b
+    for nv, nf in [(5, 1), (1, 2), (2, 3), (-1, 0)]:
+        with pytest.raises(moc.MocError) as ei:
+            hfem.HFEMSolver(g, volume_order=nv, face_order=nf, device=-1)
+        assert ei.value.code == moc.MOC_EINVAL
+
+
 def _compare_tracking(prob):
     s = moc.Solver(prob, device=-1)
     o = Oracle.from_problem(prob)
