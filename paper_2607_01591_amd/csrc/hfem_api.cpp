@@ -255,11 +255,57 @@ static void hf_create_impl(const moc_hfem_grid *grid, const moc_xs *xs, const mo
     d.nsf = c->upload(std::vector<double>(xs->nu_sigma_f, xs->nu_sigma_f + (size_t)M * G));
     d.chi = c->upload(std::vector<double>(xs->chi, xs->chi + (size_t)M * G));
     d.vmode = c->upload(vm);
-    d.fmode = c->upload(fm);
-    d.R = c->dalloc<double>(npg * Nft * Nft);
-    d.B = c->dalloc<double>(npg * Np * Nft);
-    d.Ainv = c->dalloc<double>(npg * Np * Np);
-    d.P = c->dalloc<double>(npg * Nft * Np);
+    d.npg_blk = 256 / Nft;
+    d.nblk[0] = ((int64_t)n_red * G + d.npg_blk - 1) / d.npg_blk;
+    d.nblk[1] = ((int64_t)(N - n_red) * G + d.npg_blk - 1) / d.npg_blk;
+    const size_t slots = (size_t)(d.nblk[0] + d.nblk[1]) * d.npg_blk;   // node-groups incl. block padding
+    d.R = c->dalloc<double>(slots * Nft * Nft);
+    d.Ainv = c->dalloc<double>(slots * Np * Np);
+    // face factor t of face DoF r and volume mode k: sqrt(2a+1) (+-1)^a for the degree a
+    // normal to the face when the transverse degrees match the face mode, else 0
+    std::vector<double> tface((size_t)Nft * Np, 0.0);
+    for (int r = 0; r < Nft; ++r) {
+        const int f = r / d.Nfb, mm = r % d.Nfb, ax = f / 2;
+        const int t0 = ax == 0 ? 1 : 0, t1 = ax == 2 ? 1 : 2;
+        for (int k = 0; k < Np; ++k) {
+            const int *vk = &vm[3 * (size_t)k];
+            if (vk[t0] != fm[2 * (size_t)mm] || vk[t1] != fm[2 * (size_t)mm + 1]) continue;
+            const double v = std::sqrt(2.0 * vk[ax] + 1.0);
+            tface[(size_t)r * Np + k] = (f % 2 == 1 || vk[ax] % 2 == 0) ? v : -v;
+        }
+    }
+    d.tface = c->upload(tface);
+    // per moment, the face DoFs it couples to (at most one mode on each of the 6 faces)
+    std::vector<int> flist((size_t)Np * 6, -1);
+    std::vector<double> fval((size_t)Np * 6, 0.0);
+    for (int k = 0; k < Np; ++k) {
+        int q = 0;
+        for (int r = 0; r < Nft; ++r)
+            if (tface[(size_t)r * Np + k] != 0.0) {
+                if (q == 6) throw Error(MOC_EINVAL, "internal: a moment couples to more than 6 face DoFs");
+                flist[(size_t)k * 6 + q] = r;
+                fval[(size_t)k * 6 + q] = tface[(size_t)r * Np + k];
+                ++q;
+            }
+    }
+    d.flist = c->upload(flist);
+    d.fval = c->upload(fval);
+    // per face DoF, the moments it couples to
+    d.nr = c->nv + 1;
+    std::vector<int> rlist((size_t)Nft * d.nr, -1);
+    std::vector<double> rval((size_t)Nft * d.nr, 0.0);
+    for (int r = 0; r < Nft; ++r) {
+        int q = 0;
+        for (int k = 0; k < Np; ++k)
+            if (tface[(size_t)r * Np + k] != 0.0) {
+                if (q == d.nr) throw Error(MOC_EINVAL, "internal: a face DoF couples to too many moments");
+                rlist[(size_t)r * d.nr + q] = k;
+                rval[(size_t)r * d.nr + q] = tface[(size_t)r * Np + k];
+                ++q;
+            }
+    }
+    d.rlist = c->upload(rlist);
+    d.rval = c->upload(rval);
     d.jp = c->dalloc<double>(npg * Nft);
     d.s = c->dalloc<double>(npg * Np);
     d.bq = c->dalloc<double>(npg * Nft);
@@ -324,11 +370,10 @@ static void hf_drain_profile(moc_hfem_ctx *c) {
     c->prof_pending.clear();
 }
 
-// One HFEM solve for the source moments in d.s: B s, then the red-black iterations (each
-// timed when profiling), then the reconstruction into phi_out.
+// One HFEM solve after launch_hf_prepare has formed s and h: the red-black iterations
+// (each timed when profiling), then the reconstruction into phi_out.
 static void hf_sweep_impl(moc_hfem_ctx *c, double *phi_out, hipStream_t s) {
     DevHF &d = c->d;
-    launch_hf_bq(d, s);
     for (int it = 0; it < c->n_inner; ++it) {
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
         if (c->profiling) {
@@ -367,7 +412,7 @@ static int hf_solve_impl(moc_hfem_ctx *c, double tol, int max_iter, int check_ev
     double res = 1.0, dk = 1.0, k = 1.0;
     for (it = 1; it <= max_iter; ++it) {
         double *phi_old = d.phi[c->cur_phi], *phi_new = d.phi[1 - c->cur_phi];
-        launch_hf_source(d, phi_old, s);
+        launch_hf_prepare(d, phi_old, nullptr, s);
         hf_sweep_impl(c, phi_new, s);
         ++sweeps;
         launch_hf_fission(d, phi_new, phi_old, s);
@@ -430,7 +475,7 @@ int moc_hfem_sweep(moc_hfem_ctx *c, const double *source_dev, double *phi_out_de
         hf_need_device(c);
         HF_HIP(hipSetDevice(c->device));
         hipStream_t s = stream ? (hipStream_t)stream : c->stream;
-        launch_hf_user_source(c->d, source_dev, s);
+        launch_hf_prepare(c->d, nullptr, source_dev, s);
         hf_sweep_impl(c, phi_out_dev, s);
     });
 }

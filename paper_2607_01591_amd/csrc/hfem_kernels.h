@@ -27,15 +27,25 @@ struct DevHF {
     double *sigs = nullptr;  // [M][G][G] from -> to
     double *nsf = nullptr, *chi = nullptr;     // [M][G]
     int *vmode = nullptr;    // [Np][3] Legendre degrees of the volume modes
-    int *fmode = nullptr;    // [Nfb][2] degrees of the face modes
-    // per (colour-sorted node, group), each column-major: column index outer, row inner
-    double *R = nullptr;     // [N][G][Nft cols][Nft rows]
-    double *B = nullptr;     // [N][G][Np cols][Nft rows]
-    double *Ainv = nullptr;  // [N][G][Np cols][Np rows]
-    double *P = nullptr;     // [N][G][Nft cols][Np rows]  (A^-1 M^T)
+    // Node-groups (colour-sorted node, group) are dealt to blocks of npg_blk, colour by
+    // colour (the red blocks first; the last block of a colour may be partial). Within a
+    // block each matrix is stored column by column with the block's node-groups
+    // interleaved: entry (row i, column j) of slot pl sits at
+    //   [block][j][pl][i]
+    // so that one column of every node-group of a block is one contiguous run.
+    int npg_blk = 0;         // node-groups per block (256 / Nft)
+    int64_t nblk[2] = {0, 0};
+    double *R = nullptr;     // [blocks][Nft][npg_blk][Nft]
+    double *Ainv = nullptr;  // [blocks][Np][npg_blk][Np]
+    double *tface = nullptr; // [Nft][Np] face factors t (M = face area x t)
+    int *flist = nullptr;    // [Np][6] face DoFs with t != 0 for each moment (-1 ends the list)
+    double *fval = nullptr;  // [Np][6] their face factors
+    int nr = 0;              // length of the per-face-DoF lists
+    int *rlist = nullptr;    // [Nft][nr] moments with t != 0 for each face DoF (-1 ends the list)
+    double *rval = nullptr;  // [Nft][nr] their face factors
     double *jp = nullptr;    // [N][G][Nft] outgoing partial currents, colour-sorted
     double *s = nullptr;     // [N][G][Np] source moments (u_i, Q), colour-sorted
-    double *bq = nullptr;    // [N][G][Nft] B s
+    double *bq = nullptr;    // [N][G][Nft] h = C s / 4 (B s = h - R h)
     double *phi[2] = {nullptr, nullptr};   // [N][G][Np] by node
     double *qext = nullptr;  // [N][G][Np] by node
     double *partials = nullptr, *scal = nullptr;
@@ -47,9 +57,8 @@ enum { kHfK = 0, kHfKPrev = 1, kHfFnew = 2, kHfFold = 3, kHfRes = 4, kHfDk = 5, 
 constexpr int kHfReduceBlocks = 256;
 
 void launch_hf_assemble(const DevHF &d, hipStream_t s);
-void launch_hf_source(const DevHF &d, const double *phi, hipStream_t s);
-void launch_hf_user_source(const DevHF &d, const double *src, hipStream_t s);
-void launch_hf_bq(const DevHF &d, hipStream_t s);
+// s, A^-1 s and h from the previous flux phi (user == nullptr) or a caller's emission moments
+void launch_hf_prepare(const DevHF &d, const double *phi, const double *user, hipStream_t s);
 void launch_hf_rb(const DevHF &d, int colour, hipStream_t s);
 void launch_hf_reconstruct(const DevHF &d, double *phi_out, hipStream_t s);
 void launch_hf_fission(const DevHF &d, const double *phi_new, const double *phi_old, hipStream_t s);

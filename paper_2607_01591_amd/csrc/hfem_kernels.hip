@@ -9,12 +9,17 @@
 //   M_ri  = <v_m, u_i>_f = A_f t_ri,  r = (f, m)                    (face coupling)
 //   C     = Lambda^-1 M A^-1,  Y = C M^T
 //   J+    = R J- + B s,  R = (2I + Y)^-1 (Y - 2I) = I - 4 (2I + Y)^-1,  B = (2I + Y)^-1 C
-//   phi   = A^-1 s - P (J+ - J-),  P = A^-1 M^T
+//   phi   = A^-1 (s - M^T (J+ - J-))
+// Since (2I + Y)^-1 = (I - R) / 4, the source term is B s = h - R h with h = C s / 4, the
+// quarter of the face flux moments of A^-1 s; so each red-black update is the single
+// product J+ = R (J- - h) + h and B is never formed. h costs one pass over A^-1 per
+// outer iteration instead of one over B.
 // The Legendre integrals are closed forms: on [-1, 1] with p_a = sqrt(2a+1) P_a,
 // int p_a p_b = 2 delta_ab, int p_a' p_b' = sqrt((2a+1)(2b+1)) min(a,b) (min(a,b)+1) when
 // a + b is even (else 0), and p_a(+-1) = sqrt(2a+1) (+-1)^a; so
 // (d_x u_i, d_x u_j) = (2 V / hx^2) k(a_i, a_j) delta(b) delta(c), and the face factor
-// t_ri = p_(a_d)(+-1) when the transverse degrees of u_i equal those of v_m, else 0.
+// t_ri = p_(a_d)(+-1) when the transverse degrees of u_i equal those of v_m, else 0
+// (tabulated on the host).
 #include <cmath>
 
 #include "hfem_kernels.h"
@@ -27,19 +32,6 @@ __device__ __forceinline__ double hf_stiff1d(int a, int b) {
     if ((a + b) & 1) return 0.0;
     const int m = a < b ? a : b;
     return sqrt((double)((2 * a + 1) * (2 * b + 1))) * (double)(m * (m + 1));
-}
-
-// face factor t of face DoF r and volume mode i (0 when the transverse degrees differ)
-__device__ __forceinline__ double hf_face_factor(const int *__restrict__ vmode, const int *__restrict__ fmode, int Nfb,
-                                                 int r, int i) {
-    const int f = r / Nfb, mm = r - f * Nfb;
-    const int d = f >> 1;
-    const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-    const int *vi = vmode + 3 * i;
-    if (vi[t0] != fmode[2 * mm] || vi[t1] != fmode[2 * mm + 1]) return 0.0;
-    const int a = vi[d];
-    const double v = sqrt((double)(2 * a + 1));
-    return (f & 1) ? v : ((a & 1) ? -v : v);
 }
 
 __device__ __forceinline__ double hf_face_area(const double *h, int r, int Nfb) {
@@ -88,16 +80,38 @@ __device__ void hf_gauss_jordan(double *W, int n, int *piv_sh, int *status) {
     }
 }
 
+// global block index and slot of a colour-sorted node-group (red blocks first)
+__device__ __forceinline__ void hf_block_of(int64_t pg, int64_t red_pg, int npg_blk, int64_t nblk0, int64_t &blk,
+                                           int &pl) {
+    const int64_t lp = pg < red_pg ? pg : pg - red_pg;
+    blk = lp / npg_blk + (pg < red_pg ? 0 : nblk0);
+    pl = int(lp - (lp / npg_blk) * npg_blk);
+}
+
+// first node-group of a global block, and the end of its colour's range
+__device__ __forceinline__ void hf_block_range(int64_t blk, int64_t red_pg, int64_t all_pg, int npg_blk, int64_t nblk0,
+                                               int64_t &pg0, int64_t &pg_end) {
+    if (blk < nblk0) {
+        pg0 = blk * npg_blk;
+        pg_end = red_pg;
+    } else {
+        pg0 = red_pg + (blk - nblk0) * npg_blk;
+        pg_end = all_pg;
+    }
+}
+
 struct HfAsmArgs {
-    const int *perm, *mat, *vmode, *fmode;
-    const double *hdim, *diff, *sigr;
-    double *R, *B, *Ainv, *P;
+    const int *perm, *mat, *vmode;
+    const double *hdim, *diff, *sigr, *tface;
+    double *R, *Ainv;
     int *status;
-    int G, Np, Nfb, Nft, wsize;
+    int64_t red_pg, nblk0;
+    int G, Np, Nfb, Nft, wsize, npg_blk;
 };
 
 // Preassembly: one wavefront per (colour-sorted node, group). Builds A and inverts it,
-// forms C and 2I + Y and inverts that, and writes R, B, A^-1 and P column-major.
+// forms C and 2I + Y and inverts that, and writes R and A^-1 in the blocked column layout
+// of DevHF.
 __global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
     extern __shared__ double lds[];
     __shared__ int piv_sh;
@@ -135,7 +149,7 @@ __global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
         const int r = idx / Np, j = idx - r * Np;
         double acc = 0.0;
         for (int i = 0; i < Np; ++i) {
-            const double t = hf_face_factor(a.vmode, a.fmode, Nfb, r, i);
+            const double t = a.tface[r * Np + i];
             if (t != 0.0) acc += t * Ai[i * Np + j];
         }
         Cm[idx] = acc;
@@ -146,7 +160,7 @@ __global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
         const int r = idx / Nft, c = idx - r * Nft;
         double acc = 0.0;
         for (int i = 0; i < Np; ++i) {
-            const double t = hf_face_factor(a.vmode, a.fmode, Nfb, c, i);
+            const double t = a.tface[c * Np + i];
             if (t != 0.0) acc += Cm[r * Np + i] * t;
         }
         W[r * 2 * Nft + c] = hf_face_area(h, c, Nfb) * acc + (r == c ? 2.0 : 0.0);
@@ -154,86 +168,87 @@ __global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
     }
     __syncthreads();
     hf_gauss_jordan(W, Nft, &piv_sh, a.status);
-    const int64_t base = (int64_t)pg;
-    // R = I - 4 K^-1 (K = 2I + Y), column-major
+    int64_t blk;
+    int pl;
+    hf_block_of(pg, a.red_pg, a.npg_blk, a.nblk0, blk, pl);
+    const int nb = a.npg_blk;
+    // R = I - 4 K^-1 (K = 2I + Y)
     for (int idx = lane; idx < Nft * Nft; idx += 64) {
         const int j = idx / Nft, i = idx - j * Nft;
-        a.R[base * Nft * Nft + idx] = (i == j ? 1.0 : 0.0) - 4.0 * W[i * 2 * Nft + Nft + j];
+        a.R[((blk * Nft + j) * nb + pl) * Nft + i] = (i == j ? 1.0 : 0.0) - 4.0 * W[i * 2 * Nft + Nft + j];
     }
-    // B = K^-1 C, column-major
-    for (int idx = lane; idx < Np * Nft; idx += 64) {
-        const int k = idx / Nft, i = idx - k * Nft;
-        double acc = 0.0;
-        for (int r = 0; r < Nft; ++r) acc += W[i * 2 * Nft + Nft + r] * Cm[r * Np + k];
-        a.B[base * Np * Nft + idx] = acc;
-    }
-    // A^-1, column-major (symmetric up to rounding; stored as computed)
+    // A^-1 (symmetric up to rounding; stored as computed)
     for (int idx = lane; idx < Np * Np; idx += 64) {
         const int k = idx / Np, i = idx - k * Np;
-        a.Ainv[base * Np * Np + idx] = Ai[i * Np + k];
-    }
-    // P = A^-1 M^T: P_ic = A_c sum_k Ainv_ik t_ck, column-major
-    for (int idx = lane; idx < Nft * Np; idx += 64) {
-        const int c = idx / Np, i = idx - c * Np;
-        double acc = 0.0;
-        for (int k = 0; k < Np; ++k) {
-            const double t = hf_face_factor(a.vmode, a.fmode, Nfb, c, k);
-            if (t != 0.0) acc += Ai[i * Np + k] * t;
-        }
-        a.P[base * Nft * Np + idx] = hf_face_area(h, c, Nfb) * acc;
+        a.Ainv[((blk * Np + k) * nb + pl) * Np + i] = Ai[i * Np + k];
     }
 }
 
-// Source moments s = V Q in colour-sorted order, Q_g,i = chi_g F_i / k
-// + sum_{g' != g} Sigma_s,g'->g phi_g',i (+ external); one thread per (node, group).
-__global__ void k_hf_source(const double *__restrict__ phi, const double *__restrict__ scal, const int *__restrict__ mat,
-                            const int *__restrict__ pos, const double *__restrict__ vol, const double *__restrict__ sigs,
-                            const double *__restrict__ nsf, const double *__restrict__ chi,
-                            const double *__restrict__ qext, double *__restrict__ s, int N, int G, int Np) {
+// Per outer iteration, one block per global block of node-groups: the source moments
+// s = V Q (from the previous flux, or V times a caller's emission moments), then
+// a = A^-1 s, then h = C s / 4 = Lambda^-1 M a / 4 (face factor lists per face DoF).
+// Emission: Q_g,i = chi_g F_i / k + sum_{g' != g} Sigma_s,g'->g phi_g',i (+ external).
+__global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ phi, const double *__restrict__ user,
+                                                    const double *__restrict__ scal, const int *__restrict__ mat,
+                                                    const int *__restrict__ perm, const double *__restrict__ vol,
+                                                    const double *__restrict__ sigs, const double *__restrict__ nsf,
+                                                    const double *__restrict__ chi, const double *__restrict__ qext,
+                                                    const double *__restrict__ Ainv, const int *__restrict__ rlist,
+                                                    const double *__restrict__ rval, double *__restrict__ s,
+                                                    double *__restrict__ h, int64_t red_pg, int64_t all_pg,
+                                                    int64_t nblk0, int G, int Np, int Nft, int nr) {
+    extern __shared__ double sh[];
+    const int npg_blk = 256 / Nft;
+    double *sv = sh;                    // [npg_blk][Np]
+    double *av = sh + npg_blk * Np;     // [npg_blk][Np]
+    const int64_t blk = blockIdx.x;
+    int64_t pg0, pg_end;
+    hf_block_range(blk, red_pg, all_pg, npg_blk, nblk0, pg0, pg_end);
     const double inv_k = 1.0 / scal[kHfK];
-    const int64_t n = (int64_t)N * G;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int e = int(t / G), g = int(t - (int64_t)e * G);
-        const int m = mat[e];
-        const double *ph = phi + (int64_t)e * G * Np;
-        const double cg = chi[m * G + g] * inv_k;
-        double *out = s + ((int64_t)pos[e] * G + g) * Np;
-        for (int i = 0; i < Np; ++i) {
-            double q = 0.0;
-            for (int gp = 0; gp < G; ++gp) {
-                const double x = ph[gp * Np + i];
-                q += cg * nsf[m * G + gp] * x;
-                if (gp != g) q += sigs[((int64_t)m * G + gp) * G + g] * x;
-            }
-            if (qext) q += qext[t * Np + i];
-            out[i] = vol[e] * q;
+    for (int t = threadIdx.x; t < npg_blk * Np; t += blockDim.x) {
+        const int pl = t / Np, k = t - pl * Np;
+        const int64_t pg = pg0 + pl;
+        if (pg >= pg_end) continue;
+        const int p = int(pg / G), g = int(pg - (int64_t)p * G);
+        const int e = perm[p];
+        const int64_t src = ((int64_t)e * G + g) * Np + k;
+        double q;
+        if (user) {
+            q = user[src];
+        } else {
+            const int m = mat[e];
+            const double *ph = phi + (int64_t)e * G * Np + k;
+            const double cg = chi[m * G + g] * inv_k;
+            const double *sg = sigs + (int64_t)m * G * G + g;
+            q = qext ? qext[src] : 0.0;
+            for (int gp = 0; gp < G; ++gp) q += (cg * nsf[m * G + gp] + (gp != g ? sg[gp * G] : 0.0)) * ph[gp * Np];
         }
+        const double v = vol[e] * q;
+        sv[t] = v;
+        s[pg * Np + k] = v;
     }
-}
-
-// s = V src (caller's emission moments), colour-sorted
-__global__ void k_hf_user_source(const double *__restrict__ src, const int *__restrict__ pos,
-                                 const double *__restrict__ vol, double *__restrict__ s, int N, int G, int Np) {
-    const int64_t n = (int64_t)N * G * Np;
-    const int64_t per_node = (int64_t)G * Np;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int e = int(t / per_node);
-        s[(int64_t)pos[e] * per_node + (t - e * per_node)] = vol[e] * src[t];
-    }
-}
-
-// bq = B s; one thread per (node-group, face DoF); columns of B are contiguous.
-__global__ void k_hf_bq(const double *__restrict__ B, const double *__restrict__ s, double *__restrict__ bq, int64_t npg,
-                        int Np, int Nft) {
-    const int64_t n = npg * Nft;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t pg = t / Nft;
-        const int i = int(t - pg * Nft);
-        const double *Bc = B + pg * Np * Nft + i;
-        const double *sv = s + pg * Np;
+    __syncthreads();
+    for (int t = threadIdx.x; t < npg_blk * Np; t += blockDim.x) {
+        const int pl = t / Np, i = t - pl * Np;
+        if (pg0 + pl >= pg_end) continue;
+        const double *Ab = Ainv + blk * Np * npg_blk * Np + t;
+        const double *x = sv + pl * Np;
         double acc = 0.0;
-        for (int k = 0; k < Np; ++k) acc += Bc[(int64_t)k * Nft] * sv[k];
-        bq[t] = acc;
+        for (int k = 0; k < Np; ++k) acc += Ab[(int64_t)k * npg_blk * Np] * x[k];
+        av[t] = acc;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < npg_blk * Nft; t += blockDim.x) {
+        const int pl = t / Nft, r = t - pl * Nft;
+        const int64_t pg = pg0 + pl;
+        if (pg >= pg_end) continue;
+        double acc = 0.0;
+        for (int q = 0; q < nr; ++q) {
+            const int k = rlist[r * nr + q];
+            if (k < 0) break;
+            acc += rval[r * nr + q] * av[pl * Np + k];
+        }
+        h[pg * Nft + r] = 0.25 * acc;
     }
 }
 
@@ -247,66 +262,98 @@ __device__ __forceinline__ double hf_incoming(const double *__restrict__ jp, con
     return 0.0;
 }
 
-// Red-black half sweep over the nodes [p0, p0 + count) of one colour (Eq. HFEM_flux_response):
-// J+ = R J- + B s. Each block holds whole node-groups: the incoming currents of its
-// node-groups are gathered into LDS first (a node's own outgoing currents feed its
-// reflective faces, so they are read before any is overwritten), then thread (node-group,
-// i) forms row i of R J- from the contiguous columns of R.
-__global__ void __launch_bounds__(256) k_hf_rb(const double *__restrict__ R, const double *__restrict__ bq,
-                                               double *__restrict__ jp, const int *__restrict__ nbr, int p0, int count,
-                                               int G, int Nfb, int Nft, int npg_blk) {
+// Red-black half sweep over the blocks [blk0, blk0 + gridDim.x) of one colour
+// (Eq. HFEM_flux_response): J+ = R J- + B s = R (J- - h) + h. Thread (slot, i) holds
+// row i of its node-group: it loads that row of R (each column of the block is one
+// contiguous run) while J- - h of the block's node-groups is gathered into LDS (a node's
+// own outgoing currents feed its reflective faces, so they are read before any is
+// overwritten), then forms the product.
+template <int NFT>
+__global__ void __launch_bounds__(256) k_hf_rb(const double *__restrict__ R, const double *__restrict__ h,
+                                               double *__restrict__ jp, const int *__restrict__ nbr, int64_t blk0,
+                                               int64_t red_pg, int64_t all_pg, int64_t nblk0, int G, int Nfb) {
+    constexpr int NPG = 256 / NFT;
     __shared__ double jm[256];
-    const int64_t pg0 = (int64_t)p0 * G + (int64_t)blockIdx.x * npg_blk;
-    const int64_t pg_end = (int64_t)(p0 + count) * G;
+    const int64_t blk = blk0 + blockIdx.x;
+    int64_t pg0, pg_end;
+    hf_block_range(blk, red_pg, all_pg, NPG, nblk0, pg0, pg_end);
     const int t = threadIdx.x;
-    const int pl = t / Nft, i = t - pl * Nft;
+    const int pl = t / NFT, i = t - pl * NFT;
     const int64_t pg = pg0 + pl;
-    const bool active = pl < npg_blk && pg < pg_end;
+    const bool active = pl < NPG && pg < pg_end;
+    double row[NFT];
+    double acc = 0.0;
     if (active) {
+        const double *Rb = R + blk * NFT * NPG * NFT + t;
+#pragma unroll
+        for (int j = 0; j < NFT; ++j) row[j] = Rb[j * NPG * NFT];
+        acc = h[pg * NFT + i];
         const int p = int(pg / G), g = int(pg - (int64_t)p * G);
-        jm[t] = hf_incoming(jp, nbr, p, g, i, G, Nfb, Nft);
+        jm[t] = hf_incoming(jp, nbr, p, g, i, G, Nfb, NFT) - acc;
     }
     __syncthreads();
     if (active) {
-        const double *Rc = R + pg * Nft * Nft + i;
-        const double *x = jm + pl * Nft;
-        double acc = bq[pg * Nft + i];
-        for (int j = 0; j < Nft; ++j) acc += Rc[(int64_t)j * Nft] * x[j];
-        jp[pg * Nft + i] = acc;
+        const double *x = jm + pl * NFT;
+#pragma unroll
+        for (int j = 0; j < NFT; ++j) acc += row[j] * x[j];
+        jp[pg * NFT + i] = acc;
     }
 }
 
-// phi = A^-1 s - P (J+ - J-), written in node order; each block holds whole node-groups.
-__global__ void __launch_bounds__(256) k_hf_reconstruct(const double *__restrict__ Ainv, const double *__restrict__ P,
+// phi = A^-1 (s - M^T (J+ - J-)), written in node order, one block per global block of
+// node-groups. Thread (slot, i) loads row i of A^-1 for its node-group while the net
+// currents are gathered into LDS; then u = s - M^T j (M = face area x face factor, from
+// the compact per-moment lists of non-zero face factors), then phi_i = sum_k Ainv_ik u_k.
+template <int NP>
+__global__ void __launch_bounds__(256) k_hf_reconstruct(const double *__restrict__ Ainv, const int *__restrict__ flist,
+                                                        const double *__restrict__ fval, const double *__restrict__ hdim,
                                                         const double *__restrict__ s, const double *__restrict__ jp,
                                                         const int *__restrict__ nbr, const int *__restrict__ perm,
-                                                        double *__restrict__ phi, int N, int G, int Np, int Nfb, int Nft,
-                                                        int npg_blk) {
-    __shared__ double net[256];
-    const int64_t pg0 = (int64_t)blockIdx.x * npg_blk;
-    const int64_t npg = (int64_t)N * G;
+                                                        double *__restrict__ phi, int64_t red_pg, int64_t all_pg,
+                                                        int64_t nblk0, int G, int Nfb, int Nft) {
+    extern __shared__ double sh[];
+    const int npg_blk = 256 / Nft;
+    double *net = sh;                   // [npg_blk][Nft]
+    double *u = sh + npg_blk * Nft;     // [npg_blk][NP]
+    const int64_t blk = blockIdx.x;
+    int64_t pg0, pg_end;
+    hf_block_range(blk, red_pg, all_pg, npg_blk, nblk0, pg0, pg_end);
     for (int t = threadIdx.x; t < npg_blk * Nft; t += blockDim.x) {
         const int pl = t / Nft, i = t - pl * Nft;
         const int64_t pg = pg0 + pl;
-        if (pg < npg) {
+        if (pg < pg_end) {
             const int p = int(pg / G), g = int(pg - (int64_t)p * G);
             net[t] = jp[pg * Nft + i] - hf_incoming(jp, nbr, p, g, i, G, Nfb, Nft);
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < npg_blk * Np; t += blockDim.x) {
-        const int pl = t / Np, i = t - pl * Np;
+    for (int t = threadIdx.x; t < npg_blk * NP; t += blockDim.x) {
+        const int pl = t / NP, k = t - pl * NP;
         const int64_t pg = pg0 + pl;
-        if (pg >= npg) continue;
+        if (pg >= pg_end) continue;
+        const int p = int(pg / G);
+        const double hx = hdim[3 * p], hy = hdim[3 * p + 1], hz = hdim[3 * p + 2];
+        const double area[3] = {hy * hz, hx * hz, hx * hy};
+        double w = 0.0;
+        for (int q = 0; q < 6; ++q) {
+            const int c = flist[k * 6 + q];
+            if (c < 0) break;
+            w += area[(c / Nfb) >> 1] * fval[k * 6 + q] * net[pl * Nft + c];
+        }
+        u[t] = s[pg * NP + k] - w;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < npg_blk * NP; t += blockDim.x) {
+        const int pl = t / NP, i = t - pl * NP;
+        const int64_t pg = pg0 + pl;
+        if (pg >= pg_end) continue;
         const int p = int(pg / G), g = int(pg - (int64_t)p * G);
-        const double *Ac = Ainv + pg * Np * Np + i;
-        const double *Pc = P + pg * Nft * Np + i;
-        const double *sv = s + pg * Np;
-        const double *nv = net + pl * Nft;
+        const double *Ab = Ainv + blk * NP * npg_blk * NP + t;
+        const double *uv = u + pl * NP;
         double acc = 0.0;
-        for (int k = 0; k < Np; ++k) acc += Ac[(int64_t)k * Np] * sv[k];
-        for (int j = 0; j < Nft; ++j) acc -= Pc[(int64_t)j * Np] * nv[j];
-        phi[((int64_t)perm[p] * G + g) * Np + i] = acc;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) acc += Ab[k * npg_blk * NP] * uv[k];
+        phi[((int64_t)perm[p] * G + g) * NP + i] = acc;
     }
 }
 
@@ -460,15 +507,16 @@ void launch_hf_assemble(const DevHF &d, hipStream_t s) {
     a.perm = d.perm;
     a.mat = d.mat;
     a.vmode = d.vmode;
-    a.fmode = d.fmode;
+    a.tface = d.tface;
     a.hdim = d.hdim;
     a.diff = d.diff;
     a.sigr = d.sigr;
     a.R = d.R;
-    a.B = d.B;
     a.Ainv = d.Ainv;
-    a.P = d.P;
     a.status = d.status;
+    a.red_pg = (int64_t)d.n_red * d.G;
+    a.nblk0 = d.nblk[0];
+    a.npg_blk = d.npg_blk;
     a.G = d.G;
     a.Np = d.Np;
     a.Nfb = d.Nfb;
@@ -481,42 +529,55 @@ void launch_hf_assemble(const DevHF &d, hipStream_t s) {
     hf_check_launch();
 }
 
-void launch_hf_source(const DevHF &d, const double *phi, hipStream_t s) {
-    const int64_t n = (int64_t)d.N * d.G;
-    k_hf_source<<<hf_grid(n), 256, 0, s>>>(phi, d.scal, d.mat, d.pos, d.vol, d.sigs, d.nsf, d.chi, d.qext, d.s, d.N,
-                                           d.G, d.Np);
-    hf_check_launch();
-}
-
-void launch_hf_user_source(const DevHF &d, const double *src, hipStream_t s) {
-    const int64_t n = (int64_t)d.N * d.G * d.Np;
-    k_hf_user_source<<<hf_grid(n), 256, 0, s>>>(src, d.pos, d.vol, d.s, d.N, d.G, d.Np);
-    hf_check_launch();
-}
-
-void launch_hf_bq(const DevHF &d, hipStream_t s) {
-    const int64_t npg = (int64_t)d.N * d.G;
-    k_hf_bq<<<hf_grid(npg * d.Nft), 256, 0, s>>>(d.B, d.s, d.bq, npg, d.Np, d.Nft);
+void launch_hf_prepare(const DevHF &d, const double *phi, const double *user, hipStream_t s) {
+    const int64_t nb = d.nblk[0] + d.nblk[1];
+    if (nb <= 0) return;
+    const size_t lds = sizeof(double) * (size_t)d.npg_blk * 2 * d.Np;
+    k_hf_prepare<<<(unsigned)nb, 256, lds, s>>>(phi, user, d.scal, d.mat, d.perm, d.vol, d.sigs, d.nsf, d.chi, d.qext,
+                                                d.Ainv, d.rlist, d.rval, d.s, d.bq, (int64_t)d.n_red * d.G,
+                                                (int64_t)d.N * d.G, d.nblk[0], d.G, d.Np, d.Nft, d.nr);
     hf_check_launch();
 }
 
 void launch_hf_rb(const DevHF &d, int colour, hipStream_t s) {
-    const int p0 = colour == 0 ? 0 : d.n_red;
-    const int count = colour == 0 ? d.n_red : d.N - d.n_red;
-    if (count <= 0) return;
-    const int npg_blk = 256 / d.Nft;
-    const int64_t npg = (int64_t)count * d.G;
-    const int64_t blocks = (npg + npg_blk - 1) / npg_blk;
-    k_hf_rb<<<(unsigned)blocks, 256, 0, s>>>(d.R, d.bq, d.jp, d.nbr, p0, count, d.G, d.Nfb, d.Nft, npg_blk);
+    const int64_t nb = d.nblk[colour];
+    if (nb <= 0) return;
+    const int64_t blk0 = colour == 0 ? 0 : d.nblk[0];
+    const int64_t red_pg = (int64_t)d.n_red * d.G, all_pg = (int64_t)d.N * d.G;
+    switch (d.Nft) {
+    case 6:
+        k_hf_rb<6><<<(unsigned)nb, 256, 0, s>>>(d.R, d.bq, d.jp, d.nbr, blk0, red_pg, all_pg, d.nblk[0], d.G, d.Nfb);
+        break;
+    case 18:
+        k_hf_rb<18><<<(unsigned)nb, 256, 0, s>>>(d.R, d.bq, d.jp, d.nbr, blk0, red_pg, all_pg, d.nblk[0], d.G, d.Nfb);
+        break;
+    case 36:
+        k_hf_rb<36><<<(unsigned)nb, 256, 0, s>>>(d.R, d.bq, d.jp, d.nbr, blk0, red_pg, all_pg, d.nblk[0], d.G, d.Nfb);
+        break;
+    default:
+        throw Error(MOC_EINVAL, "hfem: unsupported number of face DoFs");
+    }
     hf_check_launch();
 }
 
+template <int NP> static void hf_reconstruct_np(const DevHF &d, double *phi_out, int64_t nb, size_t lds, hipStream_t s) {
+    k_hf_reconstruct<NP><<<(unsigned)nb, 256, lds, s>>>(d.Ainv, d.flist, d.fval, d.hdim, d.s, d.jp, d.nbr, d.perm,
+                                                        phi_out, (int64_t)d.n_red * d.G, (int64_t)d.N * d.G, d.nblk[0],
+                                                        d.G, d.Nfb, d.Nft);
+}
+
 void launch_hf_reconstruct(const DevHF &d, double *phi_out, hipStream_t s) {
-    const int npg_blk = 256 / d.Nft;
-    const int64_t npg = (int64_t)d.N * d.G;
-    const int64_t blocks = (npg + npg_blk - 1) / npg_blk;
-    k_hf_reconstruct<<<(unsigned)blocks, 256, 0, s>>>(d.Ainv, d.P, d.s, d.jp, d.nbr, d.perm, phi_out, d.N, d.G, d.Np,
-                                                      d.Nfb, d.Nft, npg_blk);
+    const int64_t nb = d.nblk[0] + d.nblk[1];
+    if (nb <= 0) return;
+    const size_t lds = sizeof(double) * (size_t)d.npg_blk * (d.Nft + d.Np);
+    switch (d.Np) {
+    case 1: hf_reconstruct_np<1>(d, phi_out, nb, lds, s); break;
+    case 4: hf_reconstruct_np<4>(d, phi_out, nb, lds, s); break;
+    case 10: hf_reconstruct_np<10>(d, phi_out, nb, lds, s); break;
+    case 20: hf_reconstruct_np<20>(d, phi_out, nb, lds, s); break;
+    case 35: hf_reconstruct_np<35>(d, phi_out, nb, lds, s); break;
+    default: throw Error(MOC_EINVAL, "hfem: unsupported number of moments");
+    }
     hf_check_launch();
 }
 

@@ -96,7 +96,7 @@ class SNSolver:
         self.T, self.G = int(len(tri)), int(st.shape[1])
 
     def close(self):
-        if getattr(self, "_h", None) is not None and moc._lib is not None:
+        if getattr(self, "_h", None) is not None and moc is not None and moc._lib is not None:
             moc._lib.moc_sn_destroy(self._h)
             self._h = None
 

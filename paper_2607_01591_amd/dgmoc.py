@@ -112,7 +112,7 @@ class DGSolver:
         self.U = self.info["n_updates"]
 
     def close(self):
-        if getattr(self, "_h", None) is not None and moc._lib is not None:
+        if getattr(self, "_h", None) is not None and moc is not None and moc._lib is not None:
             moc._lib.moc_dg_destroy(self._h)
             self._h = None
 

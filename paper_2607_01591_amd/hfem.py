@@ -108,7 +108,7 @@ class HFEMSolver:
         self.Np, self.Nft = self.info["n_moments"], self.info["n_face_dofs"]
 
     def close(self):
-        if getattr(self, "_h", None) is not None and moc._lib is not None:
+        if getattr(self, "_h", None) is not None and moc is not None and moc._lib is not None:
             moc._lib.moc_hfem_destroy(self._h)
             self._h = None
 
