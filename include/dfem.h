@@ -38,6 +38,9 @@ typedef struct {
     int64_t n_boundary_faces;
     int64_t device_bytes;
     double setup_ms;
+    int32_t tasks_per_thread; /* tasks one thread of a sweep step takes: the polar directions
+                                 of one element and azimuth (n_polar), or 1 when a level does
+                                 not consist of such runs */
 } moc_sn_info;
 
 /* Create a DFEM-SN context. mesh as for moc_create (box domain only); angles: n_azim (a

@@ -211,8 +211,18 @@ static void sn_create_impl(const moc_mesh *mesh_in, const moc_tracks *angles, co
     // ---- dependency levels per direction (Kahn), classification in FP64
     std::vector<int> level((size_t)nd * T, 0);
     std::vector<int> nlev(nd, 0);
+    // inflow / outflow by the sign of Omega . n, taken with the azimuth's unit in-plane
+    // vector so that the P polar directions of one azimuth (the same vector scaled by
+    // sin(theta_p)) always agree, also for faces almost parallel to it
+    std::vector<double> azc(A), azs(A);
+    for (int a = 0; a < A; ++a) {
+        const double ph = 2.0 * 3.14159265358979323846 * (a + 0.5) / A;
+        azc[a] = std::cos(ph);
+        azs[a] = std::sin(ph);
+    }
     auto onf = [&](int dd, int e, int k) {
-        return dirs[3 * dd] * nrm[((size_t)e * 3 + k) * 2] + dirs[3 * dd + 1] * nrm[((size_t)e * 3 + k) * 2 + 1];
+        const int a = dd / P;
+        return azc[a] * nrm[((size_t)e * 3 + k) * 2] + azs[a] * nrm[((size_t)e * 3 + k) * 2 + 1];
     };
     parallel_for(nd, c->n_threads, 1, [&](int64_t d0, int64_t d1, int) {
         std::vector<int> indeg(T), queue(T);
@@ -262,6 +272,29 @@ static void sn_create_impl(const moc_mesh *mesh_in, const moc_tracks *angles, co
             task_d[k] = dd;
             task_of[(size_t)dd * T + e] = k;
         }
+
+    // ---- the P polar directions of one azimuth see the same in-plane upwind structure, so
+    // an (element, azimuth) normally has its P tasks side by side in one level; the sweep
+    // step then takes them in one thread (one scalar-flux update instead of P). Any level
+    // that breaks the pattern (a face almost parallel to a direction can round differently
+    // for different polar angles) makes every step take one task per thread.
+    {
+        int tg = P;
+        for (int s2 = 0; s2 < nsteps && tg > 1; ++s2) {
+            const int64_t k0 = d.step_off[s2], k1 = d.step_off[s2 + 1];
+            if ((k1 - k0) % P) {
+                tg = 1;
+                break;
+            }
+            for (int64_t k = k0; k < k1 && tg > 1; k += P)
+                for (int p = 0; p < P; ++p)
+                    if (task_e[k + p] != task_e[k] || task_d[k + p] != task_d[k] + p || task_d[k] % P != 0) {
+                        tg = 1;
+                        break;
+                    }
+        }
+        d.tgroup = tg;
+    }
 
     // ---- compressed storage (Alg. DFEM_SN_sweep): a task's slot is held until the last
     // downstream element that reads it has been swept, then reused
@@ -369,7 +402,10 @@ static void sn_create_impl(const moc_mesh *mesh_in, const moc_tracks *angles, co
     };
     std::vector<int> mat(T);
     for (int e = 0; e < T; ++e) mat[e] = mesh_in->region_material[m.tri_region[e]];
-    std::vector<double> st(xs->sigma_t, xs->sigma_t + M * G);
+    // Sigma_t per (element, group), so the sweep step reads it without the material hop
+    std::vector<double> st((size_t)T * G);
+    for (int e = 0; e < T; ++e)
+        for (int g = 0; g < G; ++g) st[(size_t)e * G + g] = xs->sigma_t[(size_t)mat[e] * G + g];
     d.mass = up_real(mass);
     d.fmass = up_real(fmass);
     d.fcpl = up_real(fcpl);
@@ -447,6 +483,7 @@ static void sn_enqueue_sweep(moc_sn_ctx *c, int parity, hipStream_t s) {
     a.bnd_out = d.bnd[1 - parity];
     a.phi_acc = d.phi_acc;
     a.G = d.G;
+    a.tgroup = d.tgroup;
     for (int st = 0; st < d.nsteps; ++st) {
         a.k0 = d.step_off[st];
         a.k1 = d.step_off[st + 1];
@@ -661,6 +698,7 @@ int moc_sn_get_info(const moc_sn_ctx *c, moc_sn_info *info) {
     info->n_boundary_faces = c->d.nd > 0 ? c->d.nbnd / c->d.nd : 0;
     info->device_bytes = c->device_bytes;
     info->setup_ms = c->setup_ms;
+    info->tasks_per_thread = c->d.tgroup;
     return MOC_OK;
 }
 

@@ -16,6 +16,8 @@ constexpr int kSnVacuum = -3;    // inflow through a vacuum side: nothing enters
 
 struct DevSN {
     int T = 0, G = 0, M = 0, nd = 0, nsteps = 0, precision = 0;
+    int tgroup = 1;          // consecutive tasks (the polar directions of one element and
+                             // azimuth) taken by one thread of the sweep step
     int64_t ntask = 0, nslot = 0, nbnd = 0;
     std::vector<int64_t> step_off;   // host [nsteps + 1]
     // geometry, sweep precision
@@ -24,7 +26,7 @@ struct DevSN {
     void *fcpl = nullptr;    // [T][3][9] coupling int_f u_j (own) u_k (neighbour)
     void *nrm = nullptr;     // [T][3][2] outward unit normals
     void *gradw = nullptr;   // [T] area / L (streaming term of the slopes)
-    void *sigt = nullptr;    // [M][G]
+    void *sigt = nullptr;    // [T][G] Sigma_t of each element's material
     void *dirs = nullptr;    // [nd][3] (Omega_x, Omega_y, weight)
     double *area = nullptr;  // [T]
     double *massd = nullptr; // [T][9] FP64 mass matrices for the norms
@@ -52,6 +54,7 @@ struct SnStepArgs {
     double *phi_acc;
     int64_t k0, k1;
     int G;
+    int tgroup;
 };
 
 void launch_sn_step(const SnStepArgs &a, int precision, hipStream_t s);

@@ -20,12 +20,22 @@ namespace moc {
 static constexpr double kFourPiSn = 12.566370614359172953850573533118;
 
 // One sweep step: every (element, direction) task of one dependency level, for every
-// group; one thread per (task, group), groups fastest so that neighbouring lanes share an
-// element's matrices. The upstream elements of a task belong to earlier levels, whose
-// angular fluxes sit in their storage slots.
-template <typename Real> __global__ void k_sn_step(SnStepArgs a) {
-    const int G = a.G;
-    const int64_t n = (a.k1 - a.k0) * G;
+// group, one thread per (task, group). A run of tgroup consecutive tasks (the polar
+// directions of one element and azimuth) sits on adjacent lanes of one wavefront for each
+// group (64 / tgroup runs per wavefront, the remaining lanes idle), so the lanes of a run
+// read the same element data and their contributions to the element's scalar-flux moments
+// are summed across the run with wavefront shuffles: one FP64 atomic per moment and run.
+// The upstream elements of a task belong to earlier levels, whose angular fluxes sit in
+// their storage slots.
+template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStepArgs a) {
+    const int G = a.G, TG = a.tgroup;
+    const int runs_per_wave = 64 / TG;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int pp = lane % TG;
+    const int64_t run = wave * runs_per_wave + lane / TG;
+    const int64_t nrun = (a.k1 - a.k0) / TG * G;
+    const bool valid = lane < runs_per_wave * TG && run < nrun;
     const Real *__restrict__ mass = reinterpret_cast<const Real *>(a.mass);
     const Real *__restrict__ fmass = reinterpret_cast<const Real *>(a.fmass);
     const Real *__restrict__ fcpl = reinterpret_cast<const Real *>(a.fcpl);
@@ -37,12 +47,16 @@ template <typename Real> __global__ void k_sn_step(SnStepArgs a) {
     Real *__restrict__ psi = reinterpret_cast<Real *>(a.psi);
     const Real *__restrict__ bnd_in = reinterpret_cast<const Real *>(a.bnd_in);
     Real *__restrict__ bnd_out = reinterpret_cast<Real *>(a.bnd_out);
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = a.k0 + t / G;
-        const int g = int(t - (k - a.k0) * G);
-        const int e = a.task_e[k], d = a.task_d[k];
+    double contrib[3] = {0.0, 0.0, 0.0};
+    int e = 0, g = 0;
+    if (valid) {
+        const int64_t kg = run / G;
+        g = int(run - kg * G);
+        const int64_t k = a.k0 + kg * TG + pp;
+        e = a.task_e[k];
+        const int d = a.task_d[k];
         const Real ox = dirs[3 * d], oy = dirs[3 * d + 1], wd = dirs[3 * d + 2];
-        const Real st = sigt[a.mat[e] * G + g];
+        const Real st = sigt[(int64_t)e * G + g];
         const Real *m = mass + (int64_t)e * 6;
         const Real M[9] = {m[0], m[1], m[2], m[1], m[3], m[4], m[2], m[4], m[5]};
         Real A[9], b[3];
@@ -109,11 +123,10 @@ template <typename Real> __global__ void k_sn_step(SnStepArgs a) {
         x[1] = (b[1] - A[5] * x[2]) / A[4];
         x[0] = (b[0] - A[1] * x[1] - A[2] * x[2]) / A[0];
         Real *ps = psi + ((int64_t)a.task_slot[k] * G + g) * 3;
-        double *ph = a.phi_acc + ((int64_t)e * G + g) * 3;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             ps[i] = x[i];
-            unsafeAtomicAdd(&ph[i], (double)(wd * x[i]));
+            contrib[i] = (double)(wd * x[i]);
         }
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -125,6 +138,22 @@ template <typename Real> __global__ void k_sn_step(SnStepArgs a) {
                 o[2] = x[2];
             }
         }
+    }
+    // sum each run onto its first lane; every lane of the wavefront takes part in the
+    // shuffles (idle lanes carry zeros, and a run never crosses a wavefront)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double sum = contrib[i];
+        for (int j = 1; j < TG; ++j) {
+            const double v = __shfl_down(contrib[i], j, 64);
+            if (pp + j < TG) sum += v;
+        }
+        contrib[i] = sum;
+    }
+    if (valid && pp == 0) {
+        double *ph = a.phi_acc + ((int64_t)e * G + g) * 3;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) unsafeAtomicAdd(&ph[i], contrib[i]);
     }
 }
 
@@ -314,12 +343,16 @@ static int sn_grid(int64_t n, int block = 256, int cap = 8192) {
 }
 
 void launch_sn_step(const SnStepArgs &a, int precision, hipStream_t s) {
-    const int64_t n = (a.k1 - a.k0) * a.G;
-    if (n <= 0) return;
+    // exactly one thread per (task, group) slot: waves of 64 / tgroup runs of tgroup lanes
+    const int64_t nrun = (a.k1 - a.k0) / a.tgroup * a.G;
+    if (nrun <= 0) return;
+    const int64_t runs_per_wave = 64 / a.tgroup;
+    const int64_t waves = (nrun + runs_per_wave - 1) / runs_per_wave;
+    const int64_t blocks = (waves + 3) / 4;
     if (precision == MOC_PREC_F64)
-        k_sn_step<double><<<sn_grid(n, 128), 128, 0, s>>>(a);
+        k_sn_step<double><<<(unsigned)blocks, 256, 0, s>>>(a);
     else
-        k_sn_step<float><<<sn_grid(n, 128), 128, 0, s>>>(a);
+        k_sn_step<float><<<(unsigned)blocks, 256, 0, s>>>(a);
     sn_check_launch();
 }
 

@@ -18,7 +18,7 @@ from .moc import (MOC_ENOCONV, MOC_OK, PREC, MocError, MocMesh, MocOptions, MocP
 class MocSnInfo(C.Structure):
     _fields_ = [("n_elements", _i32), ("n_directions", _i32), ("n_groups", _i32), ("n_levels", _i32),
                 ("n_tasks", _i64), ("n_slots", _i64), ("n_boundary_faces", _i64), ("device_bytes", _i64),
-                ("setup_ms", _f64)]
+                ("setup_ms", _f64), ("tasks_per_thread", _i32)]
 
 
 SIGNATURES = {

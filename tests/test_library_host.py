@@ -87,6 +87,8 @@ def test_dfem_host_schedule(case):
     info = s.info
     assert info["n_elements"] == len(prob.tri) and info["n_tasks"] == info["n_elements"] * info["n_directions"]
     assert 0 < info["n_slots"] < info["n_tasks"]
+    # the polar directions of an (element, azimuth) share a level and run in one thread
+    assert info["tasks_per_thread"] == (2 if case == "lattice17" else prob.n_polar)
     if case != "lattice17":
         o = SN.SNOracle(prob, n_azim=A, n_polar=None)
         assert info["n_levels"] == o.n_levels
