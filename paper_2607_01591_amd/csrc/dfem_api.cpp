@@ -430,6 +430,18 @@ static void sn_create_impl(const moc_mesh *mesh_in, const moc_tracks *angles, co
     d.bnd[1] = c->dalloc<char>((size_t)std::max<int64_t>(d.nbnd, 1) * G * 3 * rs);
     d.q = c->dalloc<char>((size_t)T * G * 3 * rs);
     d.phi_acc = c->dalloc<double>((size_t)T * G * 3);
+    // runs of tgroup tasks and, per element, its runs (the scalar flux is gathered from them)
+    d.nrun = ntask / d.tgroup;
+    {
+        std::vector<int> off((size_t)T + 1, 0), runs((size_t)d.nrun);
+        for (int64_t r = 0; r < d.nrun; ++r) ++off[(size_t)task_e[(size_t)(r * d.tgroup)] + 1];
+        for (int e = 0; e < T; ++e) off[(size_t)e + 1] += off[(size_t)e];
+        std::vector<int> fill(off.begin(), off.end() - 1);
+        for (int64_t r = 0; r < d.nrun; ++r) runs[(size_t)fill[(size_t)task_e[(size_t)(r * d.tgroup)]]++] = (int)r;
+        d.elem_off = c->upload(off);
+        d.elem_runs = c->upload(runs);
+    }
+    d.run_acc = f64 ? (void *)c->dalloc<double>((size_t)d.nrun * G * 3) : (void *)c->dalloc<float>((size_t)d.nrun * G * 3);
     d.phi[0] = c->dalloc<double>((size_t)T * G * 3);
     d.phi[1] = c->dalloc<double>((size_t)T * G * 3);
     d.partials = c->dalloc<double>(2 * kSnReduceBlocks);
@@ -457,12 +469,11 @@ static std::pair<hipEvent_t, hipEvent_t> sn_prof_events(moc_sn_ctx *c) {
     return ev;
 }
 
-// The launches of one sweep with the emission in d.q: the scalar-flux accumulator is
-// cleared, then one launch per dependency level (every direction's elements of that level,
-// all groups); reflective inflow reads boundary buffer `parity`, outflow writes the other.
+// The launches of one sweep with the emission in d.q: one launch per dependency level
+// (every direction's elements of that level, all groups), then the gather of the scalar
+// flux; reflective inflow reads boundary buffer `parity`, outflow writes the other.
 static void sn_enqueue_sweep(moc_sn_ctx *c, int parity, hipStream_t s) {
     DevSN &d = c->d;
-    launch_sn_fill_f64(d.phi_acc, (int64_t)d.T * d.G * 3, 0.0, s);
     SnStepArgs a{};
     a.mass = d.mass;
     a.fmass = d.fmass;
@@ -481,7 +492,7 @@ static void sn_enqueue_sweep(moc_sn_ctx *c, int parity, hipStream_t s) {
     a.psi = d.psi;
     a.bnd_in = d.bnd[parity];
     a.bnd_out = d.bnd[1 - parity];
-    a.phi_acc = d.phi_acc;
+    a.run_acc = d.run_acc;
     a.G = d.G;
     a.tgroup = d.tgroup;
     for (int st = 0; st < d.nsteps; ++st) {
@@ -489,11 +500,12 @@ static void sn_enqueue_sweep(moc_sn_ctx *c, int parity, hipStream_t s) {
         a.k1 = d.step_off[st + 1];
         launch_sn_step(a, d.precision, s);
     }
+    launch_sn_gather(d, s);
 }
 
-// One sweep. The hundreds of small per-level launches are recorded once per parity into
-// a HIP graph (kernel nodes only; the accumulator is cleared by a kernel) and replayed,
-// which removes most of the per-launch cost.
+// One sweep. The hundreds of small per-level launches and the final gather are recorded
+// once per parity into a HIP graph (kernel nodes only) and replayed, which removes most of
+// the per-launch cost.
 static void sn_sweep_impl(moc_sn_ctx *c, hipStream_t s) {
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     const int parity = c->cur_bnd;

@@ -40,6 +40,10 @@ struct DevSN {
     void *bnd[2] = {nullptr, nullptr};  // [nbnd][G][3], entry = boundary face * nd + direction
     void *q = nullptr;       // [T][G][3] per steradian
     double *phi_acc = nullptr;          // [T][G][3]
+    int64_t nrun = 0;        // runs of tgroup tasks per sweep (run r = tasks r tgroup ...)
+    void *run_acc = nullptr; // [nrun][G][3] scalar-flux contribution of each run (sweep precision)
+    int *elem_off = nullptr; // [T + 1] runs of element e: elem_runs[elem_off[e] .. elem_off[e+1])
+    int *elem_runs = nullptr;
     double *phi[2] = {nullptr, nullptr};
     double *qext = nullptr;
     double *partials = nullptr, *scal = nullptr;
@@ -51,13 +55,14 @@ struct SnStepArgs {
     void *psi;
     const void *bnd_in;
     void *bnd_out;
-    double *phi_acc;
+    void *run_acc;
     int64_t k0, k1;
     int G;
     int tgroup;
 };
 
 void launch_sn_step(const SnStepArgs &a, int precision, hipStream_t s);
+void launch_sn_gather(const DevSN &d, hipStream_t s);
 void launch_sn_prep_user(const DevSN &d, const double *src, hipStream_t s);
 void launch_sn_source(const DevSN &d, const double *phi, hipStream_t s);
 void launch_sn_finalize(const DevSN &d, double *phi_internal, double *phi_user, double *partials, hipStream_t s);

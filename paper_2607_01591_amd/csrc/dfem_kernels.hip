@@ -24,9 +24,9 @@ static constexpr double kFourPiSn = 12.566370614359172953850573533118;
 // directions of one element and azimuth) sits on adjacent lanes of one wavefront for each
 // group (64 / tgroup runs per wavefront, the remaining lanes idle), so the lanes of a run
 // read the same element data and their contributions to the element's scalar-flux moments
-// are summed across the run with wavefront shuffles: one FP64 atomic per moment and run.
-// The upstream elements of a task belong to earlier levels, whose angular fluxes sit in
-// their storage slots.
+// are summed across the run with wavefront shuffles and stored once per run (no atomics;
+// k_sn_gather adds the runs of each element after the last level). The upstream elements
+// of a task belong to earlier levels, whose angular fluxes sit in their storage slots.
 template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStepArgs a) {
     const int G = a.G, TG = a.tgroup;
     const int runs_per_wave = 64 / TG;
@@ -48,12 +48,11 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStep
     const Real *__restrict__ bnd_in = reinterpret_cast<const Real *>(a.bnd_in);
     Real *__restrict__ bnd_out = reinterpret_cast<Real *>(a.bnd_out);
     double contrib[3] = {0.0, 0.0, 0.0};
-    int e = 0, g = 0;
+    const int64_t kg = run / G;
+    const int g = int(run - kg * G);
     if (valid) {
-        const int64_t kg = run / G;
-        g = int(run - kg * G);
         const int64_t k = a.k0 + kg * TG + pp;
-        e = a.task_e[k];
+        const int e = a.task_e[k];
         const int d = a.task_d[k];
         const Real ox = dirs[3 * d], oy = dirs[3 * d + 1], wd = dirs[3 * d + 2];
         const Real st = sigt[(int64_t)e * G + g];
@@ -151,9 +150,24 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStep
         contrib[i] = sum;
     }
     if (valid && pp == 0) {
-        double *ph = a.phi_acc + ((int64_t)e * G + g) * 3;
+        Real *ra = reinterpret_cast<Real *>(a.run_acc) + ((a.k0 / TG + kg) * G + g) * 3;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) unsafeAtomicAdd(&ph[i], contrib[i]);
+        for (int i = 0; i < 3; ++i) ra[i] = (Real)contrib[i];
+    }
+}
+
+// Scalar-flux moments of every element: the sum of its runs' contributions, in a fixed
+// order (run index), one thread per (element, group, moment).
+template <typename Real>
+__global__ void k_sn_gather(const Real *__restrict__ run_acc, const int *__restrict__ elem_off,
+                            const int *__restrict__ elem_runs, double *__restrict__ phi_acc, int T, int G) {
+    const int64_t n = (int64_t)T * G * 3;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int e = int(t / (3 * G));
+        const int gi = int(t - (int64_t)e * 3 * G);
+        double acc = 0.0;
+        for (int j = elem_off[e]; j < elem_off[e + 1]; ++j) acc += (double)run_acc[(int64_t)elem_runs[j] * G * 3 + gi];
+        phi_acc[t] = acc;
     }
 }
 
@@ -353,6 +367,17 @@ void launch_sn_step(const SnStepArgs &a, int precision, hipStream_t s) {
         k_sn_step<double><<<(unsigned)blocks, 256, 0, s>>>(a);
     else
         k_sn_step<float><<<(unsigned)blocks, 256, 0, s>>>(a);
+    sn_check_launch();
+}
+
+void launch_sn_gather(const DevSN &d, hipStream_t s) {
+    const int64_t n = (int64_t)d.T * d.G * 3;
+    if (d.precision == MOC_PREC_F64)
+        k_sn_gather<double><<<sn_grid(n), 256, 0, s>>>((const double *)d.run_acc, d.elem_off, d.elem_runs, d.phi_acc,
+                                                        d.T, d.G);
+    else
+        k_sn_gather<float><<<sn_grid(n), 256, 0, s>>>((const float *)d.run_acc, d.elem_off, d.elem_runs, d.phi_acc,
+                                                       d.T, d.G);
     sn_check_launch();
 }
 
