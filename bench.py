@@ -354,11 +354,9 @@ def main():
         n5, rc5 = P.coarse_cells(base, 17, 17)
         ws = None
         if os.path.exists(weights):
-            from paper_2607_01591_amd.warmstart import CHANNELS, WarmStart
-            ws = WarmStart(s5, base, torch.device("cuda:0"))
-            st = np.load(weights)
-            ws.net.load({"W": [st[f"W{i}"] for i in range(len(CHANNELS) - 1)],
-                         "b": [st[f"b{i}"] for i in range(len(CHANNELS) - 1)]})
+            from paper_2607_01591_amd.warmstart import WarmStart, load_net
+            dev0 = torch.device("cuda:0")
+            ws = WarmStart(s5, base, dev0, net=load_net(weights, dev0, base.n_groups))
         rows = []
         for sd in range(200000, 200000 + args.solve_seeds):
             p5 = P.config(5, seed=sd)

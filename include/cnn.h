@@ -27,21 +27,25 @@ extern "C" {
 #endif
 
 /* y = act(conv3x3(x, w) + bias): BF16 operands, FP32 accumulation on the matrix cores
- * (implicit GEMM: M = pixels, N = Co, K = 9 Ci). bias may be NULL. relu != 0 applies
- * max(0, .). Writes y_bf16 [N][H][W][Co] and/or y_f32 (either may be NULL). */
+ * (implicit GEMM: M = pixels, N = Co, K = 9 Ci). Tap (ky, kx) reads pixel
+ * (y + (ky - 1) d, x + (kx - 1) d) for dilation d >= 1, zero outside the image, so the
+ * output has the input's size. bias may be NULL. relu != 0 applies max(0, .). Writes
+ * y_bf16 [N][H][W][Co] and/or y_f32 (either may be NULL). MOC_EINVAL for bad sizes
+ * (Ci % 32, Co % 16 and Co / 16 in {1, 2, 4}) or d < 1. */
 int cnn_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias, int32_t N,
-                        int32_t H, int32_t W, int32_t Ci, int32_t Co, int32_t relu,
+                        int32_t H, int32_t W, int32_t Ci, int32_t Co, int32_t dilation, int32_t relu,
                         uint16_t *y_bf16, float *y_f32, void *stream);
 
 /* Weight layout for the input gradient: wt[ci][tap][co] = bf16(w[co][8 - tap][ci]) from
- * FP32 w [Co][9][Ci]; then dx = cnn_conv3x3_forward(dz, wt, NULL, ..., Ci'=Co, Co'=Ci). */
+ * FP32 w [Co][9][Ci]; then dx = cnn_conv3x3_forward(dz, wt, NULL, ..., Ci'=Co, Co'=Ci,
+ * same dilation). */
 int cnn_weights_for_dgrad(const float *w, int32_t Co, int32_t Ci, uint16_t *wt, void *stream);
 
-/* Weight gradient, accumulated: dw[co][tap][ci] += sum_{n,y,x} dz[n,y,x,co] x[n, y+ky-1,
- * x+kx-1, ci] (BF16 operands on the matrix cores, FP32 accumulation; dw FP32, caller
- * zeroes it). */
+/* Weight gradient, accumulated: dw[co][tap][ci] += sum_{n,y,x} dz[n,y,x,co]
+ * x[n, y + (ky-1) d, x + (kx-1) d, ci] (BF16 operands on the matrix cores, FP32
+ * accumulation; dw FP32, caller zeroes it; dilation d >= 1). */
 int cnn_conv3x3_wgrad(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t H, int32_t W,
-                      int32_t Ci, int32_t Co, float *dw, void *stream);
+                      int32_t Ci, int32_t Co, int32_t dilation, float *dw, void *stream);
 
 /* db[co] += sum over pixels of dz (FP32 dz [npix][Co]). */
 int cnn_bias_grad(const float *dz, int64_t npix, int32_t Co, float *db, void *stream);

@@ -7,53 +7,57 @@ Network: L layers of 3x3 convolutions with zero padding ("same"), stride 1, NHWC
 activations; ReLU after every layer but the last. Weights are stored as
 W[co][ky][kx][ci] with bias b[co]. Loss: mean squared error over all outputs.
 
-Every function is written from the definition of a discrete convolution:
-    z[n, y, x, co] = b[co] + sum_{ky, kx, ci} x[n, y + ky - 1, x + kx - 1, ci] W[co, ky, kx, ci]
-with x = 0 outside the image. Backward passes follow the chain rule term by term.
-Pinned by central finite differences in the tests.
+Every function is written from the definition of a discrete (dilated) convolution:
+    z[n, y, x, co] = b[co] + sum_{ky, kx, ci} x[n, y + (ky - 1) d, x + (kx - 1) d, ci] W[co, ky, kx, ci]
+with x = 0 outside the image and dilation d >= 1 (d = 1: the plain 3x3 convolution).
+Backward passes follow the chain rule term by term. Pinned by central finite
+differences and, for d > 1, by the polyphase identity (a dilated convolution acts on
+each of the d x d interleaved sub-images as the plain convolution) in the tests.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def pad(x):
-    return np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
+def pad(x, d=1):
+    return np.pad(x, ((0, 0), (d, d), (d, d), (0, 0)))
 
 
-def conv_forward(x, W, b):
-    """x [N, H, Wd, Ci], W [Co, 3, 3, Ci], b [Co] -> z [N, H, Wd, Co]."""
+def conv_forward(x, W, b, d=1):
+    """x [N, H, Wd, Ci], W [Co, 3, 3, Ci], b [Co] -> z [N, H, Wd, Co]; dilation d."""
     N, H, Wd, _ = x.shape
-    xp = pad(x)
+    xp = pad(x, d)
     z = np.zeros((N, H, Wd, W.shape[0])) + b
     for ky in range(3):
         for kx in range(3):
-            patch = xp[:, ky:ky + H, kx:kx + Wd, :]           # x[n, y+ky-1, x+kx-1, :]
+            patch = xp[:, ky * d:ky * d + H, kx * d:kx * d + Wd, :]   # x[n, y+(ky-1)d, x+(kx-1)d, :]
             z += patch @ W[:, ky, kx, :].T
     return z
 
 
-def conv_backward(x, W, dz):
+def conv_backward(x, W, dz, d=1):
     """Gradients of conv_forward given dL/dz: returns (dx, dW, db)."""
     N, H, Wd, _ = x.shape
-    xp = pad(x)
+    xp = pad(x, d)
     dW = np.zeros_like(W)
     dxp = np.zeros_like(xp)
     for ky in range(3):
         for kx in range(3):
-            patch = xp[:, ky:ky + H, kx:kx + Wd, :]
+            patch = xp[:, ky * d:ky * d + H, kx * d:kx * d + Wd, :]
             dW[:, ky, kx, :] = np.einsum("nyxo,nyxi->oi", dz, patch)
-            dxp[:, ky:ky + H, kx:kx + Wd, :] += dz @ W[:, ky, kx, :]
+            dxp[:, ky * d:ky * d + H, kx * d:kx * d + Wd, :] += dz @ W[:, ky, kx, :]
     db = dz.sum(axis=(0, 1, 2))
-    return dxp[:, 1:-1, 1:-1, :], dW, db
+    return dxp[:, d:d + H, d:d + Wd, :], dW, db
 
 
-def forward(x, params):
-    """params: list of (W, b). Returns the output and the per-layer inputs/pre-activations."""
+def forward(x, params, dils=None):
+    """params: list of (W, b); dils: dilation per layer (default 1). Returns the output
+    and the per-layer inputs/pre-activations."""
+    dils = dils or [1] * len(params)
     acts, pre = [x], []
     h = x
     for i, (W, b) in enumerate(params):
-        z = conv_forward(h, W, b)
+        z = conv_forward(h, W, b, dils[i])
         pre.append(z)
         h = np.maximum(z, 0.0) if i < len(params) - 1 else z
         acts.append(h)
@@ -64,14 +68,15 @@ def mse(y, t):
     return float(np.mean((y - t) ** 2))
 
 
-def backward(params, acts, pre, t):
+def backward(params, acts, pre, t, dils=None):
     """Gradients of mse(forward(x), t) with respect to every (W, b)."""
+    dils = dils or [1] * len(params)
     y = acts[-1]
     dh = 2.0 * (y - t) / y.size
     grads = [None] * len(params)
     for i in reversed(range(len(params))):
         dz = dh if i == len(params) - 1 else dh * (pre[i] > 0)
-        dx, dW, db = conv_backward(acts[i], params[i][0], dz)
+        dx, dW, db = conv_backward(acts[i], params[i][0], dz, dils[i])
         grads[i] = (dW, db)
         dh = dx
     return grads

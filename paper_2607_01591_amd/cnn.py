@@ -14,9 +14,9 @@ _P = C.POINTER
 _vp, _i32, _i64, _f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
 
 SIGNATURES = {
-    "cnn_conv3x3_forward": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp],
+    "cnn_conv3x3_forward": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp],
     "cnn_weights_for_dgrad": [_vp, _i32, _i32, _vp, _vp],
-    "cnn_conv3x3_wgrad": [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp],
+    "cnn_conv3x3_wgrad": [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp],
     "cnn_bias_grad": [_vp, _i64, _i32, _vp, _vp],
     "cnn_relu_backward": [_vp, _vp, _i64, _vp, _vp, _vp],
     "cnn_mse_grad": [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp],
@@ -62,10 +62,10 @@ def _ok(rc, what):
 
 
 # bfloat16 tensors are handled as torch.bfloat16 (same bit layout as the kernels' uint16)
-def conv3x3(x, w, bias=None, relu=False, out_bf16=None, out_f32=None, stream=None):
+def conv3x3(x, w, bias=None, relu=False, out_bf16=None, out_f32=None, stream=None, dilation=1):
     N, H, W, Ci = x.shape
     Co = w.shape[0]
-    _ok(lib().cnn_conv3x3_forward(_p(x), _p(w), _p(bias), N, H, W, Ci, Co, int(relu), _p(out_bf16),
+    _ok(lib().cnn_conv3x3_forward(_p(x), _p(w), _p(bias), N, H, W, Ci, Co, int(dilation), int(relu), _p(out_bf16),
                                   _p(out_f32), _s(stream)), "cnn_conv3x3_forward")
 
 
@@ -74,10 +74,11 @@ def weights_for_dgrad(w_f32, out_bf16, stream=None):
     _ok(lib().cnn_weights_for_dgrad(_p(w_f32), Co, Ci, _p(out_bf16), _s(stream)), "cnn_weights_for_dgrad")
 
 
-def wgrad(x, dz, dw, stream=None):
+def wgrad(x, dz, dw, stream=None, dilation=1):
     N, H, W, Ci = x.shape
     Co = dz.shape[-1]
-    _ok(lib().cnn_conv3x3_wgrad(_p(x), _p(dz), N, H, W, Ci, Co, _p(dw), _s(stream)), "cnn_conv3x3_wgrad")
+    _ok(lib().cnn_conv3x3_wgrad(_p(x), _p(dz), N, H, W, Ci, Co, int(dilation), _p(dw), _s(stream)),
+        "cnn_conv3x3_wgrad")
 
 
 def bias_grad(dz_f32, db, stream=None):
@@ -133,13 +134,17 @@ class ConvNet:
 
     chans: channel counts [C0, C1, ..., CL] already padded (C0..C_{L-1} multiples of 32,
     CL a multiple of 32 as well so that the input gradient of the last layer can reuse
-    the forward kernel). Master weights are FP32; BF16 copies feed the matrix cores.
+    the forward kernel). dilations: per layer (default 1). Master weights are FP32; BF16
+    copies feed the matrix cores.
     """
 
     def __init__(self, chans: List[int], device, seed: int = 0, in_used: Optional[int] = None,
-                 out_used: Optional[int] = None):
+                 out_used: Optional[int] = None, dilations: Optional[List[int]] = None):
         import torch
         self.chans = chans
+        self.dil = list(dilations) if dilations is not None else [1] * (len(chans) - 1)
+        if len(self.dil) != len(chans) - 1:
+            raise ValueError("one dilation per layer")
         self.dev = device
         g = np.random.default_rng(seed)
         self.W, self.b, self.Wb = [], [], []
@@ -178,12 +183,12 @@ class ConvNet:
             co = self.chans[li + 1]
             if li < L - 1:
                 nxt = torch.empty((N, H, Wd, co), dtype=torch.bfloat16, device=self.dev)
-                conv3x3(h, self.Wb[li], self.b[li], relu=True, out_bf16=nxt)
+                conv3x3(h, self.Wb[li], self.b[li], relu=True, out_bf16=nxt, dilation=self.dil[li])
                 acts.append(nxt)
                 h = nxt
             else:
                 out = torch.empty((N, H, Wd, co), dtype=torch.float32, device=self.dev)
-                conv3x3(h, self.Wb[li], self.b[li], relu=False, out_f32=out)
+                conv3x3(h, self.Wb[li], self.b[li], relu=False, out_f32=out, dilation=self.dil[li])
         return (out, acts) if keep else out
 
     def gradients(self, x, target, cv):
@@ -202,14 +207,14 @@ class ConvNet:
         for li in reversed(range(L)):
             dW = torch.zeros_like(self.W[li])
             db = torch.zeros_like(self.b[li])
-            wgrad(acts[li], dz_b, dW)
+            wgrad(acts[li], dz_b, dW, dilation=self.dil[li])
             bias_grad(dz_f, db)
             grads[li] = (dW, db)
             if li > 0:
                 wt = torch.empty((self.chans[li], 9, self.chans[li + 1]), dtype=torch.bfloat16, device=self.dev)
                 weights_for_dgrad(self.W[li], wt)
                 dx = torch.empty((N, H, Wd, self.chans[li]), dtype=torch.float32, device=self.dev)
-                conv3x3(dz_b, wt, None, relu=False, out_f32=dx)
+                conv3x3(dz_b, wt, None, relu=False, out_f32=dx, dilation=self.dil[li])
                 dz_f = torch.empty_like(dx)
                 dz_b = torch.empty(dx.shape, dtype=torch.bfloat16, device=self.dev)
                 relu_backward(dx, acts[li], dz_f, dz_b)
@@ -230,7 +235,7 @@ class ConvNet:
 
     def state(self):
         return {"W": [w.cpu().numpy() for w in self.W], "b": [b.cpu().numpy() for b in self.b],
-                "chans": list(self.chans)}
+                "chans": list(self.chans), "dil": list(self.dil)}
 
     def load(self, st):
         import torch

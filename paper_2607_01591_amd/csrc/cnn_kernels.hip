@@ -30,11 +30,11 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast
 
 // ---------------------------------------------------------------- forward
 // Block = 4 wavefronts = 64 consecutive pixels of one image row; wave w owns pixels
-// [16 w, 16 w + 16) and all Co = 16 NCT output channels.
+// [16 w, 16 w + 16) and all Co = 16 NCT output channels. Taps sit dil pixels apart.
 template <int NCT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
                                                   const float *__restrict__ bias, int N, int H, int W, int Ci, int relu,
-                                                  uint16_t *__restrict__ yb, float *__restrict__ yf) {
+                                                  int dil, uint16_t *__restrict__ yb, float *__restrict__ yf) {
     const int Co = NCT * 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int tiles_x = (W + 63) / 64;
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ x
 #pragma unroll
     for (int c = 0; c < NCT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1, xx = xbase + m + tap % 3 - 1;
+        const int yy = y + (tap / 3 - 1) * dil, xx = xbase + m + (tap % 3 - 1) * dil;
         const bool inb = yy >= 0 && yy < H && xx >= 0 && xx < W;
         const int64_t xoff = inb ? (((int64_t)n * H + yy) * W + xx) * Ci : 0;
         for (int c0 = 0; c0 < Ci; c0 += 32) {
@@ -83,7 +83,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ x
 // Block (row chunk, tap): rows [r0, r0 + rows) of the N*H image rows. The 16x16
 // output tiles (co, ci) are spread over the 4 wavefronts; K = pixels in steps of 32.
 __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dz, int N,
-                                                    int H, int W, int Ci, int Co, float *__restrict__ dw, int rows) {
+                                                    int H, int W, int Ci, int Co, int dil, float *__restrict__ dw,
+                                                    int rows) {
     const int tap = blockIdx.y, ky = tap / 3, kx = tap % 3;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kb = lane >> 4;
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
         f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int row = r0; row < r1; ++row) {
             const int n = row / H, y = row % H;
-            const int yy = y + ky - 1;
+            const int yy = y + (ky - 1) * dil;
             if (yy < 0 || yy >= H) continue;     // uniform over the block
             const uint16_t *dzr = dz + ((int64_t)n * H + y) * W * Co;
             const uint16_t *xr = x + ((int64_t)n * H + yy) * W * Ci;
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int px = p0 + kb * 8 + i;
-                    const int xx = px + kx - 1;
+                    const int xx = px + (kx - 1) * dil;
                     av[i] = px < W ? dzr[(int64_t)px * Co + co] : uint16_t(0);
                     bv[i] = (px < W && xx >= 0 && xx < W) ? xr[(int64_t)xx * Ci + ci] : uint16_t(0);
                 }
@@ -276,15 +277,16 @@ inline int launched() { return hipGetLastError() == hipSuccess ? MOC_OK : MOC_EH
 extern "C" {
 
 int cnn_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias, int32_t N, int32_t H, int32_t W, int32_t Ci,
-                        int32_t Co, int32_t relu, uint16_t *y_bf16, float *y_f32, void *stream) {
-    if (!x || !w || (!y_bf16 && !y_f32) || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 32 || Co <= 0 || Co % 16)
+                        int32_t Co, int32_t dilation, int32_t relu, uint16_t *y_bf16, float *y_f32, void *stream) {
+    if (!x || !w || (!y_bf16 && !y_f32) || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 32 || Co <= 0 || Co % 16 ||
+        dilation < 1)
         return MOC_EINVAL;
     const dim3 grid((unsigned)((int64_t)N * H * ((W + 63) / 64)));
     hipStream_t s = (hipStream_t)stream;
     switch (Co / 16) {
-        case 1: hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, y_bf16, y_f32); break;
-        case 2: hipLaunchKernelGGL(k_conv_fwd<2>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, y_bf16, y_f32); break;
-        case 4: hipLaunchKernelGGL(k_conv_fwd<4>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, y_bf16, y_f32); break;
+        case 1: hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
+        case 2: hipLaunchKernelGGL(k_conv_fwd<2>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
+        case 4: hipLaunchKernelGGL(k_conv_fwd<4>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
         default: return MOC_EINVAL;
     }
     return launched();
@@ -297,12 +299,13 @@ int cnn_weights_for_dgrad(const float *w, int32_t Co, int32_t Ci, uint16_t *wt, 
     return launched();
 }
 
-int cnn_conv3x3_wgrad(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co, float *dw,
-                      void *stream) {
-    if (!x || !dz || !dw || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 16 || Co <= 0 || Co % 16) return MOC_EINVAL;
+int cnn_conv3x3_wgrad(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                      int32_t dilation, float *dw, void *stream) {
+    if (!x || !dz || !dw || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 16 || Co <= 0 || Co % 16 || dilation < 1)
+        return MOC_EINVAL;
     const int rows = 4;
     const dim3 grid((unsigned)(((int64_t)N * H + rows - 1) / rows), 9);
-    hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, (hipStream_t)stream, x, dz, N, H, W, Ci, Co, dw, rows);
+    hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, (hipStream_t)stream, x, dz, N, H, W, Ci, Co, dilation, dw, rows);
     return launched();
 }
 

@@ -4,7 +4,9 @@ measure warm vs cold solves on held-out seeds.
 Data: problems of the 17 x 17 lattice family (fixed mesh, material map and cross
 sections redrawn per seed); each is solved by libmoc (FP32 sweep) to `--tol-data`,
 its flux rasterised to log(phi) targets. Training: MSE on the 7 output channels, Adam,
-all on the project's HIP kernels. Evaluation: iterations and wall time to `--tol`,
+all on the project's HIP kernels; each batch is rotated / mirrored by a random element of
+the square's symmetry group, and the weights of the epoch with the lowest validation loss
+are kept. Evaluation: iterations and wall time to `--tol`,
 cold start vs the network's guess vs a non-learned guess (flat homogenised spectrum).
 
 python -m paper_2607_01591_amd.train_warmstart --train 160 --val 32 --test 16 \
@@ -42,6 +44,7 @@ def main(argv=None):
                     help="seconds: stop after the epoch that exceeds this (0 = no limit)")
     ap.add_argument("--no-cmfd", action="store_true",
                     help="generate the training data without CMFD acceleration")
+    ap.add_argument("--no-augment", action="store_true", help="train without the rotations and mirror images")
     ap.add_argument("--data-budget", type=float, default=0.0,
                     help="seconds: stop generating training problems once this is spent (0 = no limit)")
     a = ap.parse_args(argv)
@@ -51,7 +54,7 @@ def main(argv=None):
     import torch
     from . import cnn, moc
     from . import problems as P
-    from .warmstart import C_OUT_PAD, CHANNELS, C_IN, WarmStart, homogenized_guess
+    from .warmstart import C_OUT_PAD, CHANNELS, DILATIONS, C_IN, WarmStart, homogenized_guess, load_net
 
     dev = torch.device("cuda:0")
     base = P.config(5, seed=100000)
@@ -86,9 +89,7 @@ def main(argv=None):
 
     report = {"tol": a.tol, "tol_data": a.tol_data}
     if a.weights:
-        st = np.load(a.weights)
-        ws.net.load({"W": [st[f"W{i}"] for i in range(len(CHANNELS) - 1)],
-                     "b": [st[f"b{i}"] for i in range(len(CHANNELS) - 1)]})
+        ws.net = load_net(a.weights, dev, base.n_groups)
         log(f"loaded {a.weights}")
     else:
         Xva, Tva, _ = make_data(list(range(101800, 101800 + a.val)), "val")
@@ -101,30 +102,46 @@ def main(argv=None):
         rng = np.random.default_rng(0)
         t0 = time.perf_counter()
         hist = []
+        best = (np.inf, -1, None)
         for ep in range(a.epochs):
             lr = a.lr * (0.5 ** (ep // max(1, a.epochs // 4)))
             perm = rng.permutation(n_train)
             tl = []
             for b0 in range(0, n_train - a.batch + 1, a.batch):
                 idx = torch.as_tensor(perm[b0:b0 + a.batch], device=dev)
-                tl.append(net.train_step(Xtr[idx].contiguous(), Ttr[idx].contiguous(), G, lr=lr))
+                xb, tb = Xtr[idx], Ttr[idx]
+                if not a.no_augment:
+                    # the lattice's square symmetry: a rotated or mirrored material map is
+                    # another valid problem whose flux is the same map of the flux
+                    rot, flip = int(rng.integers(4)), bool(rng.integers(2))
+                    xb, tb = torch.rot90(xb, rot, dims=(1, 2)), torch.rot90(tb, rot, dims=(1, 2))
+                    if flip:
+                        xb, tb = torch.flip(xb, dims=(2,)), torch.flip(tb, dims=(2,))
+                tl.append(net.train_step(xb.contiguous(), tb.contiguous(), G, lr=lr))
             vl = []
             for b0 in range(0, a.val, a.batch):
                 y = net.forward(Xva[b0:b0 + a.batch].contiguous())
                 vl.append(float(((y[..., :G] - Tva[b0:b0 + a.batch, ..., :G]) ** 2).mean().item()))
             hist.append((float(np.mean(tl)), float(np.mean(vl))))
+            if hist[-1][1] < best[0]:
+                best = (hist[-1][1], ep, net.state())
             log(f"epoch {ep + 1}/{a.epochs} lr {lr:.1e}: train {hist[-1][0]:.4e} val {hist[-1][1]:.4e} "
                 f"({time.perf_counter() - t0:.0f} s)")
             if a.train_budget > 0 and time.perf_counter() - t0 > a.train_budget:
                 log(f"training budget spent after {ep + 1} epochs")
                 break
+        # keep the weights of the epoch with the lowest validation loss
+        net.load(best[2])
+        log(f"best validation loss {best[0]:.4e} at epoch {best[1] + 1}")
+        report["best_val"], report["best_epoch"] = best[0], best[1] + 1
         report["train_history"] = hist
         report["train_seconds"] = time.perf_counter() - t0
         if a.out:
             os.makedirs(os.path.dirname(a.out), exist_ok=True)
             st = net.state()
             np.savez(a.out, **{f"W{i}": w for i, w in enumerate(st["W"])},
-                     **{f"b{i}": b for i, b in enumerate(st["b"])}, chans=np.array(CHANNELS))
+                     **{f"b{i}": b for i, b in enumerate(st["b"])}, chans=np.array(CHANNELS),
+                     dil=np.array(DILATIONS))
             log(f"saved {a.out}")
 
     # ---------------------------------------------------------------- evaluation

@@ -21,7 +21,23 @@ from . import cnn, moc
 IMG = 128
 C_IN, C_IN_PAD = 28, 32
 C_OUT_PAD = 32
-CHANNELS = [C_IN_PAD, 64, 64, 64, 64, 64, C_OUT_PAD]   # 6 layers, 64 channels
+CHANNELS = [C_IN_PAD, 64, 64, 64, 64, 64, 64, C_OUT_PAD]   # 7 layers, 64 channels
+# Dilations double up to 32 pixels, then a local output layer: the receptive field is
+# 1 + 2 (1 + 2 + 4 + 8 + 16 + 32 + 1) = 129 pixels, the whole 128-pixel image, so the
+# network can see the lattice-wide flux shape (the slowly decaying error of the power
+# iteration), not only a pin's neighbourhood.
+DILATIONS = [1, 2, 4, 8, 16, 32, 1]
+
+
+def load_net(path, device, n_groups) -> cnn.ConvNet:
+    """A network with the channel counts and dilations stored in a weights file
+    (numpy .npz written by train_warmstart; files without dilations are undilated)."""
+    st = np.load(path)
+    chans = [int(c) for c in st["chans"]]
+    dil = [int(d) for d in st["dil"]] if "dil" in st.files else [1] * (len(chans) - 1)
+    net = cnn.ConvNet(chans, device, seed=0, in_used=C_IN, out_used=n_groups, dilations=dil)
+    net.load({"W": [st[f"W{i}"] for i in range(len(chans) - 1)], "b": [st[f"b{i}"] for i in range(len(chans) - 1)]})
+    return net
 
 
 def material_features(prob) -> np.ndarray:
@@ -66,7 +82,7 @@ class WarmStart:
         uv = np.stack([(cen[:, 0] - x0) / self.dx - 0.5, (cen[:, 1] - y0) / self.dy - 0.5], 1)
         self.uv = torch.as_tensor(uv.astype(np.float32), device=device)
         self.net = net if net is not None else cnn.ConvNet(CHANNELS, device, seed=0, in_used=C_IN,
-                                                           out_used=self.G)
+                                                           out_used=self.G, dilations=DILATIONS)
 
     # ---------------------------------------------------------------- data
     def rasterize(self, prob, out=None):

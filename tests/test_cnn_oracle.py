@@ -1,5 +1,6 @@
-"""Pins for the numpy CNN oracle: central finite differences of the loss, and a 1x1
-special case against a plain matrix product."""
+"""Pins for the numpy CNN oracle: central finite differences of the loss, a 1x1
+special case against a plain matrix product, shifted taps, and for dilated
+convolutions the polyphase identity."""
 import numpy as np
 
 from oracle import cnn_oracle as C
@@ -74,3 +75,66 @@ def test_input_gradient_matches_central_differences():
 def test_adam_first_step_moves_by_lr():
     p, m, v = C.adam_step(np.array([1.0, -2.0]), np.array([0.3, -5.0]), np.zeros(2), np.zeros(2), 1, lr=0.01)
     np.testing.assert_allclose(p, [0.99, -1.99], rtol=1e-6)
+
+
+def test_dilated_conv_acts_on_interleaved_sub_images():
+    """Polyphase identity: with dilation d, output pixel (y, x) only sees inputs at
+    (y + (ky-1) d, x + (kx-1) d), i.e. the sub-image of pixels congruent to (y, x) mod d,
+    on which it is the plain 3x3 convolution."""
+    rng = np.random.default_rng(4)
+    W = rng.normal(size=(3, 3, 3, 2))
+    b = rng.normal(size=3)
+    for d in (2, 3):
+        x = rng.normal(size=(2, 11, 9, 2))
+        z = C.conv_forward(x, W, b, d)
+        for a in range(d):
+            for c in range(d):
+                np.testing.assert_allclose(z[:, a::d, c::d, :], C.conv_forward(x[:, a::d, c::d, :], W, b),
+                                           rtol=1e-13, atol=1e-13)
+
+
+def test_dilated_shift_tap():
+    x = np.zeros((1, 9, 9, 1))
+    x[0, 2, 5, 0] = 1.0
+    W = np.zeros((1, 3, 3, 1))
+    W[0, 0, 2, 0] = 1.0            # z[y, x] = x[y - 3, x + 3] at d = 3
+    z = C.conv_forward(x, W, np.zeros(1), 3)
+    expect = np.zeros((1, 9, 9, 1))
+    expect[0, 5, 2, 0] = 1.0
+    np.testing.assert_array_equal(z, expect)
+
+
+def test_dilated_gradients_match_central_differences():
+    rng = np.random.default_rng(5)
+    params = _params(rng, [2, 3, 2])
+    dils = [2, 3]
+    x = rng.normal(size=(1, 8, 7, 2))
+    t = rng.normal(size=(1, 8, 7, 2))
+    y, acts, pre = C.forward(x, params, dils)
+    grads = C.backward(params, acts, pre, t, dils)
+    h = 1e-6
+    for li, (W, b) in enumerate(params):
+        for arr, g in ((W, grads[li][0]), (b, grads[li][1])):
+            flat = arr.reshape(-1)
+            gf = g.reshape(-1)
+            for idx in rng.choice(flat.size, size=min(10, flat.size), replace=False):
+                old = flat[idx]
+                flat[idx] = old + h
+                lp = C.mse(C.forward(x, params, dils)[0], t)
+                flat[idx] = old - h
+                lm = C.mse(C.forward(x, params, dils)[0], t)
+                flat[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - gf[idx]) < 1e-7 + 1e-5 * abs(fd), (li, idx, fd, gf[idx])
+    W = params[0][0]
+    dz = rng.normal(size=(1, 8, 7, 3))
+    dx, _, _ = C.conv_backward(x, W, dz, 2)
+    for idx in rng.choice(x.size, size=12, replace=False):
+        xf = x.reshape(-1)
+        old = xf[idx]
+        xf[idx] = old + h
+        lp = np.sum(C.conv_forward(x, W, np.zeros(3), 2) * dz)
+        xf[idx] = old - h
+        lm = np.sum(C.conv_forward(x, W, np.zeros(3), 2) * dz)
+        xf[idx] = old
+        assert abs((lp - lm) / (2 * h) - dx.reshape(-1)[idx]) < 1e-6

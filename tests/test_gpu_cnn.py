@@ -31,64 +31,67 @@ def _np(t):
     return t.float().cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("N,H,W,Ci,Co,relu", [(2, 5, 70, 32, 16, False), (1, 4, 64, 64, 64, True),
-                                               (1, 3, 20, 32, 32, True)])
-def test_conv_forward_exact(N, H, W, Ci, Co, relu, cuda):
+@pytest.mark.parametrize("N,H,W,Ci,Co,relu,d", [(2, 5, 70, 32, 16, False, 1), (1, 4, 64, 64, 64, True, 1),
+                                                 (1, 3, 20, 32, 32, True, 1), (2, 9, 70, 32, 32, True, 2),
+                                                 (1, 12, 40, 64, 64, False, 4), (1, 5, 20, 32, 16, False, 16)])
+def test_conv_forward_exact(N, H, W, Ci, Co, relu, d, cuda):
     import torch
     from paper_2607_01591_amd import cnn
-    log(f"[cnn fwd] {N}x{H}x{W} {Ci}->{Co}")
+    log(f"[cnn fwd] {N}x{H}x{W} {Ci}->{Co} dilation {d}")
     rng = np.random.default_rng(0)
     x = _bf(rng.normal(size=(N, H, W, Ci)), cuda)
     w = _bf(rng.normal(0, 0.2, size=(Co, 9, Ci)), cuda)
     b = torch.as_tensor(rng.normal(size=Co).astype(np.float32), device=cuda)
     yf = torch.empty((N, H, W, Co), dtype=torch.float32, device=cuda)
     yb = torch.empty((N, H, W, Co), dtype=torch.bfloat16, device=cuda)
-    cnn.conv3x3(x, w, b, relu=relu, out_bf16=yb, out_f32=yf)
-    ref = CO.conv_forward(_np(x), _np(w).reshape(Co, 3, 3, Ci), _np(b))
+    cnn.conv3x3(x, w, b, relu=relu, out_bf16=yb, out_f32=yf, dilation=d)
+    ref = CO.conv_forward(_np(x), _np(w).reshape(Co, 3, 3, Ci), _np(b), d)
     if relu:
         ref = np.maximum(ref, 0)
     np.testing.assert_allclose(_np(yf), ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())
     np.testing.assert_allclose(_np(yb), ref, rtol=1e-2, atol=1e-2 * np.abs(ref).max())
 
 
-def test_wgrad_and_dgrad_exact(cuda):
+@pytest.mark.parametrize("d", [1, 3, 8])
+def test_wgrad_and_dgrad_exact(d, cuda):
     import torch
     from paper_2607_01591_amd import cnn
-    log("[cnn wgrad/dgrad]")
+    log(f"[cnn wgrad/dgrad] dilation {d}")
     rng = np.random.default_rng(1)
-    N, H, W, Ci, Co = 2, 6, 40, 32, 32
+    N, H, W, Ci, Co = 2, 10, 40, 32, 32
     x = _bf(rng.normal(size=(N, H, W, Ci)), cuda)
     dz = _bf(rng.normal(size=(N, H, W, Co)), cuda)
     w = rng.normal(0, 0.2, size=(Co, 9, Ci)).astype(np.float32)
     w_bf = _np(_bf(w, cuda))                       # the dgrad kernel rounds weights to BF16
-    dx_ref, dW_ref, _ = CO.conv_backward(_np(x), w_bf.reshape(Co, 3, 3, Ci), _np(dz))
+    dx_ref, dW_ref, _ = CO.conv_backward(_np(x), w_bf.reshape(Co, 3, 3, Ci), _np(dz), d)
     dW = torch.zeros((Co, 9, Ci), dtype=torch.float32, device=cuda)
-    cnn.wgrad(x, dz, dW)
+    cnn.wgrad(x, dz, dW, dilation=d)
     np.testing.assert_allclose(_np(dW), dW_ref.reshape(Co, 9, Ci), rtol=1e-5, atol=1e-5 * np.abs(dW_ref).max())
     wt = torch.empty((Ci, 9, Co), dtype=torch.bfloat16, device=cuda)
     cnn.weights_for_dgrad(torch.as_tensor(w, device=cuda), wt)
     dx = torch.empty((N, H, W, Ci), dtype=torch.float32, device=cuda)
-    cnn.conv3x3(dz, wt, None, relu=False, out_f32=dx)
+    cnn.conv3x3(dz, wt, None, relu=False, out_f32=dx, dilation=d)
     np.testing.assert_allclose(_np(dx), dx_ref, rtol=1e-5, atol=1e-5 * np.abs(dx_ref).max())
 
 
-def test_network_gradients_match_oracle(cuda):
+@pytest.mark.parametrize("dils", [[1, 1, 1], [1, 4, 2]])
+def test_network_gradients_match_oracle(dils, cuda):
     import torch
     from paper_2607_01591_amd import cnn
-    log("[cnn network gradients]")
+    log(f"[cnn network gradients] dilations {dils}")
     rng = np.random.default_rng(2)
     chans = [32, 32, 32, 32]
-    net = cnn.ConvNet(chans, cuda, seed=3, in_used=32, out_used=5)
+    net = cnn.ConvNet(chans, cuda, seed=3, in_used=32, out_used=5, dilations=dils)
     N, H, W = 2, 8, 64
     x = _bf(rng.normal(size=(N, H, W, 32)), cuda)
     t = torch.as_tensor(rng.normal(size=(N, H, W, 32)).astype(np.float32), device=cuda)
     loss, grads = net.gradients(x, t, cv=5)
     params = [(_np(net.Wb[i]).reshape(co, 3, 3, ci), _np(net.b[i])) for i, (ci, co) in
               enumerate(zip(chans[:-1], chans[1:]))]
-    y, acts, pre = CO.forward(_np(x), params)
+    y, acts, pre = CO.forward(_np(x), params, dils)
     tt = _np(t).copy()
     tt[..., 5:] = y[..., 5:]                   # padding channels carry no loss
-    ref = CO.backward(params, acts, pre, tt)
+    ref = CO.backward(params, acts, pre, tt, dils)
     scale = y[..., :5].size / y.size           # oracle MSE averages over all channels
     loss_ref = np.mean((y[..., :5] - _np(t)[..., :5]) ** 2)
     assert abs(loss - loss_ref) < 2e-2 * loss_ref

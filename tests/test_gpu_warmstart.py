@@ -28,13 +28,10 @@ def log(msg):
 def setup(cuda):
     if not os.path.exists(WEIGHTS):
         pytest.skip("no trained warm-start weights in the tree")
-    from paper_2607_01591_amd.warmstart import CHANNELS, WarmStart
+    from paper_2607_01591_amd.warmstart import WarmStart, load_net
     base = P.config(5, seed=100000)
     s = moc.Solver(base, precision="f64", max_iter=20000, check_every=1)
-    ws = WarmStart(s, base, cuda)
-    st = np.load(WEIGHTS)
-    ws.net.load({"W": [st[f"W{i}"] for i in range(len(CHANNELS) - 1)],
-                 "b": [st[f"b{i}"] for i in range(len(CHANNELS) - 1)]})
+    ws = WarmStart(s, base, cuda, net=load_net(WEIGHTS, cuda, base.n_groups))
     return s, ws
 
 
