@@ -3,7 +3,7 @@
  *
  * A small convolutional network predicts the scalar flux of a lattice from its
  * rasterised cross sections; the prediction is handed to moc_set_initial_guess and
- * the plain power iteration (moc_solve) remains the judge of convergence. This is a
+ * the plain power iteration (moc_solve) still decides convergence. This is a
  * project addition; the paper itself accelerates with CMFD (Sec. 2.1, Alg. 1).
  *
  * Conventions:

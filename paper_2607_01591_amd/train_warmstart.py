@@ -10,7 +10,7 @@ are kept. Evaluation: iterations and wall time to `--tol`,
 cold start vs the network's guess vs a non-learned guess (flat homogenised spectrum).
 
 python -m paper_2607_01591_amd.train_warmstart --train 160 --val 32 --test 16 \
-    --out paper_2607_01591_amd/weights/warmstart_17x17.npz --report gpurun_out/warmstart.json
+    --out paper_2607_01591_amd/weights/warmstart_17x17.npz --report warmstart_report.json
 """
 from __future__ import annotations
 
