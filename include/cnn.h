@@ -4,7 +4,7 @@
  * A small convolutional network predicts the scalar flux of a lattice from its
  * rasterised cross sections; the prediction is handed to moc_set_initial_guess and
  * the plain power iteration (moc_solve) still decides convergence. This is a
- * project addition; the paper itself accelerates with CMFD (Sec. 2.1, Alg. 1).
+ * project addition; the paper itself accelerates with CMFD (Sec. 2.1.2, Alg. MOCHFEM_CMFD).
  *
  * Conventions:
  *   - Activations are NHWC: [N][H][W][C], C fastest. BF16 tensors are passed as
