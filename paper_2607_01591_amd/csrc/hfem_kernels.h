@@ -43,7 +43,7 @@ struct DevHF {
     int nr = 0;              // length of the per-face-DoF lists
     int *rlist = nullptr;    // [Nft][nr] moments with t != 0 for each face DoF (-1 ends the list)
     double *rval = nullptr;  // [Nft][nr] their face factors
-    double *jp = nullptr;    // [N][G][Nft] outgoing partial currents, colour-sorted
+    double *jp = nullptr;    // [N][6][G][Nfb] outgoing partial currents, colour-sorted, face-major
     double *s = nullptr;     // [N][G][Np] source moments (u_i, Q), colour-sorted
     double *bq = nullptr;    // [N][G][Nft] h = C s / 4 (B s = h - R h)
     double *phi[2] = {nullptr, nullptr};   // [N][G][Np] by node

@@ -252,13 +252,20 @@ __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ p
     }
 }
 
+// Outgoing partial currents are stored face-major, [colour-sorted node][face][group][mode]:
+// the G groups of one face of a node are one contiguous run, so the neighbours of a block
+// (which holds consecutive groups of the same nodes) read whole cache lines.
+__device__ __forceinline__ int64_t hf_jp_index(int p, int f, int g, int mm, int G, int Nfb) {
+    return (((int64_t)p * 6 + f) * G + g) * Nfb + mm;
+}
+
 // Incoming partial current of face DoF i of colour-sorted node p, group g.
 __device__ __forceinline__ double hf_incoming(const double *__restrict__ jp, const int *__restrict__ nbr, int p, int g,
-                                              int i, int G, int Nfb, int Nft) {
+                                              int i, int G, int Nfb) {
     const int f = i / Nfb, mm = i - f * Nfb;
     const int code = nbr[6 * p + f];
-    if (code >= 0) return jp[((int64_t)code * G + g) * Nft + (f ^ 1) * Nfb + mm];
-    if (code == kHfReflect) return jp[((int64_t)p * G + g) * Nft + i];
+    if (code >= 0) return jp[hf_jp_index(code, f ^ 1, g, mm, G, Nfb)];
+    if (code == kHfReflect) return jp[hf_jp_index(p, f, g, mm, G, Nfb)];
     return 0.0;
 }
 
@@ -283,20 +290,23 @@ __global__ void __launch_bounds__(256) k_hf_rb(const double *__restrict__ R, con
     const bool active = pl < NPG && pg < pg_end;
     double row[NFT];
     double acc = 0.0;
+    int p = 0, g = 0;
     if (active) {
         const double *Rb = R + blk * NFT * NPG * NFT + t;
 #pragma unroll
         for (int j = 0; j < NFT; ++j) row[j] = Rb[j * NPG * NFT];
         acc = h[pg * NFT + i];
-        const int p = int(pg / G), g = int(pg - (int64_t)p * G);
-        jm[t] = hf_incoming(jp, nbr, p, g, i, G, Nfb, NFT) - acc;
+        p = int(pg / G);
+        g = int(pg - (int64_t)p * G);
+        jm[t] = hf_incoming(jp, nbr, p, g, i, G, Nfb) - acc;
     }
     __syncthreads();
     if (active) {
         const double *x = jm + pl * NFT;
 #pragma unroll
         for (int j = 0; j < NFT; ++j) acc += row[j] * x[j];
-        jp[pg * NFT + i] = acc;
+        const int f = i / Nfb;
+        jp[hf_jp_index(p, f, g, i - f * Nfb, G, Nfb)] = acc;
     }
 }
 
@@ -323,7 +333,8 @@ __global__ void __launch_bounds__(256) k_hf_reconstruct(const double *__restrict
         const int64_t pg = pg0 + pl;
         if (pg < pg_end) {
             const int p = int(pg / G), g = int(pg - (int64_t)p * G);
-            net[t] = jp[pg * Nft + i] - hf_incoming(jp, nbr, p, g, i, G, Nfb, Nft);
+            const int f = i / Nfb;
+            net[t] = jp[hf_jp_index(p, f, g, i - f * Nfb, G, Nfb)] - hf_incoming(jp, nbr, p, g, i, G, Nfb);
         }
     }
     __syncthreads();
@@ -467,13 +478,17 @@ __global__ void k_hf_residual_final(const double *__restrict__ partials, int nbl
     if (threadIdx.x == 0) scal[kHfRes] = sqrt(a / (b > 1e-300 ? b : 1e-300));
 }
 
-// outgoing currents from colour-sorted to node order
+// outgoing currents to node order, [node][group][face DoF]
 __global__ void k_hf_currents_to_nodes(const double *__restrict__ jp, const int *__restrict__ perm,
-                                       double *__restrict__ out, int N, int64_t per_node) {
-    const int64_t n = (int64_t)N * per_node;
+                                       double *__restrict__ out, int N, int G, int Nfb) {
+    const int Nft = 6 * Nfb;
+    const int64_t n = (int64_t)N * G * Nft;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int p = int(t / per_node);
-        out[(int64_t)perm[p] * per_node + (t - p * per_node)] = jp[t];
+        const int64_t pg = t / Nft;
+        const int i = int(t - pg * Nft);
+        const int p = int(pg / G), g = int(pg - (int64_t)p * G);
+        const int f = i / Nfb;
+        out[((int64_t)perm[p] * G + g) * Nft + i] = jp[hf_jp_index(p, f, g, i - f * Nfb, G, Nfb)];
     }
 }
 
@@ -600,8 +615,7 @@ void launch_hf_residual(const DevHF &d, const double *phi_new, const double *phi
 }
 
 void launch_hf_currents_to_nodes(const DevHF &d, double *out, hipStream_t s) {
-    const int64_t per_node = (int64_t)d.G * d.Nft;
-    k_hf_currents_to_nodes<<<hf_grid((int64_t)d.N * per_node), 256, 0, s>>>(d.jp, d.perm, out, d.N, per_node);
+    k_hf_currents_to_nodes<<<hf_grid((int64_t)d.N * d.G * d.Nft), 256, 0, s>>>(d.jp, d.perm, out, d.N, d.G, d.Nfb);
     hf_check_launch();
 }
 
