@@ -83,6 +83,17 @@ int cnn_gather_log(const double *table, const int32_t *idx, int64_t npix, int32_
  * rescales any guess, so only the shape of log(phi) is worth learning. */
 int cnn_center(float *img, int64_t n_images, int64_t npix, int32_t C, int32_t Cp, void *stream);
 
+/* Square-image symmetry op in 0..7 (identity, rotations by 90, 180 and 270 degrees,
+ * transpose, the two mirrors, anti-transpose): y [N][S][S][C] BF16 = x transformed
+ * (y[r][c] = x[source_op(r, c)]). x and y must not overlap. */
+int cnn_d4_transform(const uint16_t *x, int32_t N, int32_t S, int32_t C, int32_t op, uint16_t *y, void *stream);
+
+/* acc [S][S][Cs] FP32, channels [0, C) += weight * (y transformed back by the inverse of
+ * op), y [S][S][Cs] FP32 the network's output on the image transformed by op: averaging
+ * the outputs of all 8 ops gives a prediction that respects the square's symmetry. */
+int cnn_d4_accumulate(const float *y, int32_t S, int32_t Cs, int32_t C, int32_t op, float weight, float *acc,
+                      void *stream);
+
 /* De-rasterise: for each of n points with pixel coordinates (u, v) (x then y, pixel
  * centres at integers), bilinear interpolation of img FP32 [H][W][Cs] channels [0, C),
  * clamped at the border; out FP64 [n][C] = exp(value) if apply_exp else value. */

@@ -26,6 +26,8 @@ SIGNATURES = {
     "cnn_gather_log": [_vp, _vp, _i64, _i32, _i32, _vp, _vp],
     "cnn_bilinear_sample": [_vp, _i32, _i32, _i32, _i32, _vp, _i64, _i32, _vp, _vp],
     "cnn_center": [_vp, _i64, _i64, _i32, _i32, _vp],
+    "cnn_d4_transform": [_vp, _i32, _i32, _i32, _i32, _vp, _vp],
+    "cnn_d4_accumulate": [_vp, _i32, _i32, _i32, _i32, _f32, _vp, _vp],
 }
 
 _lib = None
@@ -121,6 +123,21 @@ def center(img, C_used, stream=None):
     n = img.shape[0]
     npix = img.numel() // (n * img.shape[-1])
     _ok(lib().cnn_center(_p(img), n, npix, C_used, img.shape[-1], _s(stream)), "cnn_center")
+
+
+def d4_transform(x, op, out, stream=None):
+    """out = x under square symmetry op (0..7); BF16 [N, S, S, C]."""
+    N, S, S2, Cc = x.shape
+    if S != S2:
+        raise ValueError("square images only")
+    _ok(lib().cnn_d4_transform(_p(x), N, S, Cc, int(op), _p(out), _s(stream)), "cnn_d4_transform")
+
+
+def d4_accumulate(y, C_used, op, weight, acc, stream=None):
+    """acc += weight * (y mapped back from symmetry op); FP32 [S, S, Cs]."""
+    S, S2, Cs = y.shape
+    _ok(lib().cnn_d4_accumulate(_p(y), S, Cs, C_used, int(op), float(weight), _p(acc), _s(stream)),
+        "cnn_d4_accumulate")
 
 
 def bilinear(img, C_used, uv, out, apply_exp=True, stream=None):

@@ -265,6 +265,50 @@ __global__ void k_bilinear(const float *__restrict__ img, int H, int W, int Cs, 
     }
 }
 
+// The 8 symmetries of a square image of side S, as the source pixel of output pixel
+// (r, c): identity, the three rotations, the transpose, the two mirrors and the
+// anti-transpose. Op 1 and op 3 are each other's inverse; the others are their own.
+__device__ __forceinline__ void d4_source(int op, int S, int r, int c, int &sr, int &sc) {
+    switch (op) {
+        case 0: sr = r; sc = c; break;
+        case 1: sr = c; sc = S - 1 - r; break;
+        case 2: sr = S - 1 - r; sc = S - 1 - c; break;
+        case 3: sr = S - 1 - c; sc = r; break;
+        case 4: sr = c; sc = r; break;
+        case 5: sr = r; sc = S - 1 - c; break;
+        case 6: sr = S - 1 - c; sc = S - 1 - r; break;
+        default: sr = S - 1 - r; sc = c; break;
+    }
+}
+
+// y[n][r][c][:] = x[n][source(r, c)][:] (BF16 images)
+__global__ void k_d4_transform(const uint16_t *__restrict__ x, int N, int S, int C, int op, uint16_t *__restrict__ y) {
+    const int64_t tot = (int64_t)N * S * S * C;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t px = i / C;
+        const int ch = int(i - px * C);
+        const int n = int(px / ((int64_t)S * S));
+        const int rc = int(px - (int64_t)n * S * S);
+        int sr, sc;
+        d4_source(op, S, rc / S, rc % S, sr, sc);
+        y[i] = x[(((int64_t)n * S + sr) * S + sc) * C + ch];
+    }
+}
+
+// acc[r][c][ch] += w * y[source_inv(r, c)][ch] for ch < C (FP32 images, row stride Cs):
+// maps the output of the network on a transformed image back to the original frame
+__global__ void k_d4_accumulate(const float *__restrict__ y, int S, int Cs, int C, int op_inv, float w,
+                                float *__restrict__ acc) {
+    const int64_t tot = (int64_t)S * S * C;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t px = i / C;
+        const int ch = int(i - px * C);
+        int sr, sc;
+        d4_source(op_inv, S, int(px / S), int(px % S), sr, sc);
+        acc[px * Cs + ch] += w * y[((int64_t)sr * S + sc) * Cs + ch];
+    }
+}
+
 inline int grid_for(int64_t n, int block, int cap = 4096) {
     int64_t g = (n + block - 1) / block;
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
@@ -360,6 +404,23 @@ int cnn_gather_log(const double *table, const int32_t *idx, int64_t npix, int32_
 int cnn_center(float *img, int64_t n_images, int64_t npix, int32_t C, int32_t Cp, void *stream) {
     if (!img || n_images <= 0 || npix <= 0 || C <= 0 || Cp < C || n_images > 65535) return MOC_EINVAL;
     hipLaunchKernelGGL(k_center, dim3((unsigned)n_images), dim3(1024), 0, (hipStream_t)stream, img, npix, C, Cp);
+    return launched();
+}
+
+int cnn_d4_transform(const uint16_t *x, int32_t N, int32_t S, int32_t C, int32_t op, uint16_t *y, void *stream) {
+    if (!x || !y || x == y || N <= 0 || S <= 0 || C <= 0 || op < 0 || op > 7) return MOC_EINVAL;
+    const int64_t n = (int64_t)N * S * S * C;
+    hipLaunchKernelGGL(k_d4_transform, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, x, N, S, C, op, y);
+    return launched();
+}
+
+int cnn_d4_accumulate(const float *y, int32_t S, int32_t Cs, int32_t C, int32_t op, float weight, float *acc,
+                      void *stream) {
+    if (!y || !acc || y == acc || S <= 0 || C <= 0 || Cs < C || op < 0 || op > 7) return MOC_EINVAL;
+    static const int inverse[8] = {0, 3, 2, 1, 4, 5, 6, 7};
+    const int64_t n = (int64_t)S * S * C;
+    hipLaunchKernelGGL(k_d4_accumulate, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, y, S, Cs, C,
+                       inverse[op], weight, acc);
     return launched();
 }
 

@@ -103,21 +103,32 @@ class WarmStart:
         cnn.gather_log(phi_user, self.pix_region, C_OUT_PAD, out)
         return out
 
-    def predict(self, prob):
-        """Predicted scalar flux [R, G] (device FP64, user order) and the time spent."""
+    def predict(self, prob, symmetrize: bool = True):
+        """Predicted scalar flux [R, G] (device FP64, user order) and the time spent.
+        symmetrize: average the network's log-flux over the 8 symmetries of the square
+        lattice image (rotate / mirror the input, map each output back), which removes the
+        part of the prediction error that does not respect the lattice's symmetry."""
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         img = self.rasterize(prob)
-        y = self.net.forward(img)
+        if symmetrize:
+            out = torch.zeros((IMG, IMG, C_OUT_PAD), dtype=torch.float32, device=self.dev)
+            t = torch.empty_like(img)
+            for op in range(8):
+                cnn.d4_transform(img, op, t)
+                y = self.net.forward(t)
+                cnn.d4_accumulate(y[0], self.G, op, 1.0 / 8.0, out)
+        else:
+            out = self.net.forward(img)[0]
         phi0 = torch.empty((self.solver.R, self.G), dtype=torch.float64, device=self.dev)
-        cnn.bilinear(y[0], self.G, self.uv, phi0, apply_exp=True)
+        cnn.bilinear(out, self.G, self.uv, phi0, apply_exp=True)
         torch.cuda.synchronize()
         return phi0, (time.perf_counter() - t0) * 1e3
 
-    def solve_warm(self, prob, tol=1e-6):
+    def solve_warm(self, prob, tol=1e-6, symmetrize: bool = True):
         """Warm-started solve: prediction + moc_solve; wall time includes the prediction."""
-        phi0, pred_ms = self.predict(prob)
+        phi0, pred_ms = self.predict(prob, symmetrize)
         self.solver.set_initial_guess(phi0, -1.0)
         r = self.solver.solve(tol)
         r["predict_ms"] = pred_ms

@@ -173,3 +173,43 @@ def test_center_matches_numpy(cuda):
     ref = x.astype(np.float64)
     ref[..., :7] -= ref[..., :7].reshape(3, -1).mean(axis=1)[:, None, None, None]
     np.testing.assert_allclose(got, ref, rtol=0, atol=2e-6)
+
+
+def test_d4_transforms(cuda):
+    """The 8 square symmetries: op 0 identity, 1-3 rotations, 4 transpose, 5 and 7
+    mirrors, 6 anti-transpose; every op is a permutation, the 8 are distinct, op 2 is
+    the 180-degree rotation, op 1 composed with itself is op 2, and transforming then
+    accumulating with the same op gives back the image."""
+    import torch
+    from paper_2607_01591_amd import cnn
+    rng = np.random.default_rng(8)
+    S, Cc = 12, 32
+    x = rng.normal(size=(1, S, S, Cc)).astype(np.float32)
+    xb = _bf(x, cuda)
+    xr = _np(xb)[0]
+    outs = []
+    for op in range(8):
+        y = torch.empty_like(xb)
+        cnn.d4_transform(xb, op, y)
+        outs.append(_np(y)[0])
+    np.testing.assert_array_equal(outs[0], xr)
+    np.testing.assert_array_equal(outs[4], xr.transpose(1, 0, 2))
+    np.testing.assert_array_equal(outs[5], xr[:, ::-1])
+    np.testing.assert_array_equal(outs[7], xr[::-1, :])
+    np.testing.assert_array_equal(outs[2], xr[::-1, ::-1])
+    np.testing.assert_array_equal(outs[6], xr[::-1, ::-1].transpose(1, 0, 2))
+    keys = {o.tobytes() for o in outs}
+    assert len(keys) == 8
+    for o in outs:
+        np.testing.assert_array_equal(np.sort(o.ravel()), np.sort(xr.ravel()))
+    y1 = torch.empty_like(xb)
+    cnn.d4_transform(xb, 1, y1)
+    y11 = torch.empty_like(xb)
+    cnn.d4_transform(y1, 1, y11)
+    np.testing.assert_array_equal(_np(y11)[0], outs[2])
+    for op in range(8):
+        y = torch.empty_like(xb)
+        cnn.d4_transform(xb, op, y)
+        acc = torch.zeros((S, S, Cc), dtype=torch.float32, device=cuda)
+        cnn.d4_accumulate(y[0].float().contiguous(), Cc, op, 1.0, acc)
+        np.testing.assert_array_equal(_np(acc), xr)
