@@ -243,6 +243,17 @@ def hfem_leg(args):
         f"= {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.2f} of HBM peak)")
     del s
     torch.cuda.empty_cache()
+    # the same with R and A^-1 stored in FP32 (half the bytes of the sweep)
+    s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2, check_every=1 << 30, fp32_matrices=True)
+    ms32, prof32, _ = time_iterations(s, 20, 2)
+    rb32 = prof32["sweep_ms"] / max(1, prof32["sweeps"])
+    per_pg32 = 4 * Nft * Nft + 8 * 3 * Nft
+    out["fp32_matrices"] = {"ms_per_iteration": ms32, "rb_iteration_ms": rb32, "bytes_per_node_group": per_pg32,
+                            "achieved_GBs": N * G * per_pg32 / (rb32 * 1e-3) / 1e9,
+                            "dof_updates_per_s": N * G * Nft / (rb32 * 1e-3)}
+    log(f"HFEM, FP32 matrices: {ms32:.3f} ms/iteration, red-black iteration {rb32:.3f} ms")
+    del s
+    torch.cuda.empty_cache()
     s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2, max_iter=args.hfem_max_iter,
                         check_every=10)
     r = s.solve(1e-6)

@@ -57,6 +57,9 @@ typedef struct {
                                  info only; device calls return MOC_ESTATE) */
     int32_t check_every;      /* moc_hfem_solve reads (k, residual) back every this many
                                  iterations (<= 0: 1) */
+    int32_t fp32_matrices;    /* 0: R and A^-1 stored in FP64 (default); 1: stored in FP32 (half
+                                 the bytes of the bandwidth-bound sweep; products, currents,
+                                 moments and norms stay FP64) */
 } moc_hfem_options;
 
 typedef struct {
@@ -69,11 +72,13 @@ typedef struct {
     double setup_ms;          /* host checks, uploads and device preassembly */
     double assemble_ms;       /* device preassembly alone: matrix construction and the two
                                  batched Gauss-Jordan inversions per node and group */
+    int32_t fp32_matrices;    /* as in the options */
 } moc_hfem_info;
 
-/* Create a context and preassemble, per node and group, the response matrices R, B of
- * Eq. HFEM_flux_response (J+ = R J- + B s, s_i = (u_i, Q)), the inverse reaction matrix
- * and the reconstruction matrix. All host arrays are borrowed and copied. Errors:
+/* Create a context and preassemble, per node and group, the response matrix R of
+ * Eq. HFEM_flux_response (J+ = R J- + B s, s_i = (u_i, Q); B s is formed from A^-1 s, as
+ * h - R h with h = Lambda^-1 M A^-1 s / 4, so B is not stored) and the inverse reaction
+ * matrix A^-1, both computed in FP64. All host arrays are borrowed and copied. Errors:
  * MOC_EINVAL (null pointer, bad sizes or orders, edges not increasing, material out of
  * range, bc not 0/1, Sigma_t <= 0 or Sigma_r <= 0, non-finite data), MOC_ENOMEM, MOC_EHIP. */
 int moc_hfem_create(const moc_hfem_grid *grid, const moc_xs *xs, const moc_hfem_options *opts, moc_hfem_ctx **out);

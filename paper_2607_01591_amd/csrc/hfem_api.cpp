@@ -259,8 +259,14 @@ static void hf_create_impl(const moc_hfem_grid *grid, const moc_xs *xs, const mo
     d.nblk[0] = ((int64_t)n_red * G + d.npg_blk - 1) / d.npg_blk;
     d.nblk[1] = ((int64_t)(N - n_red) * G + d.npg_blk - 1) / d.npg_blk;
     const size_t slots = (size_t)(d.nblk[0] + d.nblk[1]) * d.npg_blk;   // node-groups incl. block padding
-    d.R = c->dalloc<double>(slots * Nft * Nft);
-    d.Ainv = c->dalloc<double>(slots * Np * Np);
+    d.mat32 = o.fp32_matrices ? 1 : 0;
+    if (d.mat32) {
+        d.R = c->dalloc<float>(slots * Nft * Nft);
+        d.Ainv = c->dalloc<float>(slots * Np * Np);
+    } else {
+        d.R = c->dalloc<double>(slots * Nft * Nft);
+        d.Ainv = c->dalloc<double>(slots * Np * Np);
+    }
     // face factor t of face DoF r and volume mode k: sqrt(2a+1) (+-1)^a for the degree a
     // normal to the face when the transverse degrees match the face mode, else 0
     std::vector<double> tface((size_t)Nft * Np, 0.0);
@@ -555,6 +561,7 @@ int moc_hfem_get_info(const moc_hfem_ctx *c, moc_hfem_info *info) {
     info->device_bytes = c->device_bytes;
     info->setup_ms = c->setup_ms;
     info->assemble_ms = c->assemble_ms;
+    info->fp32_matrices = c->d.mat32;
     return MOC_OK;
 }
 

@@ -35,8 +35,9 @@ struct DevHF {
     // so that one column of every node-group of a block is one contiguous run.
     int npg_blk = 0;         // node-groups per block (256 / Nft)
     int64_t nblk[2] = {0, 0};
-    double *R = nullptr;     // [blocks][Nft][npg_blk][Nft]
-    double *Ainv = nullptr;  // [blocks][Np][npg_blk][Np]
+    int mat32 = 0;           // R and A^-1 stored in FP32 (products still accumulate in FP64)
+    void *R = nullptr;       // [blocks][Nft][npg_blk][Nft]
+    void *Ainv = nullptr;    // [blocks][Np][npg_blk][Np]
     double *tface = nullptr; // [Nft][Np] face factors t (M = face area x t)
     int *flist = nullptr;    // [Np][6] face DoFs with t != 0 for each moment (-1 ends the list)
     double *fval = nullptr;  // [Np][6] their face factors

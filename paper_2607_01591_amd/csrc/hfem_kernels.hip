@@ -103,10 +103,10 @@ __device__ __forceinline__ void hf_block_range(int64_t blk, int64_t red_pg, int6
 struct HfAsmArgs {
     const int *perm, *mat, *vmode;
     const double *hdim, *diff, *sigr, *tface;
-    double *R, *Ainv;
+    void *R, *Ainv;   // double, or float when mat32
     int *status;
     int64_t red_pg, nblk0;
-    int G, Np, Nfb, Nft, wsize, npg_blk;
+    int G, Np, Nfb, Nft, wsize, npg_blk, mat32;
 };
 
 // Preassembly: one wavefront per (colour-sorted node, group). Builds A and inverts it,
@@ -175,12 +175,21 @@ __global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
     // R = I - 4 K^-1 (K = 2I + Y)
     for (int idx = lane; idx < Nft * Nft; idx += 64) {
         const int j = idx / Nft, i = idx - j * Nft;
-        a.R[((blk * Nft + j) * nb + pl) * Nft + i] = (i == j ? 1.0 : 0.0) - 4.0 * W[i * 2 * Nft + Nft + j];
+        const double v = (i == j ? 1.0 : 0.0) - 4.0 * W[i * 2 * Nft + Nft + j];
+        const int64_t o = ((blk * Nft + j) * nb + pl) * Nft + i;
+        if (a.mat32)
+            reinterpret_cast<float *>(a.R)[o] = (float)v;
+        else
+            reinterpret_cast<double *>(a.R)[o] = v;
     }
     // A^-1 (symmetric up to rounding; stored as computed)
     for (int idx = lane; idx < Np * Np; idx += 64) {
         const int k = idx / Np, i = idx - k * Np;
-        a.Ainv[((blk * Np + k) * nb + pl) * Np + i] = Ai[i * Np + k];
+        const int64_t o = ((blk * Np + k) * nb + pl) * Np + i;
+        if (a.mat32)
+            reinterpret_cast<float *>(a.Ainv)[o] = (float)Ai[i * Np + k];
+        else
+            reinterpret_cast<double *>(a.Ainv)[o] = Ai[i * Np + k];
     }
 }
 
@@ -188,12 +197,13 @@ __global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
 // s = V Q (from the previous flux, or V times a caller's emission moments), then
 // a = A^-1 s, then h = C s / 4 = Lambda^-1 M a / 4 (face factor lists per face DoF).
 // Emission: Q_g,i = chi_g F_i / k + sum_{g' != g} Sigma_s,g'->g phi_g',i (+ external).
+template <typename MT>
 __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ phi, const double *__restrict__ user,
                                                     const double *__restrict__ scal, const int *__restrict__ mat,
                                                     const int *__restrict__ perm, const double *__restrict__ vol,
                                                     const double *__restrict__ sigs, const double *__restrict__ nsf,
                                                     const double *__restrict__ chi, const double *__restrict__ qext,
-                                                    const double *__restrict__ Ainv, const int *__restrict__ rlist,
+                                                    const MT *__restrict__ Ainv, const int *__restrict__ rlist,
                                                     const double *__restrict__ rval, double *__restrict__ s,
                                                     double *__restrict__ h, int64_t red_pg, int64_t all_pg,
                                                     int64_t nblk0, int G, int Np, int Nft, int nr) {
@@ -231,10 +241,10 @@ __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ p
     for (int t = threadIdx.x; t < npg_blk * Np; t += blockDim.x) {
         const int pl = t / Np, i = t - pl * Np;
         if (pg0 + pl >= pg_end) continue;
-        const double *Ab = Ainv + blk * Np * npg_blk * Np + t;
+        const MT *Ab = Ainv + blk * Np * npg_blk * Np + t;
         const double *x = sv + pl * Np;
         double acc = 0.0;
-        for (int k = 0; k < Np; ++k) acc += Ab[(int64_t)k * npg_blk * Np] * x[k];
+        for (int k = 0; k < Np; ++k) acc += (double)Ab[(int64_t)k * npg_blk * Np] * x[k];
         av[t] = acc;
     }
     __syncthreads();
@@ -275,8 +285,8 @@ __device__ __forceinline__ double hf_incoming(const double *__restrict__ jp, con
 // contiguous run) while J- - h of the block's node-groups is gathered into LDS (a node's
 // own outgoing currents feed its reflective faces, so they are read before any is
 // overwritten), then forms the product.
-template <int NFT>
-__global__ void __launch_bounds__(256) k_hf_rb(const double *__restrict__ R, const double *__restrict__ h,
+template <int NFT, typename MT>
+__global__ void __launch_bounds__(256) k_hf_rb(const MT *__restrict__ R, const double *__restrict__ h,
                                                double *__restrict__ jp, const int *__restrict__ nbr, int64_t blk0,
                                                int64_t red_pg, int64_t all_pg, int64_t nblk0, int G, int Nfb) {
     constexpr int NPG = 256 / NFT;
@@ -292,9 +302,9 @@ __global__ void __launch_bounds__(256) k_hf_rb(const double *__restrict__ R, con
     double acc = 0.0;
     int p = 0, g = 0;
     if (active) {
-        const double *Rb = R + blk * NFT * NPG * NFT + t;
+        const MT *Rb = R + blk * NFT * NPG * NFT + t;
 #pragma unroll
-        for (int j = 0; j < NFT; ++j) row[j] = Rb[j * NPG * NFT];
+        for (int j = 0; j < NFT; ++j) row[j] = (double)Rb[j * NPG * NFT];
         acc = h[pg * NFT + i];
         p = int(pg / G);
         g = int(pg - (int64_t)p * G);
@@ -314,8 +324,8 @@ __global__ void __launch_bounds__(256) k_hf_rb(const double *__restrict__ R, con
 // node-groups. Thread (slot, i) loads row i of A^-1 for its node-group while the net
 // currents are gathered into LDS; then u = s - M^T j (M = face area x face factor, from
 // the compact per-moment lists of non-zero face factors), then phi_i = sum_k Ainv_ik u_k.
-template <int NP>
-__global__ void __launch_bounds__(256) k_hf_reconstruct(const double *__restrict__ Ainv, const int *__restrict__ flist,
+template <int NP, typename MT>
+__global__ void __launch_bounds__(256) k_hf_reconstruct(const MT *__restrict__ Ainv, const int *__restrict__ flist,
                                                         const double *__restrict__ fval, const double *__restrict__ hdim,
                                                         const double *__restrict__ s, const double *__restrict__ jp,
                                                         const int *__restrict__ nbr, const int *__restrict__ perm,
@@ -359,11 +369,11 @@ __global__ void __launch_bounds__(256) k_hf_reconstruct(const double *__restrict
         const int64_t pg = pg0 + pl;
         if (pg >= pg_end) continue;
         const int p = int(pg / G), g = int(pg - (int64_t)p * G);
-        const double *Ab = Ainv + blk * NP * npg_blk * NP + t;
+        const MT *Ab = Ainv + blk * NP * npg_blk * NP + t;
         const double *uv = u + pl * NP;
         double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) acc += Ab[k * npg_blk * NP] * uv[k];
+        for (int k = 0; k < NP; ++k) acc += (double)Ab[k * npg_blk * NP] * uv[k];
         phi[((int64_t)perm[p] * G + g) * NP + i] = acc;
     }
 }
@@ -528,6 +538,7 @@ void launch_hf_assemble(const DevHF &d, hipStream_t s) {
     a.sigr = d.sigr;
     a.R = d.R;
     a.Ainv = d.Ainv;
+    a.mat32 = d.mat32;
     a.status = d.status;
     a.red_pg = (int64_t)d.n_red * d.G;
     a.nblk0 = d.nblk[0];
@@ -544,41 +555,59 @@ void launch_hf_assemble(const DevHF &d, hipStream_t s) {
     hf_check_launch();
 }
 
+template <typename MT>
+static void hf_prepare_t(const DevHF &d, const double *phi, const double *user, int64_t nb, size_t lds, hipStream_t s) {
+    k_hf_prepare<MT><<<(unsigned)nb, 256, lds, s>>>(phi, user, d.scal, d.mat, d.perm, d.vol, d.sigs, d.nsf, d.chi, d.qext,
+                                                    (const MT *)d.Ainv, d.rlist, d.rval, d.s, d.bq,
+                                                    (int64_t)d.n_red * d.G, (int64_t)d.N * d.G, d.nblk[0], d.G, d.Np,
+                                                    d.Nft, d.nr);
+}
+
 void launch_hf_prepare(const DevHF &d, const double *phi, const double *user, hipStream_t s) {
     const int64_t nb = d.nblk[0] + d.nblk[1];
     if (nb <= 0) return;
     const size_t lds = sizeof(double) * (size_t)d.npg_blk * 2 * d.Np;
-    k_hf_prepare<<<(unsigned)nb, 256, lds, s>>>(phi, user, d.scal, d.mat, d.perm, d.vol, d.sigs, d.nsf, d.chi, d.qext,
-                                                d.Ainv, d.rlist, d.rval, d.s, d.bq, (int64_t)d.n_red * d.G,
-                                                (int64_t)d.N * d.G, d.nblk[0], d.G, d.Np, d.Nft, d.nr);
+    if (d.mat32)
+        hf_prepare_t<float>(d, phi, user, nb, lds, s);
+    else
+        hf_prepare_t<double>(d, phi, user, nb, lds, s);
     hf_check_launch();
+}
+
+template <int NFT, typename MT>
+static void hf_rb_t(const DevHF &d, int64_t nb, int64_t blk0, hipStream_t s) {
+    k_hf_rb<NFT, MT><<<(unsigned)nb, 256, 0, s>>>((const MT *)d.R, d.bq, d.jp, d.nbr, blk0, (int64_t)d.n_red * d.G,
+                                                  (int64_t)d.N * d.G, d.nblk[0], d.G, d.Nfb);
 }
 
 void launch_hf_rb(const DevHF &d, int colour, hipStream_t s) {
     const int64_t nb = d.nblk[colour];
     if (nb <= 0) return;
     const int64_t blk0 = colour == 0 ? 0 : d.nblk[0];
-    const int64_t red_pg = (int64_t)d.n_red * d.G, all_pg = (int64_t)d.N * d.G;
-    switch (d.Nft) {
-    case 6:
-        k_hf_rb<6><<<(unsigned)nb, 256, 0, s>>>(d.R, d.bq, d.jp, d.nbr, blk0, red_pg, all_pg, d.nblk[0], d.G, d.Nfb);
-        break;
-    case 18:
-        k_hf_rb<18><<<(unsigned)nb, 256, 0, s>>>(d.R, d.bq, d.jp, d.nbr, blk0, red_pg, all_pg, d.nblk[0], d.G, d.Nfb);
-        break;
-    case 36:
-        k_hf_rb<36><<<(unsigned)nb, 256, 0, s>>>(d.R, d.bq, d.jp, d.nbr, blk0, red_pg, all_pg, d.nblk[0], d.G, d.Nfb);
-        break;
-    default:
-        throw Error(MOC_EINVAL, "hfem: unsupported number of face DoFs");
+    switch (d.Nft * 2 + (d.mat32 ? 1 : 0)) {
+    case 12: hf_rb_t<6, double>(d, nb, blk0, s); break;
+    case 13: hf_rb_t<6, float>(d, nb, blk0, s); break;
+    case 36: hf_rb_t<18, double>(d, nb, blk0, s); break;
+    case 37: hf_rb_t<18, float>(d, nb, blk0, s); break;
+    case 72: hf_rb_t<36, double>(d, nb, blk0, s); break;
+    case 73: hf_rb_t<36, float>(d, nb, blk0, s); break;
+    default: throw Error(MOC_EINVAL, "hfem: unsupported number of face DoFs");
     }
     hf_check_launch();
 }
 
+template <int NP, typename MT>
+static void hf_reconstruct_t(const DevHF &d, double *phi_out, int64_t nb, size_t lds, hipStream_t s) {
+    k_hf_reconstruct<NP, MT><<<(unsigned)nb, 256, lds, s>>>((const MT *)d.Ainv, d.flist, d.fval, d.hdim, d.s, d.jp, d.nbr,
+                                                            d.perm, phi_out, (int64_t)d.n_red * d.G, (int64_t)d.N * d.G,
+                                                            d.nblk[0], d.G, d.Nfb, d.Nft);
+}
+
 template <int NP> static void hf_reconstruct_np(const DevHF &d, double *phi_out, int64_t nb, size_t lds, hipStream_t s) {
-    k_hf_reconstruct<NP><<<(unsigned)nb, 256, lds, s>>>(d.Ainv, d.flist, d.fval, d.hdim, d.s, d.jp, d.nbr, d.perm,
-                                                        phi_out, (int64_t)d.n_red * d.G, (int64_t)d.N * d.G, d.nblk[0],
-                                                        d.G, d.Nfb, d.Nft);
+    if (d.mat32)
+        hf_reconstruct_t<NP, float>(d, phi_out, nb, lds, s);
+    else
+        hf_reconstruct_t<NP, double>(d, phi_out, nb, lds, s);
 }
 
 void launch_hf_reconstruct(const DevHF &d, double *phi_out, hipStream_t s) {

@@ -22,13 +22,13 @@ class MocHfemGrid(C.Structure):
 
 class MocHfemOptions(C.Structure):
     _fields_ = [("volume_order", _i32), ("face_order", _i32), ("inner_iterations", _i32), ("max_iter", _i32),
-                ("device", _i32), ("check_every", _i32)]
+                ("device", _i32), ("check_every", _i32), ("fp32_matrices", _i32)]
 
 
 class MocHfemInfo(C.Structure):
     _fields_ = [("n_nodes", _i32), ("n_groups", _i32), ("n_moments", _i32), ("n_face_dofs", _i32), ("n_red", _i32),
                 ("n_black", _i32), ("inner_iterations", _i32), ("device_bytes", _i64), ("setup_ms", _f64),
-                ("assemble_ms", _f64)]
+                ("assemble_ms", _f64), ("fp32_matrices", _i32)]
 
 
 SIGNATURES = {
@@ -61,7 +61,8 @@ def lib():
     return L
 
 
-def make_structs(grid, volume_order=2, face_order=1, inner_iterations=2, max_iter=10000, device=0, check_every=1):
+def make_structs(grid, volume_order=2, face_order=1, inner_iterations=2, max_iter=10000, device=0, check_every=1,
+                 fp32_matrices=False):
     """The ABI structures of a BrickGrid; returns (grid, xs, options, keep-alive list)."""
     keep = []
 
@@ -82,18 +83,20 @@ def make_structs(grid, volume_order=2, face_order=1, inner_iterations=2, max_ite
     x = MocXS()
     x.n_materials, x.n_groups = st.shape
     x.sigma_t, x.sigma_s, x.nu_sigma_f, x.chi = _ptr(st, _f64), _ptr(ss, _f64), _ptr(nsf, _f64), _ptr(chi, _f64)
-    o = MocHfemOptions(volume_order, face_order, inner_iterations, max_iter, device, check_every)
+    o = MocHfemOptions(volume_order, face_order, inner_iterations, max_iter, device, check_every, int(fp32_matrices))
     return g, x, o, keep
 
 
 class HFEMSolver:
     """One HFEM context for a ``problems.BrickGrid``; flux and source tensors are device
-    FP64 [N, G, Np] in node order, partial currents [N, G, Nft]."""
+    FP64 [N, G, Np] in node order, partial currents [N, G, Nft]. fp32_matrices stores R and
+    A^-1 in FP32 (FP64 arithmetic otherwise unchanged)."""
 
     def __init__(self, grid, volume_order: int = 2, face_order: int = 1, inner_iterations: int = 2,
-                 max_iter: int = 10000, device: int = 0, check_every: int = 1):
+                 max_iter: int = 10000, device: int = 0, check_every: int = 1, fp32_matrices: bool = False):
         L = lib()
-        g, x, o, keep = make_structs(grid, volume_order, face_order, inner_iterations, max_iter, device, check_every)
+        g, x, o, keep = make_structs(grid, volume_order, face_order, inner_iterations, max_iter, device, check_every,
+                                     fp32_matrices)
         h = C.c_void_p()
         rc = L.moc_hfem_create(C.byref(g), C.byref(x), C.byref(o), C.byref(h))
         del keep

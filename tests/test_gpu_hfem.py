@@ -7,6 +7,7 @@
   a one-node-wide column.
 * Exactly n power iterations (eigenvalue and flux after each full outer loop), a
   converged eigenvalue solve and a fixed-source solve against the oracle's.
+* The same sweeps and eigenvalue solve with R and A^-1 stored in FP32.
 * The 51 x 51 x 32 pin-cell core (7 groups, per-node cross sections) in the timed
   configuration: after two sweeps, sampled nodes satisfy the response relation of
   Eq. HFEM_flux_response (black nodes, whose last update saw the final red currents) and
@@ -57,11 +58,15 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,make,nv,nf,n_inner", CASES, ids=[c[0] for c in CASES])
-def test_sweeps_match_oracle(name, make, nv, nf, n_inner, cuda):
-    log(f"[hfem sweeps] {name}")
+@pytest.mark.parametrize("fp32", [False, True], ids=["f64", "f32mat"])
+def test_sweeps_match_oracle(name, make, nv, nf, n_inner, fp32, cuda):
+    """FP64 matrices to 1e-11; R and A^-1 stored in FP32 to 1e-5 (relative to the
+    largest average flux / current)."""
+    log(f"[hfem sweeps] {name} {'fp32 matrices' if fp32 else 'fp64'}")
     g = make()
     o = _oracle(g, nv, nf, n_inner)
-    s = hfem.HFEMSolver(g, volume_order=nv, face_order=nf, inner_iterations=n_inner)
+    s = hfem.HFEMSolver(g, volume_order=nv, face_order=nf, inner_iterations=n_inner, fp32_matrices=fp32)
+    tol = 1e-5 if fp32 else 1e-11
     rng = np.random.default_rng(9)
     for k in range(4):
         q = rng.uniform(0.1, 2.0, o.shape())
@@ -72,7 +77,7 @@ def test_sweeps_match_oracle(name, make, nv, nf, n_inner, cuda):
         jerr = float(np.abs(_host(s.currents()) - o.jp).max() / max(np.abs(o.jp).max(), 1e-300))
         log(f"  sweep {k + 1}: flux error {err:.2e}, current error {jerr:.2e} ({s.info['n_red']} red, "
             f"{s.info['n_black']} black nodes)")
-        assert err < 1e-11 and jerr < 1e-11
+        assert err < tol and jerr < tol
 
 
 def test_power_iterations_match_oracle(cuda):
@@ -89,11 +94,14 @@ def test_power_iterations_match_oracle(cuda):
         assert abs(r["k"] - k_ref) < 1e-12 and err < 1e-11
 
 
-def test_eigen_solve_matches_oracle(cuda):
-    log("[hfem eigen solve]")
+@pytest.mark.parametrize("fp32", [False, True], ids=["f64", "f32mat"])
+def test_eigen_solve_matches_oracle(fp32, cuda):
+    log(f"[hfem eigen solve] {'fp32 matrices' if fp32 else 'fp64'}")
     g = P.brick_box(4, 4, 4, G=7, n_fuel=2, n_other=1, seed=12, bc=(1, 0, 1, 0, 1, 0))
     ref = _oracle(g, 2, 1, 2).solve(tol=1e-10, max_iter=20000)
-    s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2, max_iter=20000)
+    s = hfem.HFEMSolver(g, volume_order=2, face_order=1, inner_iterations=2, max_iter=20000, fp32_matrices=fp32)
+    # FP32-stored matrices are a fixed operator: the iteration still converges to its own
+    # fixed point in FP64, which differs from the oracle's by the rounding of the matrices
     r = s.solve(1e-10)
     phi = _host(s.flux())
     dx, dy, dz = (np.diff(e) for e in g.edges)
@@ -102,8 +110,11 @@ def test_eigen_solve_matches_oracle(cuda):
     err = float(np.abs(phi / fr(phi) - ref["phi"] / fr(ref["phi"])).max() / np.abs(ref["phi"][..., 0] / fr(ref["phi"])).max())
     log(f"  k {r['k']:.12f} vs {ref['k']:.12f}; {r['iterations']} vs {ref['iterations']} iterations; flux error {err:.2e}")
     assert r["converged"] and ref["converged"]
-    assert abs(r["iterations"] - ref["iterations"]) <= 1
-    assert abs(r["k"] - ref["k"]) < 1e-10 and err < 1e-8
+    if fp32:
+        assert abs(r["k"] - ref["k"]) < 1e-6 and err < 1e-5
+    else:
+        assert abs(r["iterations"] - ref["iterations"]) <= 1
+        assert abs(r["k"] - ref["k"]) < 1e-10 and err < 1e-8
 
 
 def test_fixed_source_solve_matches_oracle(cuda):
