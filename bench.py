@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--no-sn", action="store_true", help="skip the DFEM-SN leg")
     ap.add_argument("--sn-only", action="store_true", help="run only the DFEM-SN leg (profiling)")
     ap.add_argument("--no-hfem", action="store_true", help="skip the HFEM leg")
+    ap.add_argument("--no-cnn", action="store_true", help="skip the warm-start network leg")
+    ap.add_argument("--cnn-only", action="store_true", help="run only the warm-start network leg (profiling)")
     ap.add_argument("--hfem-only", action="store_true", help="run only the HFEM leg (profiling)")
     ap.add_argument("--hfem-max-iter", type=int, default=5000, help="iteration cap of the HFEM solve")
     ap.add_argument("--exp-mode", default="poly")
@@ -200,6 +202,55 @@ def sn_leg(args):
     return out
 
 
+def cnn_leg(args):
+    """Warm-start network on the matrix cores: BF16 forward of the 7-layer dilated network
+    on a batch of 128 x 128 lattice images (FP32 accumulation) and one training step
+    (forward, input and weight gradients, Adam), against the dense BF16 MFMA peak."""
+    import torch
+    from paper_2607_01591_amd import cnn
+    from paper_2607_01591_amd.warmstart import C_IN, CHANNELS, DILATIONS, IMG
+    dev = torch.device("cuda:0")
+    N = 8
+    net = cnn.ConvNet(CHANNELS, dev, seed=0, in_used=C_IN, out_used=7, dilations=DILATIONS)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    x = torch.randn((N, IMG, IMG, CHANNELS[0]), generator=g).to(dev).to(torch.bfloat16)
+    t = torch.randn((N, IMG, IMG, CHANNELS[-1]), generator=g).to(dev)
+    flops_fwd = sum(2 * 9 * ci * co * N * IMG * IMG for ci, co in zip(CHANNELS[:-1], CHANNELS[1:]))
+    for _ in range(3):
+        net.forward(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        net.forward(x)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    for _ in range(2):
+        net.train_step(x, t, 7, lr=1e-4)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        net.train_step(x, t, 7, lr=1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / reps
+    # a training step: forward, input gradient of every layer but the first, weight gradient
+    flops_step = flops_fwd + 2 * flops_fwd - 2 * 9 * CHANNELS[0] * CHANNELS[1] * N * IMG * IMG
+    peak = 2500.0
+    out = {"workload": f"{len(CHANNELS) - 1}-layer 3x3 network {CHANNELS}, dilations {DILATIONS}, batch {N} x "
+                       f"{IMG} x {IMG}, BF16 operands, FP32 accumulation",
+           "forward_ms": fwd_ms, "forward_TFLOPs": flops_fwd / (fwd_ms * 1e-3) / 1e12,
+           "train_step_ms": step_ms, "train_step_TFLOPs": flops_step / (step_ms * 1e-3) / 1e12,
+           "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": peak,
+                        "achieved": flops_fwd / (fwd_ms * 1e-3) / 1e12,
+                        "frac": flops_fwd / (fwd_ms * 1e-3) / 1e12 / peak, "kernel": "k_conv_fwd (whole forward)"}}
+    log(f"CNN: forward {fwd_ms:.3f} ms ({out['forward_TFLOPs']:.1f} TFLOP/s), training step {step_ms:.3f} ms "
+        f"({out['train_step_TFLOPs']:.1f} TFLOP/s)")
+    return out
+
+
 def copy_probe():
     """Two plain 1 GiB device-to-device copies: their HBM counters calibrate the scale of
     the counters of the kernels measured in the same run."""
@@ -282,6 +333,9 @@ def main():
         return
     if args.sn_only:
         print(json.dumps({"dfem_sn": sn_leg(args)}), flush=True)
+        return
+    if args.cnn_only:
+        print(json.dumps({"cnn": cnn_leg(args)}), flush=True)
         return
     if args.hfem_only:
         hf = hfem_leg(args)
@@ -418,6 +472,10 @@ def main():
     if not args.no_hfem:
         hf = hfem_leg(args)
 
+    cn = None
+    if not args.no_cnn:
+        cn = cnn_leg(args)
+
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -450,6 +508,7 @@ def main():
         "dgmoc_3d": dg,
         "dfem_sn": sn,
         "hfem": hf,
+        "cnn": cn,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
