@@ -29,54 +29,69 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(uint3
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 // ---------------------------------------------------------------- forward
-// Block = 4 wavefronts = 64 consecutive pixels of one image row; wave w owns pixels
-// [16 w, 16 w + 16) and all Co = 16 NCT output channels. Taps sit dil pixels apart.
-template <int NCT>
+// Block = 4 wavefronts = 64 MT consecutive pixels of one image row; wave w owns pixels
+// [16 MT w, 16 MT (w + 1)) as MT tiles of 16 and all Co = 16 NCT output channels, so each
+// weight operand it loads feeds MT matrix-core products. Taps sit dil pixels apart.
+template <int NCT, int MT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
                                                   const float *__restrict__ bias, int N, int H, int W, int Ci, int relu,
                                                   int dil, uint16_t *__restrict__ yb, float *__restrict__ yf) {
     const int Co = NCT * 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int tiles_x = (W + 63) / 64;
+    const int tiles_x = (W + 64 * MT - 1) / (64 * MT);
     int t = blockIdx.x;
     const int tx = t % tiles_x;
     t /= tiles_x;
     const int y = t % H, n = t / H;
-    const int xbase = tx * 64 + wv * 16;
+    const int xbase = tx * 64 * MT + wv * 16 * MT;
     const int m = lane & 15, kb = lane >> 4;
-    f32x4 acc[NCT];
+    f32x4 acc[MT][NCT];
 #pragma unroll
-    for (int c = 0; c < NCT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < MT; ++u)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) acc[u][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + (tap / 3 - 1) * dil, xx = xbase + m + (tap % 3 - 1) * dil;
-        const bool inb = yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const int64_t xoff = inb ? (((int64_t)n * H + yy) * W + xx) * Ci : 0;
+        const int yy = y + (tap / 3 - 1) * dil;
+        int64_t xoff[MT];
+        bool inb[MT];
+#pragma unroll
+        for (int u = 0; u < MT; ++u) {
+            const int xx = xbase + u * 16 + m + (tap % 3 - 1) * dil;
+            inb[u] = yy >= 0 && yy < H && xx >= 0 && xx < W;
+            xoff[u] = inb[u] ? (((int64_t)n * H + yy) * W + xx) * Ci : 0;
+        }
         for (int c0 = 0; c0 < Ci; c0 += 32) {
-            const uint4 av = inb ? *reinterpret_cast<const uint4 *>(x + xoff + c0 + kb * 8) : make_uint4(0, 0, 0, 0);
-            const bf16x8 a = as_bf16x8(av);
+            bf16x8 a[MT];
+#pragma unroll
+            for (int u = 0; u < MT; ++u)
+                a[u] = as_bf16x8(inb[u] ? *reinterpret_cast<const uint4 *>(x + xoff[u] + c0 + kb * 8)
+                                        : make_uint4(0, 0, 0, 0));
 #pragma unroll
             for (int c = 0; c < NCT; ++c) {
                 const int co = c * 16 + m;
-                const uint4 bv = *reinterpret_cast<const uint4 *>(w + ((int64_t)co * 9 + tap) * Ci + c0 + kb * 8);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf16x8(bv), acc[c], 0, 0, 0);
+                const bf16x8 b = as_bf16x8(*reinterpret_cast<const uint4 *>(w + ((int64_t)co * 9 + tap) * Ci + c0 + kb * 8));
+#pragma unroll
+                for (int u = 0; u < MT; ++u) acc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b, acc[u][c], 0, 0, 0);
             }
         }
     }
 #pragma unroll
-    for (int c = 0; c < NCT; ++c) {
-        const int co = c * 16 + (lane & 15);
-        const float b = bias ? bias[co] : 0.f;
+    for (int u = 0; u < MT; ++u)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int px = xbase + 4 * (lane >> 4) + i;
-            if (px >= W) continue;
-            float v = acc[c][i] + b;
-            if (relu) v = fmaxf(v, 0.f);
-            const int64_t o = (((int64_t)n * H + y) * W + px) * Co + co;
-            if (yb) yb[o] = f2bf(v);
-            if (yf) yf[o] = v;
+        for (int c = 0; c < NCT; ++c) {
+            const int co = c * 16 + (lane & 15);
+            const float b = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = xbase + u * 16 + 4 * (lane >> 4) + i;
+                if (px >= W) continue;
+                float v = acc[u][c][i] + b;
+                if (relu) v = fmaxf(v, 0.f);
+                const int64_t o = (((int64_t)n * H + y) * W + px) * Co + co;
+                if (yb) yb[o] = f2bf(v);
+                if (yf) yf[o] = v;
+            }
         }
-    }
 }
 
 // ---------------------------------------------------------------- weight gradient
@@ -325,12 +340,18 @@ int cnn_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias,
     if (!x || !w || (!y_bf16 && !y_f32) || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 32 || Co <= 0 || Co % 16 ||
         dilation < 1)
         return MOC_EINVAL;
-    const dim3 grid((unsigned)((int64_t)N * H * ((W + 63) / 64)));
+    // two pixel tiles per wavefront once a row fills 128 pixels (each weight load then feeds
+    // two products); one for narrower images
+    const int mt = W >= 128 ? 2 : 1;
+    const dim3 grid((unsigned)((int64_t)N * H * ((W + 64 * mt - 1) / (64 * mt))));
     hipStream_t s = (hipStream_t)stream;
-    switch (Co / 16) {
-        case 1: hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
-        case 2: hipLaunchKernelGGL(k_conv_fwd<2>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
-        case 4: hipLaunchKernelGGL(k_conv_fwd<4>, grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
+    switch ((Co / 16) * 4 + mt) {
+        case 5: hipLaunchKernelGGL((k_conv_fwd<1, 1>), grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
+        case 6: hipLaunchKernelGGL((k_conv_fwd<1, 2>), grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
+        case 9: hipLaunchKernelGGL((k_conv_fwd<2, 1>), grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
+        case 10: hipLaunchKernelGGL((k_conv_fwd<2, 2>), grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
+        case 17: hipLaunchKernelGGL((k_conv_fwd<4, 1>), grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
+        case 18: hipLaunchKernelGGL((k_conv_fwd<4, 2>), grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
         default: return MOC_EINVAL;
     }
     return launched();

@@ -33,7 +33,9 @@ def _np(t):
 
 @pytest.mark.parametrize("N,H,W,Ci,Co,relu,d", [(2, 5, 70, 32, 16, False, 1), (1, 4, 64, 64, 64, True, 1),
                                                  (1, 3, 20, 32, 32, True, 1), (2, 9, 70, 32, 32, True, 2),
-                                                 (1, 12, 40, 64, 64, False, 4), (1, 5, 20, 32, 16, False, 16)])
+                                                 (1, 12, 40, 64, 64, False, 4), (1, 5, 20, 32, 16, False, 16),
+                                                 (1, 3, 130, 32, 64, True, 2), (2, 4, 128, 64, 32, False, 1),
+                                                 (1, 2, 200, 32, 16, False, 8)])
 def test_conv_forward_exact(N, H, W, Ci, Co, relu, d, cuda):
     import torch
     from paper_2607_01591_amd import cnn
