@@ -193,6 +193,8 @@ def sn_leg(args):
         n_solves = s.info["n_tasks"] * prob.n_groups
         out[prec] = {"local_solves_per_sweep": n_solves, "solves_per_s": n_solves / (sw * 1e-3),
                      "ms_per_iteration": ms, "sweep_ms": sw, "levels": s.info["n_levels"],
+                     # one dependent launch per level: the sweep is bound by the per-level latency
+                     "bound": "latency", "us_per_level": sw * 1e3 / max(1, s.info["n_levels"]),
                      "slots": s.info["n_slots"], "tasks": s.info["n_tasks"],
                      "device_GiB": s.info["device_bytes"] / 2**30, "k_after": r["k"]}
         log(f"DFEM-SN {prec}: {ms:.2f} ms/iteration, sweep {sw:.2f} ms, {n_solves / (sw * 1e-3):.3e} solves/s, "
