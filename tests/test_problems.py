@@ -67,3 +67,32 @@ def test_pincell_regions_symmetric():
     A = p.region_areas()
     np.testing.assert_allclose(A[[0, 2, 4, 4, 4]], A[[1, 3, 5, 6, 7]], rtol=1e-12)
     assert abs(A[:4].sum() - math.pi * 0.54 ** 2) < 1e-12
+
+
+def test_brick_core_layout():
+    """The 51 x 51 x 32 HFEM core: pin-cell nodes of 1.26 cm, fuel in the first 34 x 34
+    pins below 64.26 cm (guide tubes at 25 positions per assembly), moderator elsewhere,
+    reflective on the three low sides, every node with its own cross sections within 2 %
+    of its material's."""
+    g = P.brick_core()
+    nx, ny, nz = (len(e) - 1 for e in g.edges)
+    assert (nx, ny, nz) == (51, 51, 32) and g.n_nodes == 51 * 51 * 32 and g.n_groups == 7
+    assert np.allclose(np.diff(g.edges[0]), 1.26) and np.isclose(g.edges[2][-1], 85.68)
+    assert g.bc == (P.BC_REFLECTIVE, P.BC_VACUUM, P.BC_REFLECTIVE, P.BC_VACUUM, P.BC_REFLECTIVE, P.BC_VACUUM)
+    fiss = (g.nu_sigma_f.sum(axis=1) > 0).reshape(nz, ny, nx)
+    zc = 0.5 * (g.edges[2][:-1] + g.edges[2][1:])
+    assert not fiss[:, :, 34:].any() and not fiss[:, 34:, :].any() and not fiss[zc > 64.26].any()
+    per_asm = fiss[0, :17, :17]
+    assert per_asm.sum() == 17 * 17 - 25
+    assert len(np.unique(g.node_material)) == g.n_nodes
+    # removal stays positive, and the per-node factors stay within the stated 2 %
+    assert (g.sigma_t - np.einsum("mgg->mg", g.sigma_s) > 0).all()
+    ratio = g.sigma_s.sum(axis=2) / g.sigma_t
+    assert (ratio > 0.29).all() and (ratio < 0.96).all()
+
+
+def test_brick_box_edges_and_materials():
+    g = P.brick_box(4, 3, 5, G=2, n_fuel=1, n_other=2, seed=9, size=(2.0, 3.0, 4.0))
+    for e, L in zip(g.edges, (2.0, 3.0, 4.0)):
+        assert e[0] == 0.0 and np.isclose(e[-1], L) and (np.diff(e) > 0).all()
+    assert g.node_material.shape == (60,) and g.node_material.max() < 3 and g.sigma_t.shape == (3, 2)
