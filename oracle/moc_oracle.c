@@ -64,6 +64,7 @@ typedef struct {
     double *qext;          /* optional external source [R][G] (emission density) */
     int gs_boundary;       /* 1: boundary Gauss-Seidel inside a sweep */
     int gs_energy;         /* 1: energy Gauss-Seidel inside a power iteration */
+    int nthreads;          /* threads of the track loop (1 = serial) */
     double max_gap;        /* largest uncovered gap found while tracking (diagnostic) */
     /* coarse mesh for CMFD (off when n_cells == 0): surface partial currents */
     int n_cells;
@@ -74,6 +75,9 @@ typedef struct {
     double *jin_bnd;       /* [n_cells][G] partial current entering the cell from outside */
     char err[256];
 } orc_t;
+
+static int g_default_threads = 1;   /* threads of contexts created from now on */
+void orc_set_default_threads(int n) { g_default_threads = n > 0 ? n : 1; }
 
 static void *xmalloc(size_t n) {
     void *p = calloc(n ? n : 1, 1);
@@ -219,6 +223,80 @@ static int cmp_cidx(const void *a, const void *b) {
 /* n . x with n = (-sin phi, cos phi). Pinned by: every track's piece lengths sum  */
 /* to its chord, sum of volumes = W*H, agreement with an independent walker.       */
 /* ------------------------------------------------------------------------------ */
+/* Segments of the tracks [tfirst, tlast) of angle a: clip every track of the angle   */
+/* against every triangle whose projection it crosses, order the pieces along each    */
+/* track, drop pieces shorter than 1e-12 cm, then merge consecutive pieces of the same */
+/* region. Output: per-track offsets (relative), regions, lengths, the largest gap.    */
+typedef struct { int64_t n; int64_t *off; int *reg; double *len; double max_gap; } angle_segs_t;
+
+static void trace_angle(const orc_t *o, int a, int tfirst, int tlast, angle_segs_t *out) {
+    int nta = tlast - tfirst;
+    double ph = o->phi[a], ux = cos(ph), uy = sin(ph);
+    double nxn = -uy, nyn = ux;
+    double *c = xmalloc(sizeof(double) * (nta ? nta : 1));
+    for (int k = 0; k < nta; k++) c[k] = nxn * o->t_x0[tfirst + k] + nyn * o->t_y0[tfirst + k];
+    int64_t cap = 1 << 16, np = 0;
+    piece_t *pc = xmalloc(sizeof(piece_t) * cap);
+    for (int e = 0; e < o->nt; e++) {
+        const int *v = o->tri + 3 * e;
+        double px[3], py[3], pmin = 1e300, pmax = -1e300;
+        for (int q = 0; q < 3; q++) {
+            px[q] = o->xy[2 * v[q]]; py[q] = o->xy[2 * v[q] + 1];
+            double pr = nxn * px[q] + nyn * py[q];
+            if (pr < pmin) pmin = pr;
+            if (pr > pmax) pmax = pr;
+        }
+        /* triangle half-planes (CCW => inward normal of edge (p,q) is (-(qy-py), qx-px)) */
+        double ex[3], ey[3], ec[3];
+        for (int q = 0; q < 3; q++) {
+            int r = (q + 1) % 3;
+            ex[q] = -(py[r] - py[q]); ey[q] = px[r] - px[q];
+            ec[q] = ex[q] * px[q] + ey[q] * py[q];
+        }
+        /* first track with c > pmin */
+        int lo = 0, hi = nta;
+        while (lo < hi) { int mid = (lo + hi) / 2; if (c[mid] <= pmin) lo = mid + 1; else hi = mid; }
+        for (int k = lo; k < nta && c[k] < pmax; k++) {
+            int t = tfirst + k;
+            double s0, s1;
+            if (!clip_convex(o->t_x0[t], o->t_y0[t], ux, uy, 3, ex, ey, ec, &s0, &s1)) continue;
+            if (np == cap) { cap *= 2; pc = realloc(pc, sizeof(piece_t) * cap); if (!pc) abort(); }
+            pc[np].trk = t; pc[np].s0 = s0; pc[np].s1 = s1; pc[np].reg = o->tri_region[e];
+            np++;
+        }
+    }
+    free(c);
+    qsort(pc, np, sizeof(piece_t), cmp_piece);
+    int64_t scap = np > 0 ? np : 1, S = 0;
+    int *sreg = xmalloc(sizeof(int) * scap);
+    double *slen = xmalloc(sizeof(double) * scap);
+    int64_t *off = xmalloc(sizeof(int64_t) * (nta ? nta : 1));
+    double max_gap = 0.0;
+    int64_t i = 0;
+    for (int t = tfirst; t < tlast; t++) {
+        off[t - tfirst] = S;
+        double last_end = 0.0;
+        int prev = -1;
+        for (; i < np && pc[i].trk == t; i++) {
+            double L = pc[i].s1 - pc[i].s0;
+            if (L < 1e-12) continue;            /* drop first ... */
+            double g = pc[i].s0 - last_end;     /* pieces must tile the chord */
+            if (fabs(g) > max_gap) max_gap = fabs(g);
+            if (pc[i].s1 > last_end) last_end = pc[i].s1;
+            if (prev == pc[i].reg) {             /* ... then merge */
+                slen[S - 1] += L;
+                continue;
+            }
+            sreg[S] = pc[i].reg; slen[S] = L; S++;
+            prev = pc[i].reg;
+        }
+        double g = o->t_len[t] - last_end;
+        if (fabs(g) > max_gap) max_gap = fabs(g);
+    }
+    free(pc);
+    out->n = S; out->off = off; out->reg = sreg; out->len = slen; out->max_gap = max_gap;
+}
+
 static int trace(orc_t *o) {
     double W = o->box[2] - o->box[0], H = o->box[3] - o->box[1];
     int NA = o->NA;
@@ -272,85 +350,40 @@ static int trace(orc_t *o) {
     free(ci);
     o->T = T;
 
-    /* pieces, angle by angle */
-    int64_t cap = 1 << 20, np = 0;
-    piece_t *pc = xmalloc(sizeof(piece_t) * cap);
-    int64_t scap = 1 << 20, S = 0;
-    int *sreg = xmalloc(sizeof(int) * scap);
-    double *slen = xmalloc(sizeof(double) * scap);
+    /* pieces, angle by angle; the angles are independent, so they may run on several   */
+    /* threads (each angle's segments in arrays of its own, joined in angle order after) */
     o->t_off = xmalloc(sizeof(int64_t) * (T + 1));
     o->max_gap = 0.0;
-    int tfirst = 0;
+    int *afirst = xmalloc(sizeof(int) * (NA + 1));
+    {
+        int t = 0;
+        for (int a = 0; a < NA; a++) {
+            afirst[a] = t;
+            while (t < T && o->t_angle[t] == a) t++;
+        }
+        afirst[NA] = T;
+    }
+    angle_segs_t *as = xmalloc(sizeof(angle_segs_t) * (NA ? NA : 1));
+    int nth = o->nthreads > 0 ? o->nthreads : 1;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nth) schedule(dynamic, 1)
+#endif
+    for (int a = 0; a < NA; a++) trace_angle(o, a, afirst[a], afirst[a + 1], &as[a]);
+    int64_t S = 0;
+    for (int a = 0; a < NA; a++) S += as[a].n;
+    int *sreg = xmalloc(sizeof(int) * (S ? S : 1));
+    double *slen = xmalloc(sizeof(double) * (S ? S : 1));
+    int64_t pos = 0;
     for (int a = 0; a < NA; a++) {
-        int tlast = tfirst;
-        while (tlast < T && o->t_angle[tlast] == a) tlast++;
-        int nta = tlast - tfirst;
-        double ph = o->phi[a], ux = cos(ph), uy = sin(ph);
-        double nxn = -uy, nyn = ux;
-        double *c = xmalloc(sizeof(double) * (nta ? nta : 1));
-        for (int k = 0; k < nta; k++) c[k] = nxn * o->t_x0[tfirst + k] + nyn * o->t_y0[tfirst + k];
-        np = 0;
-        for (int e = 0; e < o->nt; e++) {
-            const int *v = o->tri + 3 * e;
-            double px[3], py[3], pmin = 1e300, pmax = -1e300;
-            for (int q = 0; q < 3; q++) {
-                px[q] = o->xy[2 * v[q]]; py[q] = o->xy[2 * v[q] + 1];
-                double pr = nxn * px[q] + nyn * py[q];
-                if (pr < pmin) pmin = pr;
-                if (pr > pmax) pmax = pr;
-            }
-            /* triangle half-planes (CCW => inward normal of edge (p,q) is (-(qy-py), qx-px)) */
-            double ex[3], ey[3], ec[3];
-            for (int q = 0; q < 3; q++) {
-                int r = (q + 1) % 3;
-                ex[q] = -(py[r] - py[q]); ey[q] = px[r] - px[q];
-                ec[q] = ex[q] * px[q] + ey[q] * py[q];
-            }
-            /* first track with c > pmin */
-            int lo = 0, hi = nta;
-            while (lo < hi) { int mid = (lo + hi) / 2; if (c[mid] <= pmin) lo = mid + 1; else hi = mid; }
-            for (int k = lo; k < nta && c[k] < pmax; k++) {
-                int t = tfirst + k;
-                double s0, s1;
-                if (!clip_convex(o->t_x0[t], o->t_y0[t], ux, uy, 3, ex, ey, ec, &s0, &s1)) continue;
-                if (np == cap) { cap *= 2; pc = realloc(pc, sizeof(piece_t) * cap); if (!pc) abort(); }
-                pc[np].trk = t; pc[np].s0 = s0; pc[np].s1 = s1; pc[np].reg = o->tri_region[e];
-                np++;
-            }
-        }
-        free(c);
-        qsort(pc, np, sizeof(piece_t), cmp_piece);
-        int64_t i = 0;
-        for (int t = tfirst; t < tlast; t++) {
-            o->t_off[t] = S;
-            double last_end = 0.0;
-            int prev = -1;
-            for (; i < np && pc[i].trk == t; i++) {
-                double L = pc[i].s1 - pc[i].s0;
-                if (L < 1e-12) continue;            /* drop first ... */
-                double g = pc[i].s0 - last_end;     /* pieces must tile the chord */
-                if (fabs(g) > o->max_gap) o->max_gap = fabs(g);
-                if (pc[i].s1 > last_end) last_end = pc[i].s1;
-                if (prev == pc[i].reg) {             /* ... then merge */
-                    slen[S - 1] += L;
-                    continue;
-                }
-                if (S == scap) {
-                    scap *= 2;
-                    sreg = realloc(sreg, sizeof(int) * scap);
-                    slen = realloc(slen, sizeof(double) * scap);
-                    if (!sreg || !slen) abort();
-                }
-                sreg[S] = pc[i].reg; slen[S] = L; S++;
-                prev = pc[i].reg;
-            }
-            double g = o->t_len[t] - last_end;
-            if (fabs(g) > o->max_gap) o->max_gap = fabs(g);
-        }
-        tfirst = tlast;
+        for (int t = afirst[a]; t < afirst[a + 1]; t++) o->t_off[t] = pos + as[a].off[t - afirst[a]];
+        memcpy(sreg + pos, as[a].reg, sizeof(int) * as[a].n);
+        memcpy(slen + pos, as[a].len, sizeof(double) * as[a].n);
+        pos += as[a].n;
+        if (as[a].max_gap > o->max_gap) o->max_gap = as[a].max_gap;
+        free(as[a].off); free(as[a].reg); free(as[a].len);
     }
     o->t_off[T] = S;
-    free(pc);
+    free(as); free(afirst);
     o->s_reg = sreg; o->s_len = slen; o->S = S;
     return 0;
 }
@@ -464,6 +497,7 @@ orc_t *orc_create(int nv, const double *xy, int nt, const int *tri, const int *t
     o->nsf = xmalloc(sizeof(double) * M * G); memcpy(o->nsf, nsf, sizeof(double) * M * G);
     o->chi = xmalloc(sizeof(double) * M * G); memcpy(o->chi, chi, sizeof(double) * M * G);
     o->A = A; o->P = P; o->NA = A / 2; o->spacing = spacing;
+    o->nthreads = g_default_threads;
     int NA = A / 2;
     o->phi = xmalloc(sizeof(double) * NA); o->dlt = xmalloc(sizeof(double) * NA);
     o->wa = xmalloc(sizeof(double) * NA);
@@ -564,10 +598,13 @@ static int64_t coarse_slot(const orc_t *o, int i, int j) {
     return -1;   /* cannot happen: the adjacency was built from these same segments */
 }
 
-static void sweep_group(orc_t *o, int g, const double *qhat_g /* [R] */, double *T_g /* [R] */) {
+/* The tracks [t0, t1) of one group sweep, tallied into T_g (and, with a coarse mesh, */
+/* the partial currents into jpart [slots][G] and jin [cells][G]).                  */
+static void sweep_tracks(orc_t *o, int g, const double *qhat_g, double *T_g, double *jpart, double *jin,
+                         int t0, int t1) {
     int P = o->P, G = o->G;
     const int *cell = o->region_cell;
-    for (int t = 0; t < o->T; t++) {
+    for (int t = t0; t < t1; t++) {
         int a = o->t_angle[t];
         for (int sense = 0; sense < 2; sense++) {
             for (int p = 0; p < P; p++) {
@@ -583,8 +620,8 @@ static void sweep_group(orc_t *o, int g, const double *qhat_g /* [R] */, double 
                         /* a coarse-cell boundary crossed with the current psi: the same   */
                         /* weight c turns angular flux into current as Delta into tally    */
                         int ci = cell[r];
-                        if (i == 0) o->jin_bnd[(size_t)ci * G + g] += c * psi;
-                        else if (ci != cprev) o->jpart[coarse_slot(o, cprev, ci) * G + g] += c * psi;
+                        if (i == 0) jin[(size_t)ci * G + g] += c * psi;
+                        else if (ci != cprev) jpart[coarse_slot(o, cprev, ci) * G + g] += c * psi;
                         cprev = ci;
                     }
                     double st = o->sigt[o->region_material[r] * G + g];
@@ -593,7 +630,7 @@ static void sweep_group(orc_t *o, int g, const double *qhat_g /* [R] */, double 
                     psi -= delta;
                     T_g[r] += c * delta;
                 }
-                if (o->n_cells && n > 0) o->jpart[coarse_slot(o, cprev, -1) * G + g] += c * psi;
+                if (o->n_cells && n > 0) jpart[coarse_slot(o, cprev, -1) * G + g] += c * psi;
                 o->psi_exit[idx] = psi;
                 int dst = o->link[2 * t + sense];
                 if (dst >= 0) {
@@ -604,6 +641,61 @@ static void sweep_group(orc_t *o, int g, const double *qhat_g /* [R] */, double 
             }
         }
     }
+}
+
+/* Threads (a timing convenience; the arithmetic of every track is unchanged). With   */
+/* Jacobi boundary updates the tracks of a sweep are independent: thread i takes the  */
+/* contiguous track range [i T/n, (i+1) T/n), tallies into private arrays, and the    */
+/* arrays are added in thread order afterwards, so a run is reproducible for a given  */
+/* thread count, and with one thread every sum is formed in the serial order.         */
+/* Boundary Gauss-Seidel runs on one thread.                                          */
+int orc_set_threads(orc_t *o, int n) {
+    o->nthreads = n > 0 ? n : 1;
+#ifdef _OPENMP
+    return 1;
+#else
+    return 0;
+#endif
+}
+
+static void sweep_group(orc_t *o, int g, const double *qhat_g /* [R] */, double *T_g /* [R] */) {
+    int nth = o->nthreads;
+    if (nth <= 1 || o->gs_boundary || o->T < 2 * nth) {
+        sweep_tracks(o, g, qhat_g, T_g, o->jpart, o->jin_bnd, 0, o->T);
+        return;
+    }
+    int R = o->R, G = o->G;
+    size_t nj = o->n_cells ? (size_t)o->nbr_off[o->n_cells] * G : 0;
+    size_t ni = o->n_cells ? (size_t)o->n_cells * G : 0;
+    size_t per = (size_t)R + nj + ni;
+    double *priv = xmalloc(sizeof(double) * per * nth);
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nth) schedule(static, 1)
+#endif
+    for (int i = 0; i < nth; i++) {
+        int t0 = (int)((int64_t)o->T * i / nth), t1 = (int)((int64_t)o->T * (i + 1) / nth);
+        double *b = priv + per * i;
+        sweep_tracks(o, g, qhat_g, b, b + R, b + R + nj, t0, t1);
+    }
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nth) schedule(static)
+#endif
+    for (int r = 0; r < R; r++) {
+        double v = T_g[r];
+        for (int i = 0; i < nth; i++) v += priv[per * i + r];
+        T_g[r] = v;
+    }
+    for (size_t e = 0; e < nj; e++) {
+        double v = o->jpart[e];
+        for (int i = 0; i < nth; i++) v += priv[per * i + R + e];
+        o->jpart[e] = v;
+    }
+    for (size_t e = 0; e < ni; e++) {
+        double v = o->jin_bnd[e];
+        for (int i = 0; i < nth; i++) v += priv[per * i + R + nj + e];
+        o->jin_bnd[e] = v;
+    }
+    free(priv);
 }
 
 static double sigt_of(const orc_t *o, int r, int g) { return o->sigt[o->region_material[r] * o->G + g]; }

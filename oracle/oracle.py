@@ -18,24 +18,33 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "moc_oracle.c")
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C11, -O2, no fast-math)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _SO)
-    return _SO
+def build(force: bool = False, native: bool = False, out: str | None = None) -> str:
+    """Compile the oracle with gcc: plain C11, -O3, OpenMP for the track loop, no
+    fast-math. ``native`` adds -march=native for timing on the machine that runs it (the
+    default build is portable, since the library may run on another host than the one
+    that built it); ``out`` names the library file (default: liboracle.so here)."""
+    so = out or _SO
+    if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(_SRC):
+        tmp = so + ".tmp"
+        flags = ["-O3", "-std=c11", "-Wall", "-fPIC", "-shared", "-fopenmp"]
+        if native:
+            flags.append("-march=native")
+        subprocess.check_call(["gcc"] + flags + ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, so)
+    return so
 
 
 _lib = None
 
 
-def lib():
+def lib(path: str | None = None):
+    """The oracle library (built here on first use); ``path`` loads another build of the
+    same source instead (the benchmark's -march=native copy), before any other use."""
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_SO)
+        if path is None:
+            build()
+        L = C.CDLL(path or _SO)
         P = C.POINTER
         d, i, i64 = C.c_double, C.c_int, C.c_int64
         L.orc_create.restype = C.c_void_p
@@ -54,6 +63,9 @@ def lib():
         L.orc_set_psi.argtypes = [C.c_void_p, P(d)]
         L.orc_get_exit_psi.argtypes = [C.c_void_p, P(d)]
         L.orc_set_options.argtypes = [C.c_void_p, i, i]
+        L.orc_set_threads.restype = i
+        L.orc_set_default_threads.argtypes = [i]
+        L.orc_set_threads.argtypes = [C.c_void_p, i]
         L.orc_set_external_source.argtypes = [C.c_void_p, P(d)]
         L.orc_sweep.argtypes = [C.c_void_p, P(d), P(d), P(d)]
         L.orc_set_coarse.restype = i
@@ -105,8 +117,10 @@ class Oracle:
     """
 
     def __init__(self, xy, tri, tri_region, n_regions, region_material, domain, box,
-                 hex_apothem, bc, sigma_t, sigma_s, nu_sigma_f, chi, n_azim, n_polar, spacing):
+                 hex_apothem, bc, sigma_t, sigma_s, nu_sigma_f, chi, n_azim, n_polar, spacing,
+                 threads: int = 1):
         L = lib()
+        L.orc_set_default_threads(int(threads))   # tracking and sweeps of this context
         self._keep = [_f64(xy), _i32(tri), _i32(tri_region), _i32(region_material),
                       _f64(box), _i32(bc), _f64(sigma_t), _f64(sigma_s), _f64(nu_sigma_f),
                       _f64(chi)]
@@ -133,10 +147,10 @@ class Oracle:
         self.region_material = rm
 
     @classmethod
-    def from_problem(cls, p):
+    def from_problem(cls, p, threads: int = 1):
         return cls(p.xy, p.tri, p.tri_region, p.n_regions, p.region_material, p.domain,
                    p.box, p.hex_apothem, p.bc, p.sigma_t, p.sigma_s, p.nu_sigma_f, p.chi,
-                   p.n_azim, p.n_polar, p.spacing)
+                   p.n_azim, p.n_polar, p.spacing, threads=threads)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -200,6 +214,11 @@ class Oracle:
 
     def set_options(self, gs_boundary=False, gs_energy=False):
         lib().orc_set_options(self._h, int(gs_boundary), int(gs_energy))
+
+    def set_threads(self, n: int) -> bool:
+        """Threads of the sweep's track loop (1 = serial, the default). Returns whether the
+        library was built with OpenMP."""
+        return bool(lib().orc_set_threads(self._h, int(n)))
 
     def set_external_source(self, q):
         if q is None:

@@ -327,3 +327,43 @@ def test_links_are_geometric_reflections():
             refl = np.array([-d[0], d[1]]) if side < 2 else np.array([d[0], -d[1]])
             np.testing.assert_allclose(d2, refl, atol=1e-12)
     assert n_linked > 0
+
+
+# ---------------------------------------------------------------- threads
+def test_threads_change_nothing_but_summation_order():
+    """The threaded track loop and tracker (a timing convenience) give the serial answer:
+    tracking is identical, one sweep's flux, exit flux and coarse currents agree to 1e-12,
+    a short power iteration agrees to 1e-12, and one thread reproduces the serial sums."""
+    prob = P.square_lattice(4, 3, seed=31, n_azim=32, spacing=0.03, bc=(1, 0, 1, 0))
+    o1 = Oracle.from_problem(prob, threads=1)
+    o4 = Oracle.from_problem(prob, threads=4)
+    r1, l1 = o1.segments()
+    r4, l4 = o4.segments()
+    assert np.array_equal(r1, r4) and np.array_equal(l1, l4)
+    assert np.array_equal(o1.volumes(), o4.volumes())
+    assert o4.set_threads(4), "oracle built without OpenMP"
+    rng = np.random.default_rng(5)
+    src = rng.uniform(0.1, 2.0, size=(o1.R, o1.G))
+    psi0 = rng.uniform(0.0, 1.0, size=o1.psi_shape())
+    n_cells, cells = P.coarse_cells(prob, 4, 3)   # coarse currents too
+    out = []
+    for o in (o1, o4):
+        o.set_coarse(n_cells, cells)
+        o.set_psi(psi0)
+        phi, T = o.sweep(src, return_tally=True)
+        jp, jin = o.currents()
+        out.append((phi, T, o.get_exit_psi(), o.get_psi(), jp, jin))
+    for a, b in zip(*out):
+        np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-14 * np.abs(a).max())
+    # one thread: the very same sums as the serial loop (bit for bit)
+    o4.set_threads(1)
+    o4.set_psi(psi0)
+    phi1, T1 = o4.sweep(src, return_tally=True)
+    assert np.array_equal(phi1, out[0][0]) and np.array_equal(T1, out[0][1])
+    # a short power iteration
+    o1b = Oracle.from_problem(prob, threads=1)
+    o4b = Oracle.from_problem(prob, threads=4)
+    ra = o1b.solve(tol=1e-30, max_iter=25)
+    rb = o4b.solve(tol=1e-30, max_iter=25)
+    assert abs(ra["k"] - rb["k"]) < 1e-12
+    np.testing.assert_allclose(rb["phi"], ra["phi"], rtol=1e-12)
