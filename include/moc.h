@@ -52,10 +52,17 @@ extern "C" {
 #define MOC_PREC_F32 0   /* FP32 sweep; FP64 source, eigenvalue, norms and tallies */
 #define MOC_PREC_F64 1   /* FP64 everywhere (same kernels instantiated in double) */
 
-/* evaluation of 1 - exp(-tau) in the FP32 sweep (the FP64 sweep always uses expm1) */
-#define MOC_EXP_POLY 0   /* hardware exp2 for large tau, Taylor polynomial for small tau */
+/* evaluation of the segment update of Eq. MOC_sol in the FP32 sweep (the FP64 sweep
+ * always forms (psi - qhat)(1 - e^-tau) with expm1) */
+#define MOC_EXP_DIFF 0   /* default: e = e^-tau from the hardware exponential (within 0.8 units
+                            in the last place on gfx950) and the increment t (1 - e), t = psi -
+                            qhat, as one fused multiply-add t - t e: a single rounding, so the
+                            increment's only other error is the exponential's absolute error */
 #define MOC_EXP_TABLE 1  /* linear interpolation in a table of (1 - e^-x)/x */
 #define MOC_EXP_LIBM 2   /* device libm expm1f */
+#define MOC_EXP_POLY 3   /* 1 - e^-tau as the larger of two lower bounds: a degree-4 Taylor
+                            polynomial and the hardware exponential lowered by 4 units in the
+                            last place (relative error <= 2.7e-6) */
 
 /* moc_result.flags */
 #define MOC_FLAG_FELL_BACK_TO_COLD 1  /* the initial guess was rejected; cold start used */

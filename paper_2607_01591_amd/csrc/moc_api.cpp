@@ -130,12 +130,12 @@ void moc::create_context(const moc_mesh *mesh_in, const moc_tracks *tr_in, const
     if (!mesh_in || !tr_in || !xs) throw Error(MOC_EINVAL, "create: null argument");
     moc_options o{};
     o.precision = MOC_PREC_F32;
-    o.exp_mode = MOC_EXP_POLY;
+    o.exp_mode = MOC_EXP_DIFF;
     if (opt) o = *opt;
     if (o.tally_slots != 0 && (o.tally_slots < kBatch || o.tally_slots > kMaxSlots))
         throw Error(MOC_EINVAL, "options: tally_slots must be 0 or in 64..256");
     if (o.precision != MOC_PREC_F32 && o.precision != MOC_PREC_F64) throw Error(MOC_EINVAL, "options: bad precision");
-    if (o.exp_mode < MOC_EXP_POLY || o.exp_mode > MOC_EXP_LIBM) throw Error(MOC_EINVAL, "options: bad exp_mode");
+    if (o.exp_mode < MOC_EXP_DIFF || o.exp_mode > MOC_EXP_POLY) throw Error(MOC_EINVAL, "options: bad exp_mode");
     c->max_iter = o.max_iter > 0 ? o.max_iter : 10000;
     c->check_every = o.check_every > 0 ? o.check_every : 1;
     c->n_threads = o.n_threads > 0 ? o.n_threads : std::max(1u, std::thread::hardware_concurrency());
@@ -729,8 +729,8 @@ static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell,
     if (opts) o = *opts;
     if (o.tol < 0 || o.max_outer < 0 || o.max_inner < 0) throw Error(MOC_EINVAL, "coarse mesh: negative option");
     if (o.coarse_blocks < 0 || o.coarse_blocks > 256) throw Error(MOC_EINVAL, "coarse mesh: coarse_blocks must be in 0..256");
-    if (d.precision == MOC_PREC_F32 && d.exp_mode != MOC_EXP_POLY)
-        throw Error(MOC_EINVAL, "coarse mesh: CMFD currents need the default exponential (exp_mode 0)");
+    if (d.precision == MOC_PREC_F32 && d.exp_mode != MOC_EXP_POLY && d.exp_mode != MOC_EXP_DIFF)
+        throw Error(MOC_EINVAL, "coarse mesh: CMFD currents need exp_mode MOC_EXP_DIFF or MOC_EXP_POLY");
     std::vector<int64_t> count(n_cells, 0);
     for (int u = 0; u < R; ++u) {
         if (region_cell[u] < 0 || region_cell[u] >= n_cells) throw Error(MOC_EINVAL, "coarse mesh: cell index out of range");

@@ -47,7 +47,7 @@ struct SweepArgs {
 struct DevProblem {
     int R = 0, G = 0, Gp = 0, M = 0, P = 0, NA = 0, T = 0;
     int nb = 0, nslots = 0, gb = 1, n_gb = 1;
-    int precision = MOC_PREC_F32, exp_mode = MOC_EXP_POLY;
+    int precision = MOC_PREC_F32, exp_mode = MOC_EXP_DIFF;
     // per material, FP64
     double *sigt_m = nullptr, *sigs_m = nullptr, *nsf_m = nullptr, *chi_m = nullptr;
     // per internal region

@@ -100,7 +100,8 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
 
     // per polar angle: tally weight, and the factor turning Sigma_t l into the exponent
     // argument (tau = Sigma_t l / sin(theta), or x = -tau log2(e) for the POLY mode)
-    constexpr bool kX = sizeof(Real) == 4 && MODE == MOC_EXP_POLY;
+    constexpr bool kDiff = sizeof(Real) == 4 && MODE == MOC_EXP_DIFF;
+    constexpr bool kX = sizeof(Real) == 4 && (MODE == MOC_EXP_POLY || kDiff);
     Real c[NP], is[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -198,6 +199,21 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
                 acc[j] = 0;
 #pragma unroll
                 for (int p = 0; p < NP; ++p) {
+                    if constexpr (kDiff) {
+                        // e = e^-tau from the hardware exponential; the increment
+                        // t (1 - e) with t = psi - qhat is formed by one fused multiply-add
+                        // (t - t e, a single rounding), so its only error beyond that
+                        // rounding is the absolute error of e
+                        const Real e = __builtin_amdgcn_exp2f(st[j] * lp[p]);
+                        const Real t = psi[p][j] - q[j];
+                        const Real d = __builtin_fmaf(-t, e, t);
+                        if constexpr (CUR)
+                            psi[p][j] -= keep * d;
+                        else
+                            psi[p][j] -= d;
+                        acc[j] += cw[p] * d;
+                        continue;
+                    }
                     Real F;
                     if constexpr (kX)
                         F = one_minus_exp2_poly(st[j] * lp[p]);
@@ -631,16 +647,20 @@ void launch_sweep(const SweepArgs &a, int precision, int exp_mode, bool currents
             ok = sweep_np<double, MOC_EXP_POLY, true>(a, nb, np, gb, n_gb, s);
         else if (exp_mode == MOC_EXP_POLY)
             ok = sweep_np<float, MOC_EXP_POLY, true>(a, nb, np, gb, n_gb, s);
+        else if (exp_mode == MOC_EXP_DIFF)
+            ok = sweep_np<float, MOC_EXP_DIFF, true>(a, nb, np, gb, n_gb, s);
         else
-            throw Error(MOC_EINVAL, "sweep: coarse-surface currents need the default exponential (exp_mode 0)");
+            throw Error(MOC_EINVAL, "sweep: coarse-surface currents need MOC_EXP_DIFF or MOC_EXP_POLY");
     } else if (precision == MOC_PREC_F64) {
         ok = sweep_np<double, MOC_EXP_POLY, false>(a, nb, np, gb, n_gb, s);
     } else if (exp_mode == MOC_EXP_TABLE) {
         ok = sweep_np<float, MOC_EXP_TABLE, false>(a, nb, np, gb, n_gb, s);
     } else if (exp_mode == MOC_EXP_LIBM) {
         ok = sweep_np<float, MOC_EXP_LIBM, false>(a, nb, np, gb, n_gb, s);
-    } else {
+    } else if (exp_mode == MOC_EXP_POLY) {
         ok = sweep_np<float, MOC_EXP_POLY, false>(a, nb, np, gb, n_gb, s);
+    } else {
+        ok = sweep_np<float, MOC_EXP_DIFF, false>(a, nb, np, gb, n_gb, s);
     }
     if (!ok) throw Error(MOC_EINVAL, "sweep: no kernel instance for this polar count / group batch");
     MOC_CHECK_LAUNCH();

@@ -15,12 +15,12 @@ C_SRC = os.path.join(ROOT, "oracle", "moc_oracle.c")
 PY_SRC = os.path.join(ROOT, "oracle", "cmfd_oracle.py")
 
 C_MUTANTS = {
-    "entry_current_unweighted": ("o->jin_bnd[(size_t)ci * G + g] += c * psi;", "o->jin_bnd[(size_t)ci * G + g] += psi;"),
-    "crossing_current_unweighted": ("o->jpart[coarse_slot(o, cprev, ci) * G + g] += c * psi;",
-                                    "o->jpart[coarse_slot(o, cprev, ci) * G + g] += psi;"),
-    "crossing_reversed": ("o->jpart[coarse_slot(o, cprev, ci) * G + g] += c * psi;",
-                          "o->jpart[coarse_slot(o, ci, cprev) * G + g] += c * psi;"),
-    "exit_current_dropped": ("if (o->n_cells && n > 0) o->jpart", "if (0) o->jpart"),
+    "entry_current_unweighted": ("if (i == 0) jin[(size_t)ci * G + g] += c * psi;", "if (i == 0) jin[(size_t)ci * G + g] += psi;"),
+    "crossing_current_unweighted": ("else if (ci != cprev) jpart[coarse_slot(o, cprev, ci) * G + g] += c * psi;",
+                                    "else if (ci != cprev) jpart[coarse_slot(o, cprev, ci) * G + g] += psi;"),
+    "crossing_reversed": ("else if (ci != cprev) jpart[coarse_slot(o, cprev, ci) * G + g] += c * psi;",
+                          "else if (ci != cprev) jpart[coarse_slot(o, ci, cprev) * G + g] += c * psi;"),
+    "exit_current_dropped": ("if (o->n_cells && n > 0) jpart", "if (0) jpart"),
 }
 
 PY_MUTANTS = {

@@ -209,7 +209,7 @@ def test_initial_guess_and_fallback(oracle_solutions, cuda):
         assert abs(r["iterations"] - cold["iterations"]) <= 1
 
 
-@pytest.mark.parametrize("exp_mode", ["table", "libm"])
+@pytest.mark.parametrize("exp_mode", ["poly", "table", "libm"])
 def test_exp_modes_sweep_parity(exp_mode, cuda):
     log(f"[sweep parity] exp mode {exp_mode}")
     prob = P.square_lattice(3, 2, seed=3, n_azim=32, spacing=0.05, bc=(1, 0, 1, 0))
