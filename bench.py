@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=3, help="problem recipe (3 = 51x51 lattice)")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle on the hexagon, the whole 51x51 lattice and to 1e-6 on the 17x17 lattice")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-hex", action="store_true")
     ap.add_argument("--solve-seeds", type=int, default=3)
@@ -120,33 +122,111 @@ def algorithmic_bytes(info, precision):
     return seg + xs + tally + psi
 
 
-def cpu_baseline(workload):
-    """The FP64 oracle, single-threaded, timed on a bounded sample of the workload: the
-    same pin-cell template, track spacing and quadrature on a 6 x 6 pin window."""
+def host_cpus():
+    """Sockets, physical cores and logical CPUs of the host (/proc/cpuinfo), and the CPUs
+    this process may run on (its affinity mask)."""
+    sockets, cores, logical = set(), set(), 0
+    phys = core = None
+    with open("/proc/cpuinfo") as f:
+        for line in f.read().splitlines() + [""]:
+            key, _, val = line.partition(":")
+            key = key.strip()
+            if key == "processor":
+                logical += 1
+            elif key == "physical id":
+                phys = val.strip()
+            elif key == "core id":
+                core = val.strip()
+            elif not line.strip() and phys is not None:
+                sockets.add(phys)
+                cores.add((phys, core))
+                phys = core = None
+    allowed = len(os.sched_getaffinity(0))
+    return {"sockets": len(sockets) or 1, "physical_cores": len(cores) or logical, "logical_cpus": logical,
+            "allowed_cpus": allowed}
+
+
+def _oracle_rate(prob, threads, reps):
+    """Median FP64 oracle sweep rate (updates/s) over `reps` sweeps after one warm-up."""
     import numpy as np
     from oracle.oracle import Oracle
-    from paper_2607_01591_amd import problems as P
-    if workload == 3:
-        prob = P.square_lattice(6, 6, seed=3, m=5, n_fuel_rings=5, n_mod_rings=7, n_azim=128,
-                                spacing=0.01, bc=(1, 0, 1, 0), name="cfg3_window6x6")
-        sample = "one FP64 oracle sweep of a 6x6-pin window of the 51x51 lattice (same template, A=128, P=3, 0.01 cm)"
-    else:
-        prob = P.config(workload)
-        sample = f"one FP64 oracle sweep of workload {workload}"
-    o = Oracle.from_problem(prob)
+    o = Oracle.from_problem(prob, threads=threads)
+    o.set_threads(threads)
     src = np.ones((o.R, o.G))
-    o.sweep(src)                      # warm caches
-    t0 = time.perf_counter()
-    n = 0
-    while True:
+    o.sweep(src)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
         o.sweep(src)
-        n += 1
-        if time.perf_counter() - t0 > 8.0:
-            break
-    dt = (time.perf_counter() - t0) / n
+        ts.append(time.perf_counter() - t0)
     U = 2 * o.P * o.G * o.S
-    return {"value": U / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}; {n} sweeps, U={U:.3e} per sweep, {dt:.2f} s per sweep"}
+    return U / float(np.median(ts)), U, float(np.median(ts))
+
+
+def cpu_baseline(workload, full=False):
+    """The FP64 oracle as it stands, built -O3 -march=native (no fast-math) for this host,
+    timed on bounded samples: one thread and all usable physical cores (at most 16, the
+    host share of one GPU), median sweep time after one warm-up. Samples: a 6 x 6 pin window
+    of the 51 x 51 lattice (same pin template, A = 128, P = 3, 0.01 cm: the `value`), the
+    17 x 17 lattice in full, and the oracle's time to a 1e-6 residual on the pin cell.
+    full=True adds the 271-pin hexagon, the whole 51 x 51 lattice (all cores, one sweep) and
+    the time to 1e-6 on the 17 x 17 lattice (minutes)."""
+    import tempfile
+    from oracle import oracle as O
+    from paper_2607_01591_amd import problems as P
+    host = host_cpus()
+    threads = max(1, min(16, host["physical_cores"], host["allowed_cpus"]))
+    so = os.path.join(tempfile.mkdtemp(prefix="oracle_native_"), "liboracle_native.so")
+    O.build(force=True, native=True, out=so)
+    O.lib(so)
+    out = {"kind": "oracle", "unit": "updates/s", "cores": threads, "host": host,
+           "build": "gcc -O3 -march=native -fopenmp (no fast-math)"}
+    win = P.square_lattice(6, 6, seed=3, m=5, n_fuel_rings=5, n_mod_rings=7, n_azim=128, spacing=0.01,
+                           bc=(1, 0, 1, 0), name="cfg3_window6x6")
+    r1, U, t1 = _oracle_rate(win, 1, 3)
+    rn, _, tn = _oracle_rate(win, threads, 5)
+    out.update(value=rn, value_1core=r1, value_allcores=rn,
+               sample=f"FP64 oracle sweeps of a 6x6-pin window of the 51x51 lattice (same template, A=128, P=3, "
+                      f"0.01 cm; U={U:.3e} per sweep): median of 3 on 1 thread ({t1:.2f} s) and of 5 on {threads} "
+                      f"threads ({tn:.2f} s), each after one warm-up")
+    log(f"oracle window: {r1:.3e} updates/s on 1 thread, {rn:.3e} on {threads}")
+    lat = P.config(2)
+    a1, U2, _ = _oracle_rate(lat, 1, 3)
+    an, _, _ = _oracle_rate(lat, threads, 5)
+    out["lattice17x17"] = {"updates_per_sweep": U2, "value_1core": a1, "value_allcores": an}
+    log(f"oracle 17x17: {a1:.3e} updates/s on 1 thread, {an:.3e} on {threads}")
+    pin = P.config(1)
+    o = O.Oracle.from_problem(pin)
+    t0 = time.perf_counter()
+    r = o.solve(tol=1e-6)
+    out["pincell_time_to_1e-6_s"] = time.perf_counter() - t0
+    out["pincell_iterations"] = r["iterations"]
+    if full:
+        hx = P.config(4)
+        h1, U4, _ = _oracle_rate(hx, 1, 1)
+        hn, _, _ = _oracle_rate(hx, threads, 3)
+        out["hexagon_g33"] = {"updates_per_sweep": U4, "value_1core": h1, "value_allcores": hn}
+        log(f"oracle hexagon: {h1:.3e} updates/s on 1 thread, {hn:.3e} on {threads}")
+        o2 = O.Oracle.from_problem(lat, threads=threads)
+        o2.set_threads(threads)
+        t0 = time.perf_counter()
+        r2 = o2.solve(tol=1e-6)
+        out["lattice17x17_time_to_1e-6_s"] = time.perf_counter() - t0
+        out["lattice17x17_iterations"] = r2["iterations"]
+        log(f"oracle 17x17 to 1e-6: {out['lattice17x17_time_to_1e-6_s']:.1f} s, {r2['iterations']} iterations")
+        del o2
+        big = P.config(3)
+        o3 = O.Oracle.from_problem(big, threads=threads)
+        o3.set_threads(threads)
+        import numpy as np
+        src = np.ones((o3.R, o3.G))
+        t0 = time.perf_counter()
+        o3.sweep(src)
+        dt = time.perf_counter() - t0
+        out["lattice51x51"] = {"updates_per_sweep": 2 * o3.P * o3.G * o3.S, "value_allcores": 2 * o3.P * o3.G * o3.S / dt,
+                               "sweep_s": dt}
+        log(f"oracle 51x51: one sweep {dt:.1f} s on {threads} threads")
+    return out
 
 
 def dg_leg(args):
@@ -481,8 +561,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
-        cpu = cpu_baseline(args.workload)
-        log(f"oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} core")
+        cpu = cpu_baseline(args.workload, full=args.cpu_full)
+        log(f"oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
 
     out = {
         "metric": "segment-group updates/s (FP32 sweep power iteration)",

@@ -215,10 +215,16 @@ void moc_destroy(moc_ctx *ctx);
  * sweep's incoming fluxes (reflective sides), so consecutive calls iterate. */
 int moc_sweep(moc_ctx *ctx, const double *source_dev, double *scalar_flux_out_dev, void *stream);
 
-/* Power iteration (or source iteration with an external source) to `tol`: stops when
- * the residual and |dk| are both below tol. Synchronous on the context's stream. Starts
- * from the initial guess if one is set (once), else from phi = 1, k = 1, psi = 0.
- * Returns MOC_ENOCONV at max_iter with `out` filled in. */
+/* Power iteration (or source iteration with an external source) to `tol`: the
+ * k-eigenvalue problem of Eq. MGNTE (Sec. 2; k_eff is the largest eigenvalue, found by
+ * repeated transport sweeps, Sec. 2.1, each applying Eq. MOC_sol to every segment, until
+ * convergence). Each iteration: source from the previous flux (Jacobi in energy),
+ * one sweep, k <- k sum V nuSigma_f phi_new / sum V nuSigma_f phi_old, normalisation to
+ * sum V nuSigma_f phi = 1 (FP64 on the device). Residual = ||sqrt(V)(phi_n - phi_n-1)||_2 /
+ * ||sqrt(V) phi_n||_2 over all (region, group); stops when the residual and |dk| are both
+ * below tol. Synchronous on the context's stream. Starts from the initial guess if one is
+ * set (used once), else from phi = 1, k = 1, psi = 0. Returns MOC_ENOCONV at max_iter with
+ * `out` filled in; MOC_EINVAL if tol <= 0 or out is NULL. */
 int moc_solve(moc_ctx *ctx, double tol, moc_result *out);
 
 /* Exactly n iterations of the moc_solve loop (same start rules) with a single
@@ -226,20 +232,30 @@ int moc_solve(moc_ctx *ctx, double tol, moc_result *out);
  * values. Returns MOC_OK after n iterations. */
 int moc_run_iterations(moc_ctx *ctx, int n, moc_result *out);
 
-/* Initial guess for the next moc_solve: phi0_dev device FP64 [R][G] (required, any
- * scale); k0 > 0, or k0 <= 0 to estimate it as sum V nuSigma_f phi0 / sum V Sigma_a phi0;
- * psi_b0_dev device FP64 [T][2][P][G] incoming boundary fluxes in canonical track order,
- * or NULL: then psi starts at phi0 / 4 pi of the region where each track-sense enters and
- * two transport sweeps with the source frozen at (phi0, k0) make it consistent with the
- * guess before the iteration starts (counted in moc_result.sweeps). A guess with a
- * non-finite or negative entry, or all zeros, is not an error: moc_solve then cold-starts
- * and sets MOC_FLAG_FELL_BACK_TO_COLD. */
+/* Initial guess for the next moc_solve (the state the power iteration of Eq. MGNTE starts
+ * from): phi0_dev device FP64 [R][G] (required, any scale; copied); k0 > 0, or k0 <= 0 to
+ * estimate it as sum V nuSigma_f phi0 / sum V Sigma_a phi0; psi_b0_dev device FP64
+ * [T][2][P][G] incoming boundary fluxes in canonical track order (copied), or NULL: then
+ * psi starts at phi0 / 4 pi of the region where each track-sense enters and two transport
+ * sweeps with the source frozen at (phi0, k0) make it consistent with the guess before the
+ * iteration starts (counted in moc_result.sweeps). The solver owns the fallback, which is
+ * not an error: a guess with a non-finite or negative entry, or all zeros, is not used,
+ * and a guess whose residual exceeds the first residual of a cold start within its first
+ * 10 iterations is abandoned for a cold restart (the cold start's first residual is
+ * measured by one cold iteration when not yet known for the current cross sections,
+ * source mode and coarse mesh, and recorded by every cold-started solve); either way
+ * moc_solve cold-starts and sets MOC_FLAG_FELL_BACK_TO_COLD, and moc_result.sweeps counts
+ * every sweep made. Errors: MOC_EINVAL for a null phi0_dev. */
 int moc_set_initial_guess(moc_ctx *ctx, const double *phi0_dev, double k0, const double *psi_b0_dev);
 
-/* Copy the current scalar flux (device FP64 [R][G], user region order). */
+/* Copy the current scalar flux (the phi of Eq. MGNTE after the last sweep or iteration;
+ * device FP64 [R][G], user region order) to phi_dev on `stream` (NULL: the context's
+ * stream). Errors: MOC_EINVAL (null pointer), MOC_ESTATE (host-only context). */
 int moc_get_flux(moc_ctx *ctx, double *phi_dev, void *stream);
 
-/* Incoming boundary angular fluxes, device FP64 [T][2][P][G]; tracks in canonical order
+/* Incoming boundary angular fluxes psi_in of Eq. MOC_sol at the start of every track
+ * (Sec. 2.1; reflective sides feed them from the linked track's exit, vacuum sides hold 0),
+ * device FP64 [T][2][P][G]; tracks in canonical order
  * (angle index ascending, then perpendicular coordinate -sin(phi) x + cos(phi) y
  * ascending), sense 0 = along (cos phi, sin phi). Get converts from the sweep precision;
  * set rounds to it. */

@@ -15,6 +15,8 @@ static thread_local std::string g_create_error;
 
 // transport sweeps with a frozen source that precede a warm start without boundary fluxes
 static constexpr int kWarmBoundarySweeps = 2;
+// iterations of a warm start whose residual is compared with the cold start's first one
+static constexpr int kGuessWatch = 10;
 
 // default lane stagger of the tally windows (moc_options.lane_stagger = 0)
 static constexpr int kDefaultLaneStagger = 2;
@@ -455,6 +457,7 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
     const bool eigen = c->fissile && !c->fixed_source;
     const int64_t nphi = (int64_t)d.R * d.G;
     const int64_t npsi = (int64_t)2 * d.P * d.Gp * d.nslots;
+    const size_t psi_bytes = (size_t)npsi * (d.precision == MOC_PREC_F64 ? sizeof(double) : sizeof(float));
     int flags = c->fixed_source ? MOC_FLAG_FIXED_SOURCE : 0;
     bool use_guess = false;
     if (c->guess_pending) {
@@ -466,41 +469,50 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         use_guess = chk[0] == 0.0 && chk[1] > 0.0 && std::isfinite(c->guess_k);
         if (!use_guess) flags |= MOC_FLAG_FELL_BACK_TO_COLD;
     }
-    c->cur_phi = 0;
-    double k0 = 1.0;
-    if (use_guess) {
-        HIP_OK(hipMemcpyAsync(d.phi[0], c->guess_phi, nphi * sizeof(double), hipMemcpyDeviceToDevice, s));
-        k0 = c->guess_k;
-        if (!c->guess_has_psi) launch_psi_from_phi(d, d.phi[0], d.psi[c->cur_psi], s);
-    } else {
-        launch_fill_f64(d.phi[0], nphi, 1.0, s);
-        launch_fill_real(d.psi[0], npsi, d.precision, s);
-        launch_fill_real(d.psi[1], npsi, d.precision, s);
-    }
-    c->host_scal[0] = eigen ? (k0 > 0 ? k0 : 1.0) : 1.0;
-    HIP_OK(hipMemcpyAsync(d.scal + kScalK, c->host_scal, sizeof(double), hipMemcpyHostToDevice, s));
-    if (use_guess && eigen && !(k0 > 0)) launch_k_estimate(d, d.phi[0], d.partials, s);
     int sweeps = 0;
-    if (use_guess && !c->guess_has_psi) {
-        // boundary fluxes consistent with the guess: sweeps with the source frozen at
-        // (phi0, k0); the scalar flux of these sweeps is discarded
-        launch_source(d, d.phi[0], s);
-        for (int i = 0; i < kWarmBoundarySweeps; ++i) {
-            sweep_impl(c, s);
-            ++sweeps;
+    double res = 1.0, dk = 1.0, k = 1.0;
+
+    // initial state: the guess (scalar flux, k, boundary fluxes given or made consistent
+    // with it by sweeps at a frozen source), or the cold start phi = 1, k = 1, psi = 0;
+    // then the normalisation sum V nuSigma_f phi = 1 in eigenvalue mode
+    auto start = [&](bool warm) {
+        c->cur_phi = 0;
+        double k0 = 1.0;
+        if (warm) {
+            HIP_OK(hipMemcpyAsync(d.phi[0], c->guess_phi, nphi * sizeof(double), hipMemcpyDeviceToDevice, s));
+            k0 = c->guess_k;
+            if (c->guess_has_psi)
+                HIP_OK(hipMemcpyAsync(d.psi[c->cur_psi], c->guess_psi, psi_bytes, hipMemcpyDeviceToDevice, s));
+            else
+                launch_psi_from_phi(d, d.phi[0], d.psi[c->cur_psi], s);
+        } else {
+            launch_fill_f64(d.phi[0], nphi, 1.0, s);
+            launch_fill_real(d.psi[0], npsi, d.precision, s);
+            launch_fill_real(d.psi[1], npsi, d.precision, s);
         }
-    }
-    if (eigen) {
-        launch_fission_partials(d, d.phi[0], d.partials, s);
-        launch_eigen_update(d, d.partials, 0, s);
-        launch_scale_f64(d.phi[0], nphi, d.scal + kScalF, s);
-        launch_scale_real(d.psi[c->cur_psi], npsi, d.precision, d.scal + kScalF, s);
-    }
-    launch_fill_f64(d.scal + kScalRes, 2, 1.0, s);   // no residual or dk yet (the CMFD step reads them)
-    int it = 0;
-    bool conv = false;
-    double res = 1.0, dk = 1.0, k = k0;
-    for (it = 1; it <= max_iter; ++it) {
+        c->host_scal[0] = eigen ? (k0 > 0 ? k0 : 1.0) : 1.0;
+        HIP_OK(hipMemcpyAsync(d.scal + kScalK, c->host_scal, sizeof(double), hipMemcpyHostToDevice, s));
+        if (warm && eigen && !(k0 > 0)) launch_k_estimate(d, d.phi[0], d.partials, s);
+        if (warm && !c->guess_has_psi) {
+            // boundary fluxes consistent with the guess: sweeps with the source frozen at
+            // (phi0, k0); the scalar flux of these sweeps is discarded
+            launch_source(d, d.phi[0], s);
+            for (int i = 0; i < kWarmBoundarySweeps; ++i) {
+                sweep_impl(c, s);
+                ++sweeps;
+            }
+        }
+        if (eigen) {
+            launch_fission_partials(d, d.phi[0], d.partials, s);
+            launch_eigen_update(d, d.partials, 0, s);
+            launch_scale_f64(d.phi[0], nphi, d.scal + kScalF, s);
+            launch_scale_real(d.psi[c->cur_psi], npsi, d.precision, d.scal + kScalF, s);
+        }
+        launch_fill_f64(d.scal + kScalRes, 2, 1.0, s);   // no residual or dk yet (the CMFD step reads them)
+    };
+    // one iteration: source, sweep, scalar flux, (CMFD step), eigenvalue update,
+    // normalisation and residual
+    auto iterate = [&] {
         double *phi_old = d.phi[c->cur_phi], *phi_new = d.phi[1 - c->cur_phi];
         launch_source(d, phi_old, s);
         sweep_impl(c, s);
@@ -526,13 +538,42 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
         launch_norm_residual(d, phi_new, phi_old, d.partials, s);
         if (eigen) launch_scale_real(d.psi[c->cur_psi], npsi, d.precision, d.scal + kScalF, s);
         c->cur_phi = 1 - c->cur_phi;
-        if (it % check_every == 0 || it == max_iter) {
-            HIP_OK(hipMemcpyAsync(c->host_scal, d.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIP_OK(hipStreamSynchronize(s));
-            k = c->host_scal[kScalK];
-            res = c->host_scal[kScalRes];
-            dk = c->host_scal[kScalDk];
-            if (!std::isfinite(res) || !std::isfinite(k)) throw Error(MOC_EHIP, "solve: non-finite iterate");
+    };
+    auto read_back = [&] {
+        HIP_OK(hipMemcpyAsync(c->host_scal, d.scal, kScalCount * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        k = c->host_scal[kScalK];
+        res = c->host_scal[kScalRes];
+        dk = c->host_scal[kScalDk];
+        if (!std::isfinite(res) || !std::isfinite(k)) throw Error(MOC_EHIP, "solve: non-finite iterate");
+    };
+
+    if (use_guess && !(c->cold_res0 >= 0)) {
+        // the cold start's first residual is the bar a guess has to stay under: one cold
+        // iteration measures it (once per cross-section set, source mode and coarse mesh)
+        start(false);
+        iterate();
+        read_back();
+        c->cold_res0 = res;
+    }
+    start(use_guess);
+    int it = 0;
+    bool conv = false;
+    for (it = 1; it <= max_iter; ++it) {
+        iterate();
+        const bool watch = use_guess && it <= kGuessWatch;
+        const bool record = !use_guess && it == 1 && !(c->cold_res0 >= 0);
+        if (it % check_every == 0 || it == max_iter || watch || record) {
+            read_back();
+            if (record) c->cold_res0 = res;
+            if (watch && res > c->cold_res0) {
+                // the guess does worse than a cold start would: restart cold
+                flags |= MOC_FLAG_FELL_BACK_TO_COLD;
+                use_guess = false;
+                start(false);
+                it = 0;
+                continue;
+            }
             if (res < tol && dk < tol) {
                 conv = true;
                 break;
@@ -579,7 +620,17 @@ int moc_set_initial_guess(moc_ctx *c, const double *phi0_dev, double k0, const d
         launch_permute_rows(c->d, phi0_dev, c->guess_phi, 0, c->stream);
         c->guess_k = k0;
         c->guess_has_psi = psi_b0_dev != nullptr;
-        if (psi_b0_dev) launch_psi_canon(c->d, const_cast<double *>(psi_b0_dev), c->d.psi[c->cur_psi], 0, c->stream);
+        if (psi_b0_dev) {
+            const int64_t npsi = (int64_t)2 * c->d.P * c->d.Gp * c->d.nslots;
+            if (!c->guess_psi) {
+                if (c->d.precision == MOC_PREC_F64)
+                    c->guess_psi = c->dalloc<double>((size_t)npsi);
+                else
+                    c->guess_psi = c->dalloc<float>((size_t)npsi);
+            }
+            launch_fill_real(c->guess_psi, npsi, c->d.precision, c->stream);
+            launch_psi_canon(c->d, const_cast<double *>(psi_b0_dev), c->guess_psi, 0, c->stream);
+        }
         HIP_OK(hipStreamSynchronize(c->stream));
         c->guess_pending = true;
     });
@@ -627,6 +678,7 @@ int moc_set_external_source(moc_ctx *c, const double *q_dev) {
     return guarded(c, [&] {
         need_device(c);
         HIP_OK(hipSetDevice(c->device));
+        c->cold_res0 = -1.0;
         if (!q_dev) {
             c->fixed_source = false;
             c->d.qext = nullptr;
@@ -690,6 +742,7 @@ int moc_set_materials(moc_ctx *c, const int32_t *region_material, const moc_xs *
         c->fixed_source = false;
         d.qext = nullptr;
         c->guess_pending = false;
+        c->cold_res0 = -1.0;
     });
 }
 
@@ -901,7 +954,10 @@ static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell,
 
 int moc_set_coarse_mesh(moc_ctx *c, int32_t n_cells, const int32_t *region_cell, const moc_cmfd_options *opts) {
     if (!c) return MOC_EINVAL;
-    return guarded(c, [&] { set_coarse_impl(c, n_cells, region_cell, opts); });
+    return guarded(c, [&] {
+        c->cold_res0 = -1.0;
+        set_coarse_impl(c, n_cells, region_cell, opts);
+    });
 }
 
 int moc_get_coarse_info(moc_ctx *c, moc_coarse_info *info) {

@@ -49,6 +49,10 @@ struct moc_ctx {
     double guess_k = 1.0;
     bool guess_has_psi = false;
     double *guess_phi = nullptr;   // internal [R][G]
+    void *guess_psi = nullptr;     // internal boundary-flux layout, sweep precision
+    // residual of the first iteration from a cold start with the current cross sections,
+    // source mode and coarse mesh (negative: not known yet); a warm start must stay below it
+    double cold_res0 = -1.0;
     double *exit_canon = nullptr;  // user buffer
     double *host_scal = nullptr;   // pinned
     std::vector<std::pair<void *, size_t>> allocs;
