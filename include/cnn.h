@@ -60,6 +60,18 @@ int cnn_relu_backward(const float *dy, const uint16_t *y, int64_t n, float *dz_f
 int cnn_mse_grad(const float *y, const float *t, int64_t npix, int32_t cs, int32_t cv, float *dy,
                  double *loss_partials, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): cnn_mse_grad without the workspace. Same dy;
+ * loss (device FP64, one value) receives the mean squared error, the partial sums
+ * divided by npix * cv. The 256 per-block partials live in a fixed 2 KiB array inside
+ * the library (one per device, kept until the process ends; its size does not depend on
+ * the input, so every size cnn_mse_grad accepts is accepted). Nothing is allocated.
+ * Calls that overlap on one device (other streams, other threads) share that array and
+ * race; serialise them. MOC_EINVAL for bad sizes or null pointers, MOC_EHIP if the
+ * array's device address cannot be obtained or the launch fails. */
+int cnn_mse_grad_noalloc(const float *y, const float *t, int64_t npix, int32_t cs, int32_t cv, float *dy,
+                         double *loss, void *stream);
+
 /* Adam with bias correction (step t >= 1) on FP32 master parameters p; also writes the
  * BF16 copy p_bf16 (may be NULL). */
 int cnn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1,

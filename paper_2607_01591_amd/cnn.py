@@ -20,6 +20,7 @@ SIGNATURES = {
     "cnn_bias_grad": [_vp, _i64, _i32, _vp, _vp],
     "cnn_relu_backward": [_vp, _vp, _i64, _vp, _vp, _vp],
     "cnn_mse_grad": [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp],
+    "cnn_mse_grad_noalloc": [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp],
     "cnn_adam": [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i32, _vp, _vp],
     "cnn_to_bf16": [_vp, _i64, _vp, _vp],
     "cnn_gather_rows": [_vp, _vp, _i64, _i32, _i32, _vp, _vp],
@@ -97,6 +98,13 @@ def mse_grad(y, t, cv, dy, partials, stream=None):
     cs = y.shape[-1]
     _ok(lib().cnn_mse_grad(_p(y), _p(t), y.numel() // cs, cs, cv, _p(dy), _p(partials), _s(stream)),
         "cnn_mse_grad")
+
+
+def mse_grad_noalloc(y, t, cv, dy, loss, stream=None):
+    """cnn_mse_grad_noalloc: dy as mse_grad, loss (device FP64 [1]) = the mean squared error."""
+    cs = y.shape[-1]
+    _ok(lib().cnn_mse_grad_noalloc(_p(y), _p(t), y.numel() // cs, cs, cv, _p(dy), _p(loss), _s(stream)),
+        "cnn_mse_grad_noalloc")
 
 
 def adam(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, p_bf16=None, stream=None):

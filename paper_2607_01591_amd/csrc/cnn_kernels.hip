@@ -7,6 +7,7 @@
 // holds rows 4 (l / 16) .. + 3 of column l % 16.
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include <hip/hip_runtime.h>
 
@@ -331,6 +332,48 @@ inline int grid_for(int64_t n, int block, int cap = 4096) {
 
 inline int launched() { return hipGetLastError() == hipSuccess ? MOC_OK : MOC_EHIP; }
 
+// ---------------------------------------------------------------- allocation-free loss
+// Blocks of the loss kernel: the partial sums of squares have exactly this many entries.
+constexpr int kMseBlocks = 256;
+
+// Sum of the per-block partials in block order, divided by the element count.
+__global__ void k_mse_finish(const double *__restrict__ partials, int nblk, double inv_count, double *__restrict__ loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < nblk; ++i) s += partials[i];
+        loss[0] = s * inv_count;
+    }
+}
+
+}  // namespace
+
+// Partial sums of cnn_mse_grad_noalloc: a file-scope device array instead of a caller's
+// workspace, held by every device the library runs on until the process ends. In host
+// code this name denotes a host-side stand-in; the device address of each device's copy
+// comes from hipGetSymbolAddress and is the only form host code passes to kernels.
+static __device__ __align__(256) double scratch[kMseBlocks];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_on_current_device(double **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return MOC_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return MOC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MOC_EHIP;
+        g_scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return MOC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -389,7 +432,22 @@ int cnn_relu_backward(const float *dy, const uint16_t *y, int64_t n, float *dz_f
 int cnn_mse_grad(const float *y, const float *t, int64_t npix, int32_t cs, int32_t cv, float *dy, double *loss_partials,
                  void *stream) {
     if (!y || !t || !dy || !loss_partials || npix <= 0 || cs <= 0 || cv <= 0 || cv > cs) return MOC_EINVAL;
-    hipLaunchKernelGGL(k_mse_grad, dim3(256), dim3(256), 0, (hipStream_t)stream, y, t, npix, cs, cv, dy, loss_partials);
+    hipLaunchKernelGGL(k_mse_grad, dim3(kMseBlocks), dim3(256), 0, (hipStream_t)stream, y, t, npix, cs, cv, dy,
+                       loss_partials);
+    return launched();
+}
+
+int cnn_mse_grad_noalloc(const float *y, const float *t, int64_t npix, int32_t cs, int32_t cv, float *dy, double *loss,
+                         void *stream) {
+    if (!y || !t || !dy || !loss || npix <= 0 || cs <= 0 || cv <= 0 || cv > cs) return MOC_EINVAL;
+    double *part = nullptr;
+    const int rc = scratch_on_current_device(&part);
+    if (rc != MOC_OK) return rc;
+    // every one of the kMseBlocks blocks writes its own partial, so the array needs no
+    // clearing between calls
+    hipLaunchKernelGGL(k_mse_grad, dim3(kMseBlocks), dim3(256), 0, (hipStream_t)stream, y, t, npix, cs, cv, dy, part);
+    hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(64), 0, (hipStream_t)stream, part, kMseBlocks,
+                       1.0 / ((double)npix * (double)cv), loss);
     return launched();
 }
 
