@@ -87,7 +87,7 @@ def parse():
     ap.add_argument("--cnn-only", action="store_true", help="run only the warm-start network leg (profiling)")
     ap.add_argument("--hfem-only", action="store_true", help="run only the HFEM leg (profiling)")
     ap.add_argument("--hfem-max-iter", type=int, default=5000, help="iteration cap of the HFEM solve")
-    ap.add_argument("--exp-mode", default="diff")
+    ap.add_argument("--exp-mode", default="poly")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch a plain 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()

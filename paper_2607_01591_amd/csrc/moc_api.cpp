@@ -132,12 +132,12 @@ void moc::create_context(const moc_mesh *mesh_in, const moc_tracks *tr_in, const
     if (!mesh_in || !tr_in || !xs) throw Error(MOC_EINVAL, "create: null argument");
     moc_options o{};
     o.precision = MOC_PREC_F32;
-    o.exp_mode = MOC_EXP_DIFF;
+    o.exp_mode = MOC_EXP_POLY;
     if (opt) o = *opt;
     if (o.tally_slots != 0 && (o.tally_slots < kBatch || o.tally_slots > kMaxSlots))
         throw Error(MOC_EINVAL, "options: tally_slots must be 0 or in 64..256");
     if (o.precision != MOC_PREC_F32 && o.precision != MOC_PREC_F64) throw Error(MOC_EINVAL, "options: bad precision");
-    if (o.exp_mode < MOC_EXP_DIFF || o.exp_mode > MOC_EXP_POLY) throw Error(MOC_EINVAL, "options: bad exp_mode");
+    if (o.exp_mode < MOC_EXP_POLY || o.exp_mode > MOC_EXP_DIFF) throw Error(MOC_EINVAL, "options: bad exp_mode");
     c->max_iter = o.max_iter > 0 ? o.max_iter : 10000;
     c->check_every = o.check_every > 0 ? o.check_every : 1;
     c->n_threads = o.n_threads > 0 ? o.n_threads : std::max(1u, std::thread::hardware_concurrency());
@@ -338,6 +338,7 @@ void moc::create_context(const moc_mesh *mesh_in, const moc_tracks *tr_in, const
     d.exp_table = c->upload(table);
     d.partials = c->dalloc<double>(2 * kReduceBlocks);
     d.scal = c->dalloc<double>(kScalCount);
+    d.tally_bound = c->dalloc<unsigned>((size_t)d.Gp);
     if (!c->host_only) {
         launch_fill_f64(d.scal, kScalCount, 0.0, c->stream);
         launch_fill_f64(d.scal, 1, 1.0, c->stream);  // k = 1
@@ -388,12 +389,15 @@ static void sweep_impl(moc_ctx *c, hipStream_t s) {
     a.inv_sin = d.inv_sin;
     a.exp_table = d.exp_table;
     a.tally = d.tally;
+    a.tally_bound = d.tally_bound;
     a.exit_canon = c->exit_canon;
     a.canon_of_slot = d.canon_of_slot;
     a.nslots = d.nslots;
     a.Gp = d.Gp;
     a.G = d.G;
     a.n_real = d.R;
+    // the FP32 sweep's window sums are fixed point scaled from a bound of the fluxes
+    if (d.precision == MOC_PREC_F32) launch_tally_bound(d, a.psi_in, s);
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (c->profiling) {
         ev = prof_events(c);
@@ -783,7 +787,7 @@ static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell,
     if (o.tol < 0 || o.max_outer < 0 || o.max_inner < 0) throw Error(MOC_EINVAL, "coarse mesh: negative option");
     if (o.coarse_blocks < 0 || o.coarse_blocks > 256) throw Error(MOC_EINVAL, "coarse mesh: coarse_blocks must be in 0..256");
     if (d.precision == MOC_PREC_F32 && d.exp_mode != MOC_EXP_POLY && d.exp_mode != MOC_EXP_DIFF)
-        throw Error(MOC_EINVAL, "coarse mesh: CMFD currents need exp_mode MOC_EXP_DIFF or MOC_EXP_POLY");
+        throw Error(MOC_EINVAL, "coarse mesh: CMFD currents need exp_mode MOC_EXP_POLY or MOC_EXP_DIFF");
     std::vector<int64_t> count(n_cells, 0);
     for (int u = 0; u < R; ++u) {
         if (region_cell[u] < 0 || region_cell[u] >= n_cells) throw Error(MOC_EINVAL, "coarse mesh: cell index out of range");

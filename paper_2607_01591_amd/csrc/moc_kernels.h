@@ -38,6 +38,7 @@ struct SweepArgs {
     const void *inv_sin;       // Real [P]
     const float *exp_table;    // [ExpTable::kN] (FP32 table mode)
     double *tally;             // [R][Gp]
+    const unsigned *tally_bound; // [Gp] FP32 sweep: max(|qhat|, |psi_in|) per group (float bits)
     double *exit_canon;        // optional [T][2][P][G]
     const int *canon_of_slot;  // [nslots] canonical track or -1
     int nslots, Gp, G;
@@ -47,7 +48,7 @@ struct SweepArgs {
 struct DevProblem {
     int R = 0, G = 0, Gp = 0, M = 0, P = 0, NA = 0, T = 0;
     int nb = 0, nslots = 0, gb = 1, n_gb = 1;
-    int precision = MOC_PREC_F32, exp_mode = MOC_EXP_DIFF;
+    int precision = MOC_PREC_F32, exp_mode = MOC_EXP_POLY;
     // per material, FP64
     double *sigt_m = nullptr, *sigs_m = nullptr, *nsf_m = nullptr, *chi_m = nullptr;
     // per internal region
@@ -73,6 +74,7 @@ struct DevProblem {
     float *exp_table = nullptr;
     // reductions
     double *partials = nullptr, *scal = nullptr;
+    unsigned *tally_bound = nullptr;   // [Gp] see SweepArgs
 };
 
 // Coarse mesh (CMFD) device state; see moc_cmfd.hip.
@@ -106,6 +108,7 @@ void launch_cmfd(const DevProblem &d, const DevCoarse &cd, double *phi, void *ps
 void launch_sweep(const SweepArgs &a, int precision, int exp_mode, bool currents, int nb, int np, int gb, int n_gb,
                   hipStream_t s);
 void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+void launch_tally_bound(const DevProblem &d, const void *psi_in, hipStream_t s);
 void launch_fill_real(void *p, int64_t n, int precision, hipStream_t s);
 void launch_scale_real(void *p, int64_t n, int precision, const double *f, hipStream_t s);
 void launch_scale_f64(double *p, int64_t n, const double *f, hipStream_t s);

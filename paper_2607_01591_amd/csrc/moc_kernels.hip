@@ -32,6 +32,19 @@ struct ExpTable {
     static constexpr float kMax = kExpTableMax;
 };
 
+// LDS of one sweep workgroup: the window tally [cap][GB] (FP64, or 64-bit fixed point in
+// the FP32 sweep; 8 bytes either way), the window's slot -> region table for the flush,
+// the per-group inverse fixed-point scales, and the exponential table (FP32 table mode).
+template <typename Real, int GB, int MODE> struct SweepLds {
+    static constexpr int kScaleSlots = 16;   // >= GB
+    static constexpr size_t tab(int cap) { return sizeof(double) * GB * (size_t)cap; }
+    static constexpr size_t scale(int cap) { return (tab(cap) + sizeof(int) * (size_t)cap + 7) / 8 * 8; }
+    static constexpr size_t lut(int cap) { return scale(cap) + sizeof(double) * kScaleSlots; }
+    static constexpr size_t bytes(int cap) {
+        return lut(cap) + (MODE == MOC_EXP_TABLE && sizeof(Real) == 4 ? sizeof(float) * ExpTable::kN : 0);
+    }
+};
+
 template <int MODE> __device__ __forceinline__ float one_minus_exp_f(float tau, const float *lut) {
     if constexpr (MODE == MOC_EXP_TABLE) {
         const float x = tau * (ExpTable::kN / ExpTable::kMax);
@@ -63,8 +76,21 @@ template <typename Real, int MODE> __device__ __forceinline__ Real one_minus_exp
 // psi_out = qhat + (psi_in - qhat) e^-tau with tau = Sigma_t l / sin(theta_p); the
 // increment Delta = (psi - qhat)(1 - e^-tau) is summed over the polar angles with the
 // weights c_ap = 2 pi w_a w_p delta_a sin(theta_p) in registers, then added to the
-// window-local FP64 tally slot in LDS. At the end of each window every slot is flushed with
+// window-local tally slot in LDS. At the end of each window every slot is flushed with
 // one FP64 atomic per group (consecutive lanes hit consecutive groups of a region row).
+//
+// FP32 sweep: the LDS window sums are 64-bit fixed point, since an integer LDS add
+// (ds_add_u64) costs well under half of an FP64 one on gfx950. Along a segment the new
+// angular flux is a convex combination of the old one and qhat, so with
+// A_g = max(|qhat|, |incoming psi|) over the whole problem (tally_bound, formed before
+// the sweep) every |psi - qhat| <= 2 A_g and every per-step polar sum is bounded by
+// B = 2 A_g sum_p c_ap. The wave's scale for group g is s = 2^(50 - E), 2^(E-1) <= B < 2^E:
+// each step's sum is rounded to the nearest multiple of 1/s (one FP64 fused multiply-add
+// with 1.5 2^52, which leaves round(sum s) in the low mantissa bits while |sum s| < 2^51)
+// and added as an integer; a slot takes at most kMaxSlotVisits (4095) terms, each below
+// 2^50, so its sum stays below 2^62. The rounding error of a term is <= 2^(-51) B, far
+// below the FP32 rounding of the sum itself; the flush converts each slot to FP64 and
+// multiplies by 1/s (exact).
 //
 // CUR: the stream also holds coarse-surface crossing entries (region field >= n_real,
 // length +-1 for the surface orientation). Their tally row holds Sigma_t = 1e30 and
@@ -74,11 +100,16 @@ template <typename Real, int MODE> __device__ __forceinline__ Real one_minus_exp
 template <typename Real, int NP, int GB, int MODE, bool CUR>
 __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     using Seg = typename SegOf<Real>::type;
+    using Lds = SweepLds<Real, GB, MODE>;
+    constexpr bool kFix = sizeof(Real) == 4;   // 64-bit fixed-point window sums
     extern __shared__ unsigned char smem[];
-    double *tl = reinterpret_cast<double *>(smem);   // tally [cap][GB], FP64 (ds_add_f64 is much
-    // faster than ds_add_f32 on gfx950 and keeps the window sums exact to FP64 rounding)
+    // tally [cap][GB]: FP64 (ds_add_f64 is far faster than ds_add_f32 on gfx950), or, in
+    // the FP32 sweep, 64-bit fixed point (ds_add_u64 faster again)
+    double *tl = reinterpret_cast<double *>(smem);
+    unsigned long long *tlu = reinterpret_cast<unsigned long long *>(smem);
     const int cap = args.cap;
-    float *lut = reinterpret_cast<float *>(smem + (sizeof(double) * GB + sizeof(int)) * cap);
+    double *winv = reinterpret_cast<double *>(smem + Lds::scale(cap));   // [GB] 1 / s per group
+    float *lut = reinterpret_cast<float *>(smem + Lds::lut(cap));
     if constexpr (MODE == MOC_EXP_TABLE && sizeof(Real) == 4) {
         for (int i = threadIdx.x; i < ExpTable::kN; i += 64) lut[i] = args.exp_table[i];
     }
@@ -124,6 +155,24 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int j = 0; j < GB; ++j) psi[p][j] = psi_in[(int64_t)((sense * NP + p) * Gp + g0 + j) * nslots + slot];
+    // fixed-point scale s of each group for this wave (FP32 sweep)
+    double fsc[GB];
+    if constexpr (kFix) {
+        float csum = 0.f;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) csum += fabsf((float)c[p]);
+#pragma unroll
+        for (int j = 0; j < GB; ++j) {
+            const double B = 2.0 * (double)__uint_as_float(args.tally_bound[g0 + j]) * (double)csum;
+            const bool finite = B <= 1.0e300;   // false for inf and NaN
+            int E = 0;
+            if (B > 0.0 && finite) frexp(B, &E);   // B = m 2^E, 1/2 <= m < 1
+            E = E < -900 ? -900 : E;
+            fsc[j] = finite ? ldexp(1.0, 50 - E) : 0.0;
+            // a non-finite flux or source makes the tallies of the affected group NaN
+            if (threadIdx.x == j) winv[j] = finite ? ldexp(1.0, E - 50) : __builtin_nan("");
+        }
+    }
 
     // Sigma_t and qhat of a region's group batch. One code path per instantiation: a
     // runtime choice between load widths would join two paths right after the loads and
@@ -159,7 +208,7 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
         }
     };
 
-    int *tabl = reinterpret_cast<int *>(smem + sizeof(double) * GB * cap);   // slot -> region
+    int *tabl = reinterpret_cast<int *>(smem + Lds::tab(cap));   // slot -> region
     const int64_t w0 = args.batch_win[b], w1 = args.batch_win[b + 1];
     for (int64_t wi = 0; wi < w1 - w0; ++wi) {
         const int64_t w = sense ? w1 - 1 - wi : w0 + wi;
@@ -228,9 +277,20 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
                 }
             }
             if (len > Real(0)) {   // padding steps add nothing
-                double *row = tl + ts * GB;
+                if constexpr (kFix) {
+                    // round(acc s) as a 64-bit integer: adding 1.5 2^52 leaves it in the
+                    // low mantissa bits
+                    unsigned long long *row = tlu + ts * GB;
 #pragma unroll
-                for (int j = 0; j < GB; ++j) atomicAdd(&row[j], (double)acc[j]);
+                    for (int j = 0; j < GB; ++j) {
+                        const double v = __builtin_fma((double)acc[j], fsc[j], 6755399441055744.0);
+                        atomicAdd(&row[j], (unsigned long long)__double_as_longlong(v) - 0x4338000000000000ull);
+                    }
+                } else {
+                    double *row = tl + ts * GB;
+#pragma unroll
+                    for (int j = 0; j < GB; ++j) atomicAdd(&row[j], (double)acc[j]);
+                }
             }
         };
         if constexpr (sizeof(Real) == 4) {
@@ -282,10 +342,19 @@ __global__ __launch_bounds__(64) void k_sweep(SweepArgs args) {
         // flush the window's slots: (slot, group) pairs, groups fastest
         for (int e = lane; e < ns * GB; e += 64) {
             const int sl = e / GB, j = e - sl * GB;
-            const double v = tl[e];
-            if (v != 0.0) {
-                unsafeAtomicAdd(&tally[(int64_t)tabl[sl] * Gp + g0 + j], v);
-                tl[e] = 0.0;
+            if constexpr (kFix) {
+                const long long iv = (long long)tlu[e];
+                const double iw = winv[j];
+                if (iv != 0 || iw != iw) {
+                    unsafeAtomicAdd(&tally[(int64_t)tabl[sl] * Gp + g0 + j], (double)iv * iw);
+                    tlu[e] = 0ull;
+                }
+            } else {
+                const double v = tl[e];
+                if (v != 0.0) {
+                    unsafeAtomicAdd(&tally[(int64_t)tabl[sl] * Gp + g0 + j], v);
+                    tl[e] = 0.0;
+                }
             }
         }
         __syncthreads();
@@ -591,6 +660,30 @@ __global__ void k_check_guess(const double *__restrict__ x, int64_t n, double *_
     }
 }
 
+// Per-group bound of the FP32 sweep's fluxes: tally_bound[g] = max over regions of |qhat|
+// and over the incoming boundary fluxes of |psi| (float bit patterns of non-negative
+// values order like the values). Each block takes the maximum per group in LDS, then
+// one global atomic per group; the caller zeroes tally_bound first.
+__global__ void k_tally_bound(const float *__restrict__ xsq, const float *__restrict__ psi, int R, int Gp, int64_t npsi,
+                              int nslots, unsigned *__restrict__ bound) {
+    extern __shared__ unsigned bmax[];
+    for (int g = threadIdx.x; g < Gp; g += blockDim.x) bmax[g] = 0u;
+    __syncthreads();
+    const int64_t nq = (int64_t)R * Gp;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq; i += stride)
+        atomicMax(&bmax[i % Gp], __float_as_uint(fabsf(xsq[2 * i + 1])));
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npsi; i += stride)
+        atomicMax(&bmax[(i / nslots) % Gp], __float_as_uint(fabsf(psi[i])));
+    __syncthreads();
+    for (int g = threadIdx.x; g < Gp; g += blockDim.x)
+        if (bmax[g]) atomicMax(&bound[g], bmax[g]);
+}
+
+template <typename T> __global__ void k_fill_u32(T *__restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = T(0);
+}
+
 // ---------------------------------------------------------------- launchers
 static inline int grid_for(int64_t n, int block, int cap = 4096) {
     int64_t g = (n + block - 1) / block;
@@ -608,8 +701,8 @@ static inline int grid_for(int64_t n, int block, int cap = 4096) {
 template <typename Real, int NP, int GB, int MODE, bool CUR>
 static void sweep_inst(const SweepArgs &a, int nb, int n_gb, hipStream_t s) {
     if (a.cap > kMaxSlots) throw Error(MOC_EINVAL, "sweep: window slot count above the kernel maximum");
-    size_t lds = (sizeof(double) * GB + sizeof(int)) * (size_t)a.cap;
-    if (MODE == MOC_EXP_TABLE && sizeof(Real) == 4) lds += sizeof(float) * ExpTable::kN;
+    static_assert(GB <= SweepLds<Real, GB, MODE>::kScaleSlots, "group batch above the scale slots");
+    const size_t lds = SweepLds<Real, GB, MODE>::bytes(a.cap);
     if (lds > 64 * 1024) throw Error(MOC_EINVAL, "sweep: tally window does not fit in LDS");
     hipLaunchKernelGGL((k_sweep<Real, NP, GB, MODE, CUR>), dim3(nb, 2, n_gb), dim3(64), lds, s, a);
 }
@@ -650,19 +743,30 @@ void launch_sweep(const SweepArgs &a, int precision, int exp_mode, bool currents
         else if (exp_mode == MOC_EXP_DIFF)
             ok = sweep_np<float, MOC_EXP_DIFF, true>(a, nb, np, gb, n_gb, s);
         else
-            throw Error(MOC_EINVAL, "sweep: coarse-surface currents need MOC_EXP_DIFF or MOC_EXP_POLY");
+            throw Error(MOC_EINVAL, "sweep: coarse-surface currents need MOC_EXP_POLY or MOC_EXP_DIFF");
     } else if (precision == MOC_PREC_F64) {
         ok = sweep_np<double, MOC_EXP_POLY, false>(a, nb, np, gb, n_gb, s);
     } else if (exp_mode == MOC_EXP_TABLE) {
         ok = sweep_np<float, MOC_EXP_TABLE, false>(a, nb, np, gb, n_gb, s);
     } else if (exp_mode == MOC_EXP_LIBM) {
         ok = sweep_np<float, MOC_EXP_LIBM, false>(a, nb, np, gb, n_gb, s);
-    } else if (exp_mode == MOC_EXP_POLY) {
-        ok = sweep_np<float, MOC_EXP_POLY, false>(a, nb, np, gb, n_gb, s);
-    } else {
+    } else if (exp_mode == MOC_EXP_DIFF) {
         ok = sweep_np<float, MOC_EXP_DIFF, false>(a, nb, np, gb, n_gb, s);
+    } else {
+        ok = sweep_np<float, MOC_EXP_POLY, false>(a, nb, np, gb, n_gb, s);
     }
     if (!ok) throw Error(MOC_EINVAL, "sweep: no kernel instance for this polar count / group batch");
+    MOC_CHECK_LAUNCH();
+}
+
+void launch_tally_bound(const DevProblem &d, const void *psi_in, hipStream_t s) {
+    if (d.precision != MOC_PREC_F32) return;
+    const int64_t npsi = (int64_t)2 * d.P * d.Gp * d.nslots;
+    hipLaunchKernelGGL(k_fill_u32<unsigned>, dim3(1), dim3(64), 0, s, d.tally_bound, (int64_t)d.Gp);
+    const size_t lds = sizeof(unsigned) * (size_t)d.Gp;
+    if (lds > 64 * 1024) throw Error(MOC_EINVAL, "sweep: too many groups for the flux bound");
+    hipLaunchKernelGGL(k_tally_bound, dim3(grid_for((int64_t)d.R * d.Gp + npsi, 256, 2048)), dim3(256), lds, s,
+                       (const float *)d.xsq, (const float *)psi_in, d.R, d.Gp, npsi, d.nslots, d.tally_bound);
     MOC_CHECK_LAUNCH();
 }
 

@@ -6,8 +6,8 @@
 // [w L, (w + 1) L). Within a window the lanes advance in lockstep (shorter lanes are
 // padded with zero-length steps), and every distinct region the window touches gets a
 // window-local tally slot, so the sweep kernel can accumulate the window's tallies in
-// LDS and flush each slot once. A window whose slot count exceeds `cap` is split in half
-// by distance.
+// LDS and flush each slot once. A window whose slot count exceeds `cap`, or in which
+// more than kMaxSlotVisits entries fall on one region, is split in half.
 //
 // Segment entry: {length, key}, key = (internal region << kSlotBits) | slot.
 #include <algorithm>
@@ -173,8 +173,13 @@ class BatchPlanner {
         for (int l = 0; l < kBatch; ++l)
             for (size_t k = ptr_[l]; k < end_[l]; ++k) regs_.push_back(lanes_[l][k].reg);
         std::sort(regs_.begin(), regs_.end());
+        int visits = 0;   // most entries on one region
+        for (size_t i = 0, j; i < regs_.size(); i = j) {
+            for (j = i; j < regs_.size() && regs_[j] == regs_[i]; ++j) {}
+            visits = std::max(visits, int(j - i));
+        }
         regs_.erase(std::unique(regs_.begin(), regs_.end()), regs_.end());
-        if ((int)regs_.size() > in_.cap && maxn > 1) {
+        if (((int)regs_.size() > in_.cap || visits > kMaxSlotVisits) && maxn > 1) {
             split(0);
             split(1);
             return;

@@ -9,6 +9,10 @@ namespace moc {
 
 // low bits of a segment key hold the window-local tally slot
 constexpr int kSlotBits = 9;
+// most entries of one tally window that may fall on one slot: the FP32 sweep's 64-bit
+// fixed-point window sums (terms below 2^50) stay below 2^62 up to this count; a window
+// above it is split
+constexpr int kMaxSlotVisits = 4095;
 
 struct SegF {
     float len;

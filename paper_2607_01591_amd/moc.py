@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmoc.so")
 
 MOC_OK, MOC_EINVAL, MOC_ENOMEM, MOC_EHIP, MOC_ENOCONV, MOC_ESTATE = range(6)
 PREC = {"f32": 0, "f64": 1}
-EXP = {"diff": 0, "table": 1, "libm": 2, "poly": 3}
+EXP = {"poly": 0, "table": 1, "libm": 2, "diff": 3}
 FLAG_FELL_BACK_TO_COLD = 1
 FLAG_FIXED_SOURCE = 2
 
@@ -159,7 +159,7 @@ class Solver:
     quadrature and info; no sweeps).
     """
 
-    def __init__(self, prob, precision: str = "f32", exp_mode: str = "diff", device: int = 0,
+    def __init__(self, prob, precision: str = "f32", exp_mode: str = "poly", device: int = 0,
                  max_iter: int = 10000, check_every: int = 1, n_threads: int = 0,
                  polar: Optional[tuple] = None, window_cm: float = 0.0, tally_slots: int = 0,
                  group_batch: int = 0, window_steps: int = 0, lane_stagger: int = 0, batch_order: int = 0):
@@ -303,7 +303,8 @@ class Solver:
         import torch
         torch.cuda.current_stream().synchronize()
         self._check(lib().moc_run_iterations(self._h, int(n), C.byref(r)))
-        return dict(k=r.k, iterations=r.iterations, residual=r.residual, dk=r.dk, wall_ms=r.wall_ms)
+        return dict(k=r.k, iterations=r.iterations, residual=r.residual, dk=r.dk, wall_ms=r.wall_ms,
+                    flags=r.flags, sweeps=r.sweeps)
 
     def set_materials(self, prob):
         """Swap in the cross sections and material map of ``prob`` (same mesh)."""

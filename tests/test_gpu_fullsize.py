@@ -1,14 +1,14 @@
 """Parity at the benchmarked sizes, in the launch configuration bench.py times.
 
-* 17 x 17 lattice (31k regions, 12.3M segments): one FP32 sweep against one oracle
-  sweep, element by element.
-* 51 x 51 lattice (1.2M regions, 1.0e9 segments) and the 271-pin hexagon (399k regions,
-  33 groups): too large for the oracle; checked through properties that hold at any
-  size: the per-group balance identity of a sweep
+* 17 x 17 lattice (31k regions, 12.3M segments) and the 271-pin hexagon (399k regions,
+  33 groups, the group-batch-11 sweep instance): one FP32 sweep against one oracle sweep,
+  element by element.
+* 51 x 51 lattice (1.2M regions, 1.0e9 segments) and the hexagon again: the per-group
+  balance identity of a sweep
       sum_r V_r (Sigma_t phi_r - s_r) = sum_{tracks, senses, polar} c_ap (psi_in - psi_out)
   (every increment is tallied exactly once, with the right weight), and agreement of
-  the FP32 sweep with its FP64 instantiation (which matches the oracle to 1e-11 on the
-  smaller cases).
+  the FP32 sweep with its FP64 instantiation. The converged answers of these workloads are
+  checked against the oracle by the fixed-point tests.
 """
 import math
 import sys
@@ -79,6 +79,34 @@ def test_cfg2_full_size_sweep_vs_oracle(cuda):
     log(f"  max rel err {err:.2e}")
     assert err < 1e-5
     np.testing.assert_allclose(_host(ex), o.get_exit_psi(), rtol=1e-5, atol=1e-6)
+
+
+def test_cfg4_full_size_sweep_vs_oracle(cuda):
+    """The 271-pin hexagon with 33 groups in full: the sweep instance the benchmark runs
+    (group batch 11, three batches, P = 3) against one oracle sweep, element by element."""
+    import os
+    import torch
+    from oracle.oracle import Oracle
+    log("[full size] 271-pin hexagon, 33 groups: one FP32 sweep vs the oracle")
+    prob = P.config(4)
+    th = max(1, min(16, os.cpu_count() or 1))
+    o = Oracle.from_problem(prob, threads=th)
+    o.set_threads(th)
+    s = moc.Solver(prob, precision="f32")
+    assert s.info["n_groups"] == 33
+    rng = np.random.default_rng(4)
+    src = rng.uniform(0.1, 2.0, size=(s.R, s.G))
+    psi = rng.uniform(0, 1, size=s.psi_shape()).astype(np.float32).astype(np.float64)
+    o.set_psi(psi)
+    ref = o.sweep(src)
+    phi, ex = _sweep(s, _dev(src, cuda), _dev(psi, cuda), cuda)
+    phi = _host(phi)
+    err = np.max(np.abs(phi - ref) / ref)
+    log(f"  max rel err {err:.2e}")
+    assert err < 1e-5
+    np.testing.assert_allclose(_host(ex), o.get_exit_psi(), rtol=1e-5, atol=1e-6)
+    del s, ex
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("cfg", [3, 4])

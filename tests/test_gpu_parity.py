@@ -236,7 +236,7 @@ def test_growing_residual_guess_falls_back(oracle_solutions, cuda):
     assert warm["sweeps"] == warm["iterations"] + 2
 
 
-@pytest.mark.parametrize("exp_mode", ["poly", "table", "libm"])
+@pytest.mark.parametrize("exp_mode", ["diff", "table", "libm"])
 def test_exp_modes_sweep_parity(exp_mode, cuda):
     log(f"[sweep parity] exp mode {exp_mode}")
     prob = P.square_lattice(3, 2, seed=3, n_azim=32, spacing=0.05, bc=(1, 0, 1, 0))
