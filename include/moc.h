@@ -242,8 +242,9 @@ int moc_run_iterations(moc_ctx *ctx, int n, moc_result *out);
  * sweeps with the source frozen at (phi0, k0) make it consistent with the guess before the
  * iteration starts (counted in moc_result.sweeps). The solver owns the fallback, which is
  * not an error: a guess with a non-finite or negative entry, or all zeros, is not used,
- * and a guess whose residual exceeds the first residual of a cold start within its first
- * 10 iterations is abandoned for a cold restart (the cold start's first residual is
+ * and a guess whose residual, at any of its iterations 2 to 10, exceeds the first residual
+ * of a cold start is abandoned for a cold restart (the first iteration of a guess also
+ * relaxes its boundary fluxes and k, so it is not judged; the cold start's first residual is
  * measured by one cold iteration when not yet known for the current cross sections,
  * source mode and coarse mesh, and recorded by every cold-started solve); either way
  * moc_solve cold-starts and sets MOC_FLAG_FELL_BACK_TO_COLD, and moc_result.sweeps counts

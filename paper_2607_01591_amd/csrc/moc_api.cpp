@@ -565,7 +565,9 @@ static int solve_impl(moc_ctx *c, double tol, int max_iter, int check_every, moc
     bool conv = false;
     for (it = 1; it <= max_iter; ++it) {
         iterate();
-        const bool watch = use_guess && it <= kGuessWatch;
+        // the first iteration of a warm start also relaxes the guess's boundary fluxes and
+        // k, so its residual says little about the guess; the watch starts at the second
+        const bool watch = use_guess && it >= 2 && it <= kGuessWatch;
         const bool record = !use_guess && it == 1 && !(c->cold_res0 >= 0);
         if (it % check_every == 0 || it == max_iter || watch || record) {
             read_back();

@@ -1,9 +1,9 @@
 """Learned warm start on the GPU: the trained network's guess (BF16 matrix-core
 inference) must lead the power iteration to the same converged answer as the cold start
-without costing sweeps, and a corrupted prediction must fall back to the cold start. The
-comparison runs the FP64 sweep to a tight tolerance so that the two converged answers
-can be compared closely (the network's guess itself is precision-independent). How many
-sweeps the guess saves is measured by the benchmark, not asserted here."""
+(FP64 sweep to a tight tolerance, so the two answers can be compared closely), must save
+sweeps and wall time over 8 held-out seeds against the cold start and the non-learned
+guess, and against CMFD alone when combined with it; a corrupted prediction must fall
+back to the cold start."""
 import os
 import sys
 
@@ -36,10 +36,10 @@ def setup(cuda):
 
 
 @pytest.mark.parametrize("seed", [200000, 200001])
-def test_warm_start_same_answer_fewer_sweeps(seed, setup, cuda):
-    from paper_2607_01591_amd.warmstart import homogenized_guess
+def test_warm_start_same_answer(seed, setup, cuda):
+    """The network's guess leads the iteration to the cold start's fixed point."""
     s, ws = setup
-    log(f"[warm start] seed {seed}")
+    log(f"[warm start] seed {seed}: same answer")
     p = P.config(5, seed=seed)
     s.set_materials(p)
     cold = s.solve(1e-9)
@@ -51,11 +51,56 @@ def test_warm_start_same_answer_fewer_sweeps(seed, setup, cuda):
     assert abs(warm["k"] - cold["k"]) < 1e-8
     assert np.max(np.abs(phi_w - phi_c) / phi_c) < 1e-6
     log(f"  cold {cold['sweeps']} sweeps, warm {warm['sweeps']} sweeps")
-    assert warm["sweeps"] <= 1.05 * cold["sweeps"] + 5
-    s.set_initial_guess(homogenized_guess(p, s.volumes(), cuda), -1.0)
-    hom = s.solve(1e-9)
-    log(f"  homogenised guess {hom['sweeps']} sweeps")
-    assert hom["converged"] and abs(hom["k"] - cold["k"]) < 1e-8
+
+
+HELD_OUT = list(range(200000, 200008))
+
+
+def test_warm_start_saves_sweeps_on_held_out_seeds(cuda):
+    """What the trained network gains, on 8 held-out seeds of the 17 x 17 family with the
+    FP32 sweep to a 1e-6 residual: in total, the network's guess (prediction time included
+    in its wall time) takes fewer sweeps and less wall time than the cold start and fewer
+    sweeps than the non-learned guess (flat flux, spectrum of the homogenised lattice); on
+    top of CMFD it takes fewer sweeps than CMFD from a cold start."""
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("no trained warm-start weights in the tree")
+    from paper_2607_01591_amd.warmstart import WarmStart, homogenized_guess, load_net
+    base = P.config(5, seed=100000)
+    s = moc.Solver(base, precision="f32", max_iter=20000, check_every=10)
+    ws = WarmStart(s, base, cuda, net=load_net(WEIGHTS, cuda, base.n_groups))
+    n_cells, region_cell = P.coarse_cells(base, 17, 17)
+    V = s.volumes()
+    tot = dict(cold=0, warm=0, hom=0, cmfd=0, warm_cmfd=0, cold_ms=0.0, warm_ms=0.0)
+    s.run_iterations(1)   # first-use costs outside the timed solves
+    for seed in HELD_OUT:
+        p = P.config(5, seed=seed)
+        s.set_coarse_mesh(0)
+        s.set_materials(p)
+        cold = s.solve(1e-6)
+        warm = ws.solve_warm(p, 1e-6)
+        s.set_initial_guess(homogenized_guess(p, V, cuda), -1.0)
+        hom = s.solve(1e-6)
+        s.set_coarse_mesh(n_cells, region_cell)
+        cm = s.solve(1e-6)
+        wcm = ws.solve_warm(p, 1e-6)
+        for r in (cold, warm, hom, cm, wcm):
+            assert r["converged"]
+        tot["cold"] += cold["sweeps"]
+        tot["warm"] += warm["sweeps"]
+        tot["hom"] += hom["sweeps"]
+        tot["cmfd"] += cm["sweeps"]
+        tot["warm_cmfd"] += wcm["sweeps"]
+        tot["cold_ms"] += cold["wall_ms"]
+        tot["warm_ms"] += warm["total_ms"]
+        log(f"  seed {seed}: cold {cold['sweeps']}, warm {warm['sweeps']} (flags {warm['flags']}), "
+            f"non-learned {hom['sweeps']}, CMFD {cm['sweeps']}, warm + CMFD {wcm['sweeps']} sweeps; "
+            f"cold {cold['wall_ms']:.0f} ms, warm {warm['total_ms']:.0f} ms")
+    s.set_coarse_mesh(0)
+    log(f"  totals: {tot}")
+    assert tot["warm"] < tot["cold"]
+    assert tot["warm"] < tot["hom"]
+    assert tot["warm_ms"] < tot["cold_ms"]
+    assert tot["warm_cmfd"] < tot["cmfd"]
 
 
 def test_corrupted_prediction_falls_back(setup, cuda):
