@@ -765,7 +765,8 @@ void launch_tally_bound(const DevProblem &d, const void *psi_in, hipStream_t s) 
     hipLaunchKernelGGL(k_fill_u32<unsigned>, dim3(1), dim3(64), 0, s, d.tally_bound, (int64_t)d.Gp);
     const size_t lds = sizeof(unsigned) * (size_t)d.Gp;
     if (lds > 64 * 1024) throw Error(MOC_EINVAL, "sweep: too many groups for the flux bound");
-    hipLaunchKernelGGL(k_tally_bound, dim3(grid_for((int64_t)d.R * d.Gp + npsi, 256, 2048)), dim3(256), lds, s,
+    // few blocks: every block ends with one global atomic per group on the same Gp words
+    hipLaunchKernelGGL(k_tally_bound, dim3(grid_for((int64_t)d.R * d.Gp + npsi, 1024, 256)), dim3(1024), lds, s,
                        (const float *)d.xsq, (const float *)psi_in, d.R, d.Gp, npsi, d.nslots, d.tally_bound);
     MOC_CHECK_LAUNCH();
 }
