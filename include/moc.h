@@ -172,12 +172,13 @@ typedef struct {
 /* Convergence controls of the CMFD coarse solve (moc_set_coarse_mesh). Zero fields take
  * the defaults. */
 typedef struct {
-    double tol;          /* relative change of k and of the coarse flux that ends the coarse
-                            power iteration; the BiCGSTAB solves stop at tol / 10 relative
-                            residual (default 1e-5) */
+    double tol;          /* largest relative change of k and of the coarse flux that ends
+                            the coarse power iteration; each step uses the smaller of tol and
+                            a tenth of the last power iteration's residual, and the BiCGSTAB
+                            solves stop at a tenth of that relative residual (default 1e-3) */
     double shift;        /* Wielandt shift k_s = k (1 + shift), applied once k has settled
-                            (default 0.02; negative: never shift) */
-    int32_t max_outer;   /* coarse power iterations per CMFD step (default 20) */
+                            and then kept for the step (default 0.02; negative: never shift) */
+    int32_t max_outer;   /* coarse power iterations per CMFD step (default 8) */
     int32_t max_inner;   /* BiCGSTAB iterations per coarse linear solve (default 200) */
     int32_t coarse_blocks; /* coarse solve on one 1024-thread workgroup (1) or on a
                               cooperative grid of this many 256-thread blocks (2..256);

@@ -916,9 +916,11 @@ static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell,
     cd.C = n_cells;
     cd.Ns = Ns;
     cd.nadj = (int)adj_surf.size();
-    cd.tol = o.tol > 0 ? o.tol : 1e-5;
+    cd.max_deg = 0;
+    for (int k = 0; k < n_cells; ++k) cd.max_deg = std::max(cd.max_deg, (int)(adj_off[k + 1] - adj_off[k]));
+    cd.tol = o.tol > 0 ? o.tol : 1e-3;
     cd.shift = o.shift > 0 ? o.shift : (o.shift < 0 ? 0.0 : 0.02);
-    cd.max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    cd.max_outer = o.max_outer > 0 ? o.max_outer : 8;
     cd.max_inner = o.max_inner > 0 ? o.max_inner : 200;
     cd.blocks = o.coarse_blocks;
     if (!c->host_only) {
@@ -943,11 +945,11 @@ static void set_coarse_impl(moc_ctx *c, int n_cells, const int32_t *region_cell,
         cd.Ldiag = c->dalloc<double>(N);
         cd.fchi = c->dalloc<double>(N);
         cd.fnsf = c->dalloc<double>(N);
-        cd.vec = c->dalloc<double>(10 * N);
+        cd.vec = c->dalloc<double>((size_t)kCmfdVectors * N);
         cd.ratio = c->dalloc<double>(N);
         cd.stats = c->dalloc<double>(4);
         cd.piv = c->dalloc<int>(N);
-        cd.red = c->dalloc<double>(3 * 2 * 256);
+        cd.red = c->dalloc<double>(kCmfdRedDoubles);
         int coop = 0;
         HIP_OK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
         cd.grid_ok = coop != 0;

@@ -14,16 +14,14 @@
 // on the domain boundary. Homogenisation is flux-volume weighted with the track volumes.
 //
 // Solver: inverse power iteration M y = (1/k) F x (Wielandt shift k_s = k (1 + shift) once
-// k has settled), each linear solve by BiCGSTAB preconditioned with the inverse of every
-// cell's G x G diagonal block. The whole coarse solve runs in one 1024-thread workgroup:
-// the coarse problem is small (cells x groups unknowns) and the solver is a chain of
-// dependent reductions, so one compute unit with workgroup barriers beats a chain of
-// grid-wide launches. All arithmetic is FP64.
+// k has settled, then fixed for the step), each linear solve by BiCGSTAB preconditioned
+// with the inverse of every cell's G x G diagonal block. The solver is a chain of
+// dependent reductions, so it runs as one launch: small coarse problems in one
+// 1024-thread workgroup (workgroup barriers), larger ones on a cooperative grid with its
+// own grid-wide barrier (below), never as a chain of launches. All arithmetic is FP64.
 #include <algorithm>
 #include <cmath>
 #include <string>
-
-#include <hip/hip_cooperative_groups.h>
 
 #include "moc_kernels.h"
 
@@ -112,25 +110,40 @@ struct SolveArgs {
     const double *adj_sign, *adj_L, *adj_h, *adj_hn;
     double *Bs, *Binv, *Aoff, *phih, *Dc, *Ldiag, *fchi, *fnsf, *vec, *ratio, *stats, *scal;
     int *piv;
-    double *red;               // [3 slots][2 values][kMaxGridBlocks] block partials (grid team)
+    double *red;               // exchange area of the grid team (kCmfdRedDoubles)
     double tol, shift;
     int max_outer, max_inner;
+    int max_deg;               // most surfaces of any cell
 };
 
 constexpr int kMaxGridBlocks = 256;
+// k counts as settled for the Wielandt shift when the last power iteration moved it by
+// less than kSettled (relative), or the coarse iteration by less than kSettledCoarse
+constexpr double kSettled = 1e-4, kSettledCoarse = 1e-4;
+constexpr int kGridThreads = 256;   // threads per block of the cooperative solve (512 measured the same)
 constexpr int64_t kGridSolveMinUnknowns = 4096;
 
-// sum of v over the block, returned to every thread of the block (fixed order)
-__device__ double block_sum_all(double v, double *sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// sums of v[0..NV) over the block, returned to every thread of the block (same order in
+// every block); sh holds kMaxSums x 16 doubles
+constexpr int kMaxSums = 6;
+template <int NV> __device__ void block_sum_all(double (&v)[NV], double *sh) {
+    static_assert(NV <= kMaxSums, "too many sums");
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_down(v[j], off, 64);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     __syncthreads();
-    if (l == 0) sh[w] = v;
+    if (l == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) sh[j * 16 + w] = v[j];
     __syncthreads();
-    double t = 0.0;
     const int nw = blockDim.x >> 6;
-    for (int i = 0; i < nw; ++i) t += sh[i];
-    return t;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < nw; ++i) t += sh[j * 16 + i];
+        v[j] = t;
+    }
 }
 
 // The solver runs either in one workgroup (Team = WG) or in a cooperative grid (Team =
@@ -142,49 +155,107 @@ struct WG {
     __device__ int64_t size() const { return blockDim.x; }
     __device__ bool leader() const { return threadIdx.x == 0; }
     __device__ void sync() const { __syncthreads(); }
-    __device__ void sum2(double &a, double &b) {
-        a = block_sum_all(a, sh);
-        b = block_sum_all(b, sh);
-    }
+    __device__ bool failed() const { return false; }
+    static constexpr bool kRegRows = false;   // 1024 threads: too few registers per thread
+    template <int NV> __device__ void sum(double (&v)[NV]) { block_sum_all(v, sh); }
 };
 
-struct GridTeam {
-    double *sh;
-    double *red;
-    int slot;
+// Grid-wide barrier and reduction without a shared counter. Every block owns two 128-byte
+// lines in the exchange area (picked by the parity of its barrier count): at a barrier its
+// thread 0 stores the block's partial sums and then, with release ordering at device
+// scope, the count itself; thread i of every block waits for block i's line to reach the
+// count, reads the partials after an acquire fence, and the block sums them in block
+// order. Waiting on nb separate lines in parallel costs about one memory round trip
+// whatever nb is, where a shared arrival counter serialises nb atomics (measured 0.3 us
+// per block and barrier). Two lines suffice: a block can only rewrite a line after
+// passing the next barrier, which every reader of the line's previous value has reached
+// after reading it. The area is zeroed before every launch. Waits are bounded: a wait
+// longer than 2 s raises the abort word, every block then skips all
+// remaining waits, and the aborted blocks' coarse ratios are NaN, which the host's
+// finiteness check on the iterate reports.
+constexpr int kLine = 16;                 // doubles per exchange line
+constexpr unsigned long long kWaitLimitTicks = 200000000ull;   // 2 s of the 100 MHz real-time clock
+
+__device__ bool wait_count(const double *line, unsigned long long want, unsigned *abort_word) {
+    const unsigned long long *cnt = reinterpret_cast<const unsigned long long *>(line);
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    for (unsigned n = 0;; ++n) {
+        if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
+        if ((n & 63) == 63) {
+            if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+            if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitLimitTicks) {
+                __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+template <int kThreads> struct GridTeam {
+    double *sh;          // LDS, kMaxSums x 16 doubles
+    int *lds_abort;      // LDS flag: a wait of this block gave up
+    double *red;         // exchange area (global): lines of [count, values...]
+    unsigned long long count = 0;
+    bool aborted = false;
     __device__ int64_t tid() const { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
     __device__ int64_t size() const { return (int64_t)gridDim.x * blockDim.x; }
     __device__ bool leader() const { return blockIdx.x == 0 && threadIdx.x == 0; }
-    __device__ void sync() const { cooperative_groups::this_grid().sync(); }
-    // each block's partials go to a slot, one grid barrier, then every block sums the
-    // slot in the same order; three slots rotate so a slot is rewritten only after every
-    // block has read it (two barriers later)
-    __device__ void sum2(double &a, double &b) {
-        a = block_sum_all(a, sh);
-        b = block_sum_all(b, sh);
-        double *r = red + (size_t)slot * 2 * kMaxGridBlocks;
-        if (threadIdx.x == 0) {
-            r[blockIdx.x] = a;
-            r[kMaxGridBlocks + blockIdx.x] = b;
+    __device__ bool failed() const { return aborted; }
+    static constexpr bool kRegRows = kThreads <= 512;   // 1024 threads: too few registers
+    // v: this block's sums (the same in every thread); returns the grid's sums, added in
+    // block order in every block
+    template <int NV> __device__ void exchange(double (&v)[NV]) {
+        static_assert(NV + 1 <= kLine, "exchange line too short");
+        ++count;
+        const int par = int(count & 1);
+        unsigned *abort_word = reinterpret_cast<unsigned *>(red + (size_t)kMaxGridBlocks * 2 * kLine);
+        if (threadIdx.x == 0 && !aborted) {
+            double *mine = red + ((size_t)blockIdx.x * 2 + par) * kLine;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) mine[1 + j] = v[j];
+            __hip_atomic_store(reinterpret_cast<unsigned long long *>(mine), count, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        slot = (slot + 1) % 3;
-        sync();
-        const int nb = gridDim.x;
-        double pa = threadIdx.x < nb ? r[threadIdx.x] : 0.0;
-        double pb = threadIdx.x < nb ? r[kMaxGridBlocks + threadIdx.x] : 0.0;
-        a = block_sum_all(pa, sh);
-        b = block_sum_all(pb, sh);
+        double p[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) p[j] = 0.0;
+        if ((int)threadIdx.x < (int)gridDim.x && !aborted) {
+            const double *line = red + ((size_t)threadIdx.x * 2 + par) * kLine;
+            if (wait_count(line, count, abort_word)) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+                for (int j = 0; j < NV; ++j) p[j] = line[1 + j];
+            } else {
+                *lds_abort = 1;
+            }
+        }
+        // the block sums' workgroup barriers order the other threads after the waits
+        block_sum_all(p, sh);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = p[j];
+        if (*lds_abort) aborted = true;
+    }
+    __device__ void sync() {
+        __syncthreads();   // the block's writes before thread 0's release
+        double z[1] = {0.0};
+        exchange(z);
+    }
+    template <int NV> __device__ void sum(double (&v)[NV]) {
+        block_sum_all(v, sh);   // its barriers also order the block's writes before the release
+        exchange(v);
     }
 };
 
 template <typename Team> __device__ double team_sum(Team &T, double v) {
-    double z = 0.0;
-    T.sum2(v, z);
-    return v;
+    double z[1] = {v};
+    T.sum(z);
+    return z[0];
 }
 
-// vectors of vec: x (eigenvector), y (solve), r, rh, p (two), v, t, yp, zs
-enum { kVx = 0, kVy, kVr, kVrh, kVp0, kVp1, kVv, kVt, kVyp, kVzs, kNumVec };
+// vectors of vec: x (eigenvector), y (solve), r (two), rh, p (two), v, t, yp, zs
+enum { kVx = 0, kVy, kVr0, kVr1, kVrh, kVp0, kVp1, kVv, kVt, kVyp, kVzs, kNumVec };
+static_assert(kNumVec == kCmfdVectors, "solver vector count");
 
 template <typename Team> __device__ void build_blocks(Team &T, const SolveArgs &a, double inv_ks) {
     const int C = a.C, G = a.G, HS = 2 + 4 * G + G * G;
@@ -263,37 +334,89 @@ template <typename Team> __device__ void build_blocks(Team &T, const SolveArgs &
     T.sync();
 }
 
-// row i of A x (shifted coarse operator)
-__device__ __forceinline__ double row_apply(const SolveArgs &a, const double *x, int64_t i) {
-    const int G = a.G;
-    const int c = int(i / G), g = int(i - (int64_t)c * G);
-    const double *B = a.Bs + i * G;
-    const double *xc = x + (int64_t)c * G;
-    double s = 0.0;
-    for (int gp = 0; gp < G; ++gp) s += B[gp] * xc[gp];
-    for (int64_t k = a.adj_off[c]; k < a.adj_off[c + 1]; ++k) {
-        const int j = a.adj_nbr[k];
-        if (j >= 0) s += a.Aoff[k * G + g] * x[(int64_t)j * G + g];
+// Row i of the shifted coarse operator and of the block-Jacobi preconditioner, in two
+// forms: read from global memory at every use (any size), or held in registers for the
+// whole linear solve by the thread that owns the row (every thread owns at most one row,
+// at most kRegG groups and kRegDeg surfaces per cell). Both sum in the same order.
+struct MemRows {
+    __device__ void load(const SolveArgs &, int64_t) {}
+    __device__ double apply(const SolveArgs &a, const double *x, int64_t i) const {
+        const int G = a.G;
+        const int c = int(i / G), g = int(i - (int64_t)c * G);
+        const double *B = a.Bs + i * G;
+        const double *xc = x + (int64_t)c * G;
+        double s = 0.0;
+        for (int gp = 0; gp < G; ++gp) s += B[gp] * xc[gp];
+        for (int64_t k = a.adj_off[c]; k < a.adj_off[c + 1]; ++k) {
+            const int j = a.adj_nbr[k];
+            if (j >= 0) s += a.Aoff[k * G + g] * x[(int64_t)j * G + g];
+        }
+        return s;
     }
-    return s;
-}
+    // sum over the cell's groups g' of Binv(i, g') u(cell row of g')
+    template <typename U> __device__ double precond(const SolveArgs &a, int64_t i, U u) const {
+        const int G = a.G;
+        const int64_t c0 = (i / G) * G;
+        const double *K = a.Binv + i * G;
+        double s = 0.0;
+        for (int gp = 0; gp < G; ++gp) s += K[gp] * u(c0 + gp);
+        return s;
+    }
+};
 
-// row i of the block-Jacobi preconditioner applied to u = r + beta (p - omega v) built on
-// the fly from the cell's entries (so no barrier is needed between forming u and using it)
-__device__ __forceinline__ double row_precond_lin(const SolveArgs &a, int64_t i, const double *r, const double *p,
-                                                  const double *v, double beta, double omega, double *u_out) {
-    const int G = a.G;
-    const int c = int(i / G);
-    const double *B = a.Binv + i * G;
-    const int64_t c0 = (int64_t)c * G;
-    double s = 0.0;
-    for (int gp = 0; gp < G; ++gp) {
-        const double u = r[c0 + gp] + beta * (p[c0 + gp] - omega * v[c0 + gp]);
-        s += B[gp] * u;
+constexpr int kRegG = 16, kRegDeg = 8;
+struct RegRows {
+    double B[kRegG], K[kRegG], off[kRegDeg];
+    int nbr[kRegDeg];       // neighbour's row (same group), -1: none
+    int c0 = 0;
+    int G = 0;
+    __device__ void load(const SolveArgs &a, int64_t i) {
+        G = a.G;
+#pragma unroll
+        for (int e = 0; e < kRegG; ++e) B[e] = K[e] = 0.0;
+#pragma unroll
+        for (int e = 0; e < kRegDeg; ++e) {
+            off[e] = 0.0;
+            nbr[e] = -1;
+        }
+        if (i >= (int64_t)a.C * G) return;
+        const int c = int(i / G), g = int(i - (int64_t)c * G);
+        c0 = c * G;
+#pragma unroll
+        for (int e = 0; e < kRegG; ++e)
+            if (e < G) {
+                B[e] = a.Bs[i * G + e];
+                K[e] = a.Binv[i * G + e];
+            }
+        const int64_t k0 = a.adj_off[c], k1 = a.adj_off[c + 1];
+#pragma unroll
+        for (int e = 0; e < kRegDeg; ++e)
+            if (k0 + e < k1) {
+                const int j = a.adj_nbr[k0 + e];
+                if (j >= 0) {
+                    nbr[e] = j * G + g;
+                    off[e] = a.Aoff[(k0 + e) * G + g];
+                }
+            }
     }
-    u_out[i] = r[i] + beta * (p[i] - omega * v[i]);
-    return s;
-}
+    __device__ double apply(const SolveArgs &, const double *x, int64_t) const {
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < kRegG; ++e)
+            if (e < G) s += B[e] * x[c0 + e];
+#pragma unroll
+        for (int e = 0; e < kRegDeg; ++e)
+            if (nbr[e] >= 0) s += off[e] * x[nbr[e]];
+        return s;
+    }
+    template <typename U> __device__ double precond(const SolveArgs &, int64_t, U u) const {
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < kRegG; ++e)
+            if (e < G) s += K[e] * u(c0 + e);
+        return s;
+    }
+};
 
 // (F x)_c,g = fchi_c,g sum_g' fnsf_c,g' x_c,g'; returns sum of F x, writes scale F x if out
 template <typename Team>
@@ -315,89 +438,106 @@ __device__ double apply_F(Team &T, const SolveArgs &a, const double *x, double *
 }
 
 // BiCGSTAB (right block-Jacobi preconditioning) on A y = b, y holds the initial guess;
-// stops at ||r|| <= rtol ||b||. Returns the iterations taken. Barriers: one per
-// reduction (four per iteration) plus one before each product with A.
-template <typename Team> __device__ int bicgstab(Team &T, const SolveArgs &a, const double *b, double rtol, int max_it) {
+// stops at ||r|| <= rtol ||b||. Returns the iterations taken. Four grid barriers per
+// iteration: (1) after p and K^-1 p, (2) the reduction (rh, v), (3) after zs = K^-1 s,
+// (4) one reduction of (t, s), (t, t), (rh, s), (rh, t), (s, s), from which omega, the
+// new residual's norm ||s - omega t||^2 = (s,s) - 2 omega (t,s) + omega^2 (t,t) and
+// (rh, r) = (rh, s) - omega (rh, t) follow without a fifth one. The residual r_n+1 of a
+// row is stored by its owner after barrier (4), so the next iteration's cell-wise steps
+// (which read the rows of other threads) form r_n+1 = r_n - alpha v - omega t from the
+// published r_n, v and t; r and p alternate between two buffers so that no value is
+// overwritten while another thread may still read it.
+template <typename Team, typename Rows>
+__device__ int bicgstab(Team &T, const SolveArgs &a, const Rows &R, const double *b, double rtol, int max_it) {
     const int64_t N = (int64_t)a.C * a.G;
     double *V = a.vec;
-    double *y = V + kVy * N, *r = V + kVr * N, *rh = V + kVrh * N, *v = V + kVv * N;
+    double *y = V + kVy * N, *rh = V + kVrh * N, *v = V + kVv * N;
     double *t = V + kVt * N, *yp = V + kVyp * N, *zs = V + kVzs * N;
-    double *pa = V + kVp0 * N, *pb = V + kVp1 * N;
-    double bb = 0.0, rr = 0.0;
+    double *rs[2] = {V + kVr0 * N, V + kVr1 * N};
+    double *ps[2] = {V + kVp0 * N, V + kVp1 * N};
+    double s0[2] = {0.0, 0.0};   // (b, b), (r, r)
     for (int64_t i = T.tid(); i < N; i += T.size()) {
-        const double ri = b[i] - row_apply(a, y, i);
-        r[i] = ri;
+        const double ri = b[i] - R.apply(a, y, i);
+        rs[0][i] = ri;
+        rs[1][i] = ri;
         rh[i] = ri;
-        pa[i] = 0.0;
+        ps[0][i] = 0.0;
         v[i] = 0.0;
-        bb += b[i] * b[i];
-        rr += ri * ri;
+        t[i] = 0.0;
+        s0[0] += b[i] * b[i];
+        s0[1] += ri * ri;
     }
-    T.sum2(bb, rr);
-    const double stop = rtol * rtol * bb;
-    if (rr <= stop) return 0;
+    T.sum(s0);
+    const double stop = rtol * rtol * s0[0];
+    if (s0[1] <= stop) return 0;
     double rho = 1.0, alpha = 1.0, omega = 1.0;
-    double rn = rr;   // (rh, r) with rh = r
+    double rn = s0[1];                 // (rh, r) with rh = r
+    double al_prev = 0.0, om_prev = 0.0;   // the update that turns rs[cur ^ 1] into r_n
+    int cur = 1;                       // rs[cur] holds r_n (stored by the rows' owners)
     int it = 0;
     for (it = 1; it <= max_it; ++it) {
         if (rn == 0.0 || omega == 0.0) break;   // breakdown: keep the current y
         const double beta = (rn / rho) * (alpha / omega);
         rho = rn;
-        // p_new = r + beta (p - omega v) and yp = K^-1 p_new, cell by cell
-        for (int64_t i = T.tid(); i < N; i += T.size()) yp[i] = row_precond_lin(a, i, r, pa, v, beta, omega, pb);
+        // p_n = r_n + beta (p_n-1 - omega v), yp = K^-1 p_n, from the cell's published rows
+        {
+            const double *rp = rs[cur ^ 1], *pp = ps[(it - 1) & 1];
+            double *pn = ps[it & 1];
+            const double bt = it == 1 ? 0.0 : beta, om = omega, ap = al_prev, op = om_prev;
+            auto pcell = [&](int64_t j) { return (rp[j] - ap * v[j] - op * t[j]) + bt * (pp[j] - om * v[j]); };
+            for (int64_t i = T.tid(); i < N; i += T.size()) {
+                yp[i] = R.precond(a, i, pcell);
+                pn[i] = pcell(i);
+            }
+        }
         T.sync();
-        double rv = 0.0, z0 = 0.0;
+        double s1[1] = {0.0};   // (rh, v)
         for (int64_t i = T.tid(); i < N; i += T.size()) {
-            const double vi = row_apply(a, yp, i);
+            const double vi = R.apply(a, yp, i);
             v[i] = vi;
-            rv += rh[i] * vi;
+            s1[0] += rh[i] * vi;
         }
-        T.sum2(rv, z0);
-        if (rv == 0.0) break;
-        alpha = rho / rv;
-        // s = r - alpha v (kept in r's place is not possible: zs needs the cell's s),
-        // zs = K^-1 s from the cell's entries
-        double ss = 0.0, z1 = 0.0;
+        T.sum(s1);
+        if (s1[0] == 0.0) break;
+        alpha = rho / s1[0];
+        // zs = K^-1 s, s = r_n - alpha v, from the cell's rows
+        {
+            const double *rc = rs[cur];
+            const double al = alpha;
+            auto scell = [&](int64_t j) { return rc[j] - al * v[j]; };
+            for (int64_t i = T.tid(); i < N; i += T.size()) zs[i] = R.precond(a, i, scell);
+        }
+        T.sync();
+        double s5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s) (t,t) (rh,s) (rh,t) (s,s)
         for (int64_t i = T.tid(); i < N; i += T.size()) {
-            const int c = int(i / a.G);
-            const int64_t c0 = (int64_t)c * a.G;
-            const double *Bi = a.Binv + i * a.G;
-            double z = 0.0;
-            for (int gp = 0; gp < a.G; ++gp) z += Bi[gp] * (r[c0 + gp] - alpha * v[c0 + gp]);
-            zs[i] = z;
-            const double si = r[i] - alpha * v[i];
-            ss += si * si;
+            const double ti = R.apply(a, zs, i);
+            t[i] = ti;
+            const double si = rs[cur][i] - alpha * v[i];
+            s5[0] += ti * si;
+            s5[1] += ti * ti;
+            s5[2] += rh[i] * si;
+            s5[3] += rh[i] * ti;
+            s5[4] += si * si;
         }
-        T.sum2(ss, z1);
-        if (ss <= stop) {
+        T.sum(s5);
+        if (s5[4] <= stop) {
+            // s already small enough: y += alpha yp and stop
             for (int64_t i = T.tid(); i < N; i += T.size()) y[i] += alpha * yp[i];
-            T.sync();
             break;
         }
-        double ts = 0.0, tt = 0.0;
-        for (int64_t i = T.tid(); i < N; i += T.size()) {
-            const double ti = row_apply(a, zs, i);
-            t[i] = ti;
-            const double si = r[i] - alpha * v[i];
-            ts += ti * si;
-            tt += ti * ti;
-        }
-        T.sum2(ts, tt);
-        omega = tt > 0.0 ? ts / tt : 0.0;
-        rr = 0.0;
-        rn = 0.0;
+        omega = s5[1] > 0.0 ? s5[0] / s5[1] : 0.0;
+        // r_n+1 = s - omega t into the other buffer (its r_n-1 was last read before
+        // barrier (1) of this iteration)
+        double *rn1 = rs[cur ^ 1];
         for (int64_t i = T.tid(); i < N; i += T.size()) {
             y[i] += alpha * yp[i] + omega * zs[i];
-            const double ri = r[i] - alpha * v[i] - omega * t[i];
-            r[i] = ri;
-            rr += ri * ri;
-            rn += rh[i] * ri;
+            rn1[i] = (rs[cur][i] - alpha * v[i]) - omega * t[i];
         }
-        T.sum2(rr, rn);
-        // the new p lives in pb: swap the roles of the two p buffers
-        double *tmp = pa;
-        pa = pb;
-        pb = tmp;
+        const double rr = fmax(0.0, s5[4] - 2.0 * omega * s5[0] + omega * omega * s5[1]);
+        rn = s5[2] - omega * s5[3];
+        al_prev = alpha;
+        om_prev = omega;
+        cur ^= 1;
         if (rr <= stop) break;
     }
     T.sync();
@@ -459,40 +599,62 @@ template <typename Team> __device__ void coarse_solve(Team &T, const SolveArgs &
     // last power iteration well inside the shift margin); otherwise after the first
     // coarse iterations have settled it
     const double dk_prev = a.scal[kScalDk];
-    bool shifted = a.shift > 0 && isfinite(dk_prev) && dk_prev < 1e-4 * k;
+    bool shifted = a.shift > 0 && isfinite(dk_prev) && dk_prev < kSettled * k;
     double inv_ks = shifted ? 1.0 / (k * (1.0 + a.shift)) : 0.0;    // 0: unshifted
     int outer = 0, inner_total = 0;
+    double built = -1.0;   // inv_ks of the blocks in Bs / Binv
+    // operator rows in registers when every thread owns at most one (the same choice in
+    // every thread)
+    const bool regs = T.size() >= N && N < (int64_t)1 << 31 && G <= kRegG && a.max_deg <= kRegDeg;
     for (outer = 1; outer <= a.max_outer && fs > 0; ++outer) {
-        if (outer == 1 || shifted) build_blocks(T, a, inv_ks);
+        if (inv_ks != built) {
+            build_blocks(T, a, inv_ks);
+            built = inv_ks;
+        }
         const double lam = 1.0 / k - inv_ks;
         // A y = lam F x from y = x
         for (int64_t i = T.tid(); i < N; i += T.size()) y[i] = x[i];
         apply_F(T, a, x, b, lam);
-        inner_total += bicgstab(T, a, b, tol * 0.1, a.max_inner);
+        if constexpr (Team::kRegRows) {
+            if (regs) {
+                RegRows R;
+                R.load(a, T.tid());
+                inner_total += bicgstab(T, a, R, b, tol * 0.1, a.max_inner);
+            } else {
+                inner_total += bicgstab(T, a, MemRows{}, b, tol * 0.1, a.max_inner);
+            }
+        } else {
+            inner_total += bicgstab(T, a, MemRows{}, b, tol * 0.1, a.max_inner);
+        }
         const double fy = apply_F(T, a, y, nullptr, 0.0);
         if (!(fy > 0)) break;
         const double rho = fy / fs;
         const double knew = 1.0 / (inv_ks + lam / rho);
-        double dx = 0.0, nx = 0.0;
+        double d2[2] = {0.0, 0.0};   // ||x_new - x||^2, ||x_new||^2
         const double sc = fs / fy;
         for (int64_t i = T.tid(); i < N; i += T.size()) {
             const double yi = y[i] * sc;
-            dx += (yi - x[i]) * (yi - x[i]);
-            nx += yi * yi;
+            d2[0] += (yi - x[i]) * (yi - x[i]);
+            d2[1] += yi * yi;
             x[i] = yi;
         }
-        T.sum2(dx, nx);
+        T.sum(d2);
+        const double dx = d2[0], nx = d2[1];
         const double dk = fabs(knew - k) / knew;
         k = knew;
         if (dk < tol && dx <= tol * tol * nx) break;
-        // Wielandt shift once k has settled well inside the shift margin
-        if (!shifted && a.shift > 0 && dk < 1e-4) shifted = true;
-        if (shifted) inv_ks = 1.0 / (k * (1.0 + a.shift));
+        // Wielandt shift once k has settled well inside the shift margin; the shift then
+        // stays fixed for the rest of the step (the blocks and their inverses are built
+        // once per shift), which converges as fast as following k here
+        if (!shifted && a.shift > 0 && dk < kSettledCoarse) {
+            shifted = true;
+            inv_ks = 1.0 / (k * (1.0 + a.shift));
+        }
     }
     T.sync();
     for (int64_t i = T.tid(); i < N; i += T.size()) {
         const double ph = a.phih[i];
-        a.ratio[i] = ph > 0 ? x[i] / ph : 1.0;
+        a.ratio[i] = T.failed() ? __builtin_nan("") : (ph > 0 ? x[i] / ph : 1.0);
     }
     if (T.leader()) {
         a.scal[kScalKPrev] = a.scal[kScalK];
@@ -505,15 +667,18 @@ template <typename Team> __device__ void coarse_solve(Team &T, const SolveArgs &
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_cmfd_solve(SolveArgs a) {
-    __shared__ double sh[kSolveThreads / 64];
+    __shared__ double sh[kMaxSums * 16];
     WG T{sh};
     coarse_solve(T, a);
 }
 
 // the same solve over a cooperative grid (launched with hipLaunchCooperativeKernel)
-__global__ __launch_bounds__(256) void k_cmfd_solve_grid(SolveArgs a) {
-    __shared__ double sh[4];
-    GridTeam T{sh, a.red, 0};
+template <int kThreads> __global__ __launch_bounds__(kThreads) void k_cmfd_solve_grid(SolveArgs a) {
+    __shared__ double sh[kMaxSums * 16];
+    __shared__ int lds_abort;
+    if (threadIdx.x == 0) lds_abort = 0;
+    __syncthreads();
+    GridTeam<kThreads> T{sh, &lds_abort, a.red};
     coarse_solve(T, a);
 }
 
@@ -593,17 +758,20 @@ void launch_cmfd(const DevProblem &d, const DevCoarse &cd, double *phi, void *ps
     a.shift = cd.shift;
     a.max_outer = cd.max_outer;
     a.max_inner = cd.max_inner;
+    a.max_deg = cd.max_deg;
     // large coarse problems: the same solve spread over a cooperative grid (one block of
     // 256 threads per 256 unknowns, at most kMaxGridBlocks); small ones: one workgroup,
     // whose barriers are cheaper than grid-wide ones
     const int64_t N = (int64_t)cd.C * d.G;
     int nb = cd.blocks;
-    if (nb == 0) nb = N > kGridSolveMinUnknowns ? (int)std::min<int64_t>(kMaxGridBlocks, (N + 255) / 256) : 1;
+    if (nb == 0)
+        nb = N > kGridSolveMinUnknowns ? (int)std::min<int64_t>(kMaxGridBlocks, (N + kGridThreads - 1) / kGridThreads) : 1;
     if (nb > 1 && !cd.grid_ok) throw Error(MOC_EINVAL, "cmfd: the device does not support cooperative launches");
     if (nb > 1) {
+        launch_fill_f64(cd.red, kCmfdRedDoubles, 0.0, s);   // barrier counts start at 0
         void *args[] = {&a};
-        const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cmfd_solve_grid), dim3(nb),
-                                                        dim3(256), args, 0, s);
+        const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cmfd_solve_grid<kGridThreads>), dim3(nb),
+                                                        dim3(kGridThreads), args, 0, s);
         if (e != hipSuccess) throw Error(MOC_EHIP, std::string("cmfd: cooperative launch failed: ") + hipGetErrorString(e));
     } else {
         hipLaunchKernelGGL(k_cmfd_solve, dim3(1), dim3(kSolveThreads), 0, s, a);

@@ -78,6 +78,11 @@ struct DevProblem {
 };
 
 // Coarse mesh (CMFD) device state; see moc_cmfd.hip.
+// exchange area of the cooperative coarse solve: two 128-byte lines per block (at most
+// 256 blocks) and one line for the abort word
+constexpr int64_t kCmfdRedDoubles = (int64_t)256 * 2 * 16 + 16;
+constexpr int kCmfdVectors = 11;   // solver vectors of the coarse solve
+
 struct DevCoarse {
     int C = 0, Ns = 0, nadj = 0;
     int *cell_of = nullptr;           // [R] internal region -> cell
@@ -92,15 +97,16 @@ struct DevCoarse {
     double *Bs = nullptr, *Binv = nullptr;  // [C][G][G] diagonal blocks and their inverses
     double *Aoff = nullptr;           // [nadj][G] neighbour couplings
     double *phih = nullptr, *Dc = nullptr, *Ldiag = nullptr, *fchi = nullptr, *fnsf = nullptr;  // [C][G]
-    double *vec = nullptr;            // [10][C G] solver vectors
+    double *vec = nullptr;            // [kCmfdVectors][C G] solver vectors
     double *ratio = nullptr;          // [C][G]
     double *stats = nullptr;          // [4] outer, inner iterations, coarse k
     int *piv = nullptr;               // [C][G]
-    double *red = nullptr;            // [3][2][256] block partials of the cooperative solve
+    double *red = nullptr;            // [kCmfdRedDoubles] block exchange lines of the cooperative solve
     bool grid_ok = false;             // the device supports cooperative launches
     int blocks = 0;                   // coarse solve blocks (0 automatic, 1 one workgroup)
     double tol = 1e-5, shift = 0.02;
     int max_outer = 20, max_inner = 200;
+    int max_deg = 0;                  // most surfaces of any cell
 };
 
 void launch_cmfd(const DevProblem &d, const DevCoarse &cd, double *phi, void *psi, hipStream_t s);

@@ -119,6 +119,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_01591_amd.build`")
+        # torch first: its wheel carries its own HIP runtime under the same soname as the
+        # system one libmoc links, and the first one loaded serves the whole process. Loaded
+        # the other way round, torch runs on a runtime it was not built with and finds no GPU.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
