@@ -662,19 +662,42 @@ __global__ void k_check_guess(const double *__restrict__ x, int64_t n, double *_
 
 // Per-group bound of the FP32 sweep's fluxes: tally_bound[g] = max over regions of |qhat|
 // and over the incoming boundary fluxes of |psi| (float bit patterns of non-negative
-// values order like the values). Each block takes the maximum per group in LDS, then
-// one global atomic per group; the caller zeroes tally_bound first.
-__global__ void k_tally_bound(const float *__restrict__ xsq, const float *__restrict__ psi, int R, int Gp, int64_t npsi,
-                              int nslots, unsigned *__restrict__ bound) {
+// values order like the values). Maxima are kept in registers and meet in LDS only at the
+// end (a per-element LDS maximum on the block's Gp words serialised: 126 us per sweep at
+// 30 M elements): for qhat each thread keeps one group (thread t takes group t mod Gp of
+// every (T / Gp)-th region, T the grid's threads); psi is stored as 2 P Gp rows of nslots
+// slots, one group per row, and the whole grid walks the rows in order, so each row's
+// maximum is folded into LDS once per wave. No 64-bit index division anywhere. The
+// caller zeroes tally_bound.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void k_tally_bound(const float *__restrict__ xsq, const float *__restrict__ psi, int R,
+                                                      int Gp, int nrows, int nslots, unsigned *__restrict__ bound) {
     extern __shared__ unsigned bmax[];
     for (int g = threadIdx.x; g < Gp; g += blockDim.x) bmax[g] = 0u;
     __syncthreads();
-    const int64_t nq = (int64_t)R * Gp;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq; i += stride)
-        atomicMax(&bmax[i % Gp], __float_as_uint(fabsf(xsq[2 * i + 1])));
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npsi; i += stride)
-        atomicMax(&bmax[(i / nslots) % Gp], __float_as_uint(fabsf(psi[i])));
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t Tg = T / Gp;
+    if (tid < Tg * Gp) {
+        const int g = int(tid % Gp);
+        unsigned m = 0u;
+#pragma unroll 4
+        for (int64_t r = tid / Gp; r < R; r += Tg) m = max(m, __float_as_uint(fabsf(xsq[2 * (r * Gp + g) + 1])));
+        if (m) atomicMax(&bmax[g], m);
+    }
+    for (int q = 0; q < nrows; ++q) {
+        const float *row = psi + (int64_t)q * nslots;
+        unsigned m = 0u;
+#pragma unroll 4
+        for (int64_t j = tid; j < nslots; j += T) m = max(m, __float_as_uint(fabsf(row[j])));
+        const unsigned w = wave_max_u32(m);
+        if ((threadIdx.x & 63) == 0 && w) atomicMax(&bmax[q % Gp], w);
+    }
     __syncthreads();
     for (int g = threadIdx.x; g < Gp; g += blockDim.x)
         if (bmax[g]) atomicMax(&bound[g], bmax[g]);
@@ -766,8 +789,9 @@ void launch_tally_bound(const DevProblem &d, const void *psi_in, hipStream_t s) 
     const size_t lds = sizeof(unsigned) * (size_t)d.Gp;
     if (lds > 64 * 1024) throw Error(MOC_EINVAL, "sweep: too many groups for the flux bound");
     // few blocks: every block ends with one global atomic per group on the same Gp words
-    hipLaunchKernelGGL(k_tally_bound, dim3(grid_for((int64_t)d.R * d.Gp + npsi, 1024, 256)), dim3(1024), lds, s,
-                       (const float *)d.xsq, (const float *)psi_in, d.R, d.Gp, npsi, d.nslots, d.tally_bound);
+    const int nblk = grid_for((int64_t)d.R * d.Gp + npsi, 1024, 256);
+    hipLaunchKernelGGL(k_tally_bound, dim3(nblk), dim3(1024), lds, s, (const float *)d.xsq, (const float *)psi_in, d.R,
+                       d.Gp, 2 * d.P * d.Gp, d.nslots, d.tally_bound);
     MOC_CHECK_LAUNCH();
 }
 
