@@ -5,6 +5,7 @@
 // MFMA 16x16x32 operand layout (per lane l of a wavefront): A supplies row l % 16,
 // k = 8 (l / 16) .. + 7; B supplies column l % 16, the same k; the 16x16 FP32 result
 // holds rows 4 (l / 16) .. + 3 of column l % 16.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <mutex>
@@ -95,6 +96,110 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ x
         }
 }
 
+// Forward with the weights in LDS. Persistent blocks each stage W (Co x 9 x Ci BF16; the
+// rows of one output channel padded by 8 elements so the 16 lanes of an operand read fall
+// on distinct banks) once, then take tiles of 64 MT consecutive pixels of the flattened
+// N x H x W image: wave w owns pixels [16 MT w, 16 MT (w + 1)) of a tile as MT 16-pixel
+// tiles and all Co = 16 NCT output channels, every lane's pixel with its own (n, y, x),
+// so tiles may cross rows and images. The input operands come from global memory (16 bytes,
+// 8 channels of one pixel per lane) and are loaded one (tap, 32-channel) step ahead of the
+// matrix-core products that use them.
+template <int NCT, int MT>
+__global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
+                                                      const float *__restrict__ bias, int N, int H, int W, int Ci,
+                                                      int relu, int dil, uint16_t *__restrict__ yb,
+                                                      float *__restrict__ yf) {
+    constexpr int Co = NCT * 16;
+    extern __shared__ uint4 lds_u4[];
+    uint16_t *const wl = reinterpret_cast<uint16_t *>(lds_u4);
+    const int WS = 9 * Ci + 8;
+    {
+        const int per = 9 * Ci / 8;   // 16-byte pieces per output channel
+        for (int e = threadIdx.x; e < Co * per; e += 256) {
+            const int co = e / per, k = e - co * per;
+            *reinterpret_cast<uint4 *>(wl + co * WS + 8 * k) =
+                *reinterpret_cast<const uint4 *>(w + (int64_t)co * 9 * Ci + 8 * k);
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kb = lane >> 4;
+    const int64_t NP = (int64_t)N * H * W;
+    const int64_t ntile = (NP + 64 * MT - 1) / (64 * MT);
+    const int nc = Ci / 32, nit = 9 * nc;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t pbase = tile * 64 * MT + wv * 16 * MT;
+        int pimg[MT], py[MT], px[MT];
+        bool pv[MT];
+#pragma unroll
+        for (int u = 0; u < MT; ++u) {
+            const int64_t p = pbase + 16 * u + m;
+            pv[u] = p < NP;
+            const int64_t q = pv[u] ? p : 0;
+            px[u] = int(q % W);
+            const int64_t r = q / W;
+            py[u] = int(r % H);
+            pimg[u] = int(r / H);
+        }
+        auto load_a = [&](int it, bf16x8 (&a)[MT]) {
+            const int tap = it / nc, c0 = (it - tap * nc) * 32;
+            const int dy = (tap / 3 - 1) * dil, dx = (tap % 3 - 1) * dil;
+#pragma unroll
+            for (int u = 0; u < MT; ++u) {
+                const int yy = py[u] + dy, xx = px[u] + dx;
+                const bool ib = pv[u] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+                const int64_t off = ib ? (((int64_t)pimg[u] * H + yy) * W + xx) * Ci + c0 + kb * 8 : 0;
+                a[u] = as_bf16x8(ib ? *reinterpret_cast<const uint4 *>(x + off) : make_uint4(0, 0, 0, 0));
+            }
+        };
+        f32x4 acc[MT][NCT];
+#pragma unroll
+        for (int u = 0; u < MT; ++u)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) acc[u][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        auto step = [&](int it, const bf16x8 (&a)[MT]) {
+            const int tap = it / nc, c0 = (it - tap * nc) * 32;
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                const bf16x8 b = as_bf16x8(*reinterpret_cast<const uint4 *>(wl + (16 * c + m) * WS + tap * Ci + c0 + kb * 8));
+#pragma unroll
+                for (int u = 0; u < MT; ++u) acc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b, acc[u][c], 0, 0, 0);
+            }
+        };
+        // the input operands of step it + 2 are loaded while step it computes (three register
+        // sets, unrolled by three so no set is copied; the step count 9 Ci / 32 is a multiple
+        // of three)
+        bf16x8 a0[MT], a1[MT], a2[MT];
+        load_a(0, a0);
+        load_a(1, a1);
+        for (int it = 0; it < nit; it += 3) {
+            load_a(it + 2, a2);
+            step(it, a0);
+            if (it + 3 < nit) load_a(it + 3, a0);
+            step(it + 1, a1);
+            if (it + 4 < nit) load_a(it + 4, a1);
+            step(it + 2, a2);
+        }
+#pragma unroll
+        for (int u = 0; u < MT; ++u)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                const int co = c * 16 + m;
+                const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t pix = pbase + 16 * u + 4 * kb + i;
+                    if (pix >= NP) continue;
+                    float v = acc[u][c][i] + bv;
+                    if (relu) v = fmaxf(v, 0.f);
+                    const int64_t o = pix * Co + co;
+                    if (yb) yb[o] = f2bf(v);
+                    if (yf) yf[o] = v;
+                }
+            }
+    }
+}
+
 // ---------------------------------------------------------------- weight gradient
 // Block (row chunk, tap): rows [r0, r0 + rows) of the N*H image rows. The 16x16
 // output tiles (co, ci) are spread over the 4 wavefronts; K = pixels in steps of 32.
@@ -140,6 +245,206 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     }
 }
 
+// ---------------------------------------------------------------- weight gradient, LDS
+// dw[co][3 ky + kx][ci] += sum over pixels of dz[p][co] x[p + ((ky-1) d, (kx-1) d)][ci]:
+// a GEMM over pixels, so each matrix-core operand needs 8 consecutive pixels of one
+// channel, while NHWC keeps a pixel's channels together. Block (ky, chunk of `rows` image
+// rows); each row is taken in segments of kSeg pixels, staged transposed in LDS
+// (channel-major, pixels contiguous): dzT[co][p] for the segment and xT[ci][p] for the
+// matching x row with a halo of d pixels on both sides (zeros outside the image), so every
+// operand is one 16-byte LDS read (x shifts by kx d that break 16-byte alignment take
+// 4-byte or 2-byte reads). Global loads are 16 bytes (8 channels of one pixel), four
+// pixels per thread, turned into 8-byte LDS writes (4 pixels of one channel) by byte
+// permutes; the next segment's loads are issued before the current one is computed. The
+// four waves split each segment's 128 pixels into four k-steps of 32 and each keeps all
+// 3 x NCO x NCI output tiles; at the end the waves' partial sums meet in LDS and each
+// output element takes one global atomic per block (16 rows per block: the atomics of
+// all blocks on one word serialise, so fewer, longer blocks won: 72 us against 111 us
+// with 8 rows and 150 us with 4 on the 8 x 128 x 128, 64 -> 64 layer).
+constexpr int kSeg = 128;   // pixels per staged segment
+constexpr int kWgXU = 3;    // x staging units per thread (units of 4 pixels x 8 channels)
+
+__host__ __device__ constexpr int wg_dz_stride() { return kSeg + 8; }                            // = 8 mod 128
+__host__ __device__ inline int wg_x_stride(int dil) { return ((kSeg + 2 * dil - 8 + 127) / 128) * 128 + 8; }
+__host__ __device__ inline int wg_x_units(int Ci, int dil) { return (Ci / 8) * ((kSeg + 2 * dil + 3) / 4); }
+
+__device__ __forceinline__ uint32_t bf_pair(uint32_t hi_src, uint32_t lo_src, int half) {
+    // the 16-bit half `half` of lo_src in the low half, that of hi_src in the high half
+    return __builtin_amdgcn_perm(hi_src, lo_src, half ? 0x07060302u : 0x05040100u);
+}
+
+// 4 pixels x 8 channels (v[i] = channels of pixel i) -> 8 LDS rows of 4 pixels each
+__device__ __forceinline__ void wg_store_unit(uint16_t *dst, int stride, const uint4 (&v)[4]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int h = j & 1;
+        uint32_t w0, w1, w2, w3;
+        switch (j >> 1) {
+        case 0: w0 = v[0].x; w1 = v[1].x; w2 = v[2].x; w3 = v[3].x; break;
+        case 1: w0 = v[0].y; w1 = v[1].y; w2 = v[2].y; w3 = v[3].y; break;
+        case 2: w0 = v[0].z; w1 = v[1].z; w2 = v[2].z; w3 = v[3].z; break;
+        default: w0 = v[0].w; w1 = v[1].w; w2 = v[2].w; w3 = v[3].w; break;
+        }
+        const uint2 pk = make_uint2(bf_pair(w1, w0, h), bf_pair(w3, w2, h));
+        *reinterpret_cast<uint2 *>(dst + (int64_t)j * stride) = pk;
+    }
+}
+
+// 8 consecutive BF16 values from LDS at any 2-byte alignment (mode 0: 16-byte aligned,
+// 1: 4-byte aligned, 2: 2-byte aligned)
+__device__ __forceinline__ bf16x8 wg_read8(const uint16_t *src, int mode) {
+    uint4 r;
+    if (mode == 0) {
+        r = *reinterpret_cast<const uint4 *>(src);
+    } else if (mode == 1) {
+        const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);
+        r = make_uint4(s32[0], s32[1], s32[2], s32[3]);
+    } else {
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = uint32_t(src[2 * k]) | (uint32_t(src[2 * k + 1]) << 16);
+        r = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    return as_bf16x8(r);
+}
+
+template <int NCO, int NCI>
+__global__ __launch_bounds__(256) void k_conv_wgrad_lds(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dz,
+                                                        int N, int H, int W, int dil, float *__restrict__ dw, int rows) {
+    constexpr int Co = 16 * NCO, Ci = 16 * NCI;
+    constexpr int DS = wg_dz_stride();
+    constexpr int ndz = (Co / 8) * (kSeg / 4);   // dz staging units per segment
+    extern __shared__ uint4 lds_u4[];
+    uint16_t *const dzT = reinterpret_cast<uint16_t *>(lds_u4);
+    const int XS = wg_x_stride(dil);
+    uint16_t *const xT = dzT + Co * DS;
+    const int nqx = (kSeg + 2 * dil + 3) / 4, nx = (Ci / 8) * nqx;
+    const int ky = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, m = lane & 15, kb = lane >> 4;
+    const int r0 = blockIdx.x * rows, r1 = min(N * H, r0 + rows);
+    auto valid = [&](int row) {
+        const int yy = row % H + (ky - 1) * dil;
+        return yy >= 0 && yy < H;
+    };
+    // work items: (row, segment start) over the rows whose x row lies inside the image
+    int row = r0, s0 = 0;
+    while (row < r1 && !valid(row)) ++row;
+    auto advance = [&](int &rw, int &sg) {
+        sg += kSeg;
+        if (sg >= W) {
+            sg = 0;
+            do {
+                ++rw;
+            } while (rw < r1 && !valid(rw));
+        }
+    };
+    uint4 vd[4], vx[kWgXU][4];
+    auto load = [&](int rw, int sg) {
+        const int n = rw / H, y = rw % H, yy = y + (ky - 1) * dil;
+        if (tid < ndz) {
+            const int c8 = tid / (kSeg / 4), q = tid % (kSeg / 4);
+            const uint16_t *base = dz + (((int64_t)n * H + y) * W) * Co + 8 * c8;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = sg + 4 * q + i;
+                vd[i] = px < W ? *reinterpret_cast<const uint4 *>(base + (int64_t)px * Co) : make_uint4(0, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kWgXU; ++k) {
+            const int u = tid + 256 * k;
+            if (u < nx) {
+                const int c8 = u / nqx, q = u % nqx;
+                const uint16_t *base = x + (((int64_t)n * H + yy) * W) * Ci + 8 * c8;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int xx = sg - dil + 4 * q + i;
+                    vx[k][i] = (xx >= 0 && xx < W) ? *reinterpret_cast<const uint4 *>(base + (int64_t)xx * Ci)
+                                                    : make_uint4(0, 0, 0, 0);
+                }
+            }
+        }
+    };
+    auto store = [&]() {
+        if (tid < ndz) {
+            const int c8 = tid / (kSeg / 4), q = tid % (kSeg / 4);
+            wg_store_unit(dzT + (8 * c8) * DS + 4 * q, DS, vd);
+        }
+#pragma unroll
+        for (int k = 0; k < kWgXU; ++k) {
+            const int u = tid + 256 * k;
+            if (u < nx) {
+                const int c8 = u / nqx, q = u % nqx;
+                wg_store_unit(xT + (8 * c8) * XS + 4 * q, XS, vx[k]);
+            }
+        }
+    };
+    f32x4 acc[3][NCO][NCI];
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+        for (int c = 0; c < NCO; ++c)
+#pragma unroll
+            for (int t = 0; t < NCI; ++t) acc[kx][c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // read mode of each kx: the x operand starts at pixel pk + kx d of the staged row
+    int mode[3];
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+        const int o = kx * dil;
+        mode[kx] = o % 8 == 0 ? 0 : (o % 2 == 0 ? 1 : 2);
+    }
+    if (row < r1) load(row, s0);
+    while (row < r1) {
+        __syncthreads();   // the previous item's operand reads are done
+        store();
+        int nrow = row, ns = s0;
+        advance(nrow, ns);
+        if (nrow < r1) load(nrow, ns);   // in flight while this item computes
+        __syncthreads();
+        const int pk = 32 * wv + 8 * kb;
+        bf16x8 a[NCO];
+#pragma unroll
+        for (int c = 0; c < NCO; ++c) a[c] = as_bf16x8(*reinterpret_cast<const uint4 *>(dzT + (16 * c + m) * DS + pk));
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            const int off = pk + kx * dil;
+#pragma unroll
+            for (int t = 0; t < NCI; ++t) {
+                const bf16x8 b = wg_read8(xT + (16 * t + m) * XS + off, mode[kx]);
+#pragma unroll
+                for (int c = 0; c < NCO; ++c)
+                    acc[kx][c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b, acc[kx][c][t], 0, 0, 0);
+            }
+        }
+        row = nrow;
+        s0 = ns;
+    }
+    // the four waves' partial sums meet in LDS ([kx][co][ci] floats), then one atomic each
+    float *red = reinterpret_cast<float *>(lds_u4);
+    __syncthreads();
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+                for (int c = 0; c < NCO; ++c)
+#pragma unroll
+                    for (int t = 0; t < NCI; ++t)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int idx = (kx * Co + 16 * c + 4 * kb + i) * Ci + 16 * t + m;
+                            red[idx] = (w == 0 ? 0.f : red[idx]) + acc[kx][c][t][i];
+                        }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < 3 * Co * Ci; e += 256) {
+        const int kx = e / (Co * Ci), co = (e / Ci) % Co, ci = e % Ci;
+        const float v = red[e];
+        if (v != 0.f) unsafeAtomicAdd(&dw[((int64_t)co * 9 + 3 * ky + kx) * Ci + ci], v);
+    }
+}
+
 // ---------------------------------------------------------------- small kernels
 __global__ void k_weights_for_dgrad(const float *__restrict__ w, int Co, int Ci, uint16_t *__restrict__ wt) {
     const int64_t n = (int64_t)Co * 9 * Ci;
@@ -151,8 +456,40 @@ __global__ void k_weights_for_dgrad(const float *__restrict__ w, int Co, int Ci,
     }
 }
 
-__global__ void k_bias_grad(const float *__restrict__ dz, int64_t npix, int Co, float *__restrict__ db) {
-    // one block per channel group of 64 threads; grid-stride over pixels
+// db[co] += sum over pixels of dz[p][co]. Thread t of a block keeps channel t mod Co of
+// every (256 / Co)-th pixel (coalesced rows when Co divides 256), the block folds its
+// 256 / Co partial sums per channel in LDS and adds them with one atomic per channel. At
+// most 256 blocks: the atomics of all blocks on one channel's word serialise (1024 blocks
+// took 28 us on the 131072 x 64 gradient, 256 blocks 12 us).
+__global__ __launch_bounds__(256) void k_bias_grad(const float *__restrict__ dz, int64_t npix, int Co, float *__restrict__ db) {
+    __shared__ float sh[256];
+    const int ppb = 256 / Co;                    // pixels per block step
+    const int c = threadIdx.x % Co, j = threadIdx.x / Co;
+    float s = 0.f;
+    if (j < ppb) {
+        const int64_t step = (int64_t)gridDim.x * ppb;
+        int64_t p = (int64_t)blockIdx.x * ppb + j;
+        float s1 = 0.f, s2 = 0.f, s3 = 0.f;   // four chains, so four loads are in flight
+        for (; p + 3 * step < npix; p += 4 * step) {
+            s += dz[p * Co + c];
+            s1 += dz[(p + step) * Co + c];
+            s2 += dz[(p + 2 * step) * Co + c];
+            s3 += dz[(p + 3 * step) * Co + c];
+        }
+        for (; p < npix; p += step) s += dz[p * Co + c];
+        s += (s1 + s2) + s3;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < Co) {
+        float t = 0.f;
+        for (int k = 0; k < ppb; ++k) t += sh[k * Co + threadIdx.x];
+        atomicAdd(&db[threadIdx.x], t);
+    }
+}
+
+// the same for Co > 256 or not dividing 256: one block column per channel
+__global__ void k_bias_grad_col(const float *__restrict__ dz, int64_t npix, int Co, float *__restrict__ db) {
     const int co = blockIdx.y;
     float s = 0.f;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x)
@@ -383,11 +720,32 @@ int cnn_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias,
     if (!x || !w || (!y_bf16 && !y_f32) || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 32 || Co <= 0 || Co % 16 ||
         dilation < 1)
         return MOC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    // weights in LDS when they fit the device's per-block LDS: persistent blocks, two per
+    // compute unit, four 16-pixel tiles per wavefront
+    {
+        const size_t lds = sizeof(uint16_t) * (size_t)Co * (9 * (size_t)Ci + 8);
+        int dev = 0, lds_max = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && lds <= (size_t)lds_max &&
+            (Co == 16 || Co == 32 || Co == 64)) {
+            constexpr int MT = 4;
+            const int64_t ntile = ((int64_t)N * H * W + 64 * MT - 1) / (64 * MT);
+            const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntile, 2 * (int64_t)ncu));
+#define FWD_LAUNCH(A) hipLaunchKernelGGL((k_conv_fwd_lds<A, MT>), dim3(grid), dim3(256), lds, s, x, w, bias, N, H, W, Ci, relu, \
+                                         dilation, y_bf16, y_f32)
+            if (Co == 16) FWD_LAUNCH(1);
+            else if (Co == 32) FWD_LAUNCH(2);
+            else FWD_LAUNCH(4);
+#undef FWD_LAUNCH
+            return launched();
+        }
+    }
     // two pixel tiles per wavefront once a row fills 128 pixels (each weight load then feeds
     // two products); one for narrower images
     const int mt = W >= 128 ? 2 : 1;
     const dim3 grid((unsigned)((int64_t)N * H * ((W + 64 * mt - 1) / (64 * mt))));
-    hipStream_t s = (hipStream_t)stream;
     switch ((Co / 16) * 4 + mt) {
         case 5: hipLaunchKernelGGL((k_conv_fwd<1, 1>), grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
         case 6: hipLaunchKernelGGL((k_conv_fwd<1, 2>), grid, dim3(256), 0, s, x, w, bias, N, H, W, Ci, relu, dilation, y_bf16, y_f32); break;
@@ -411,6 +769,30 @@ int cnn_conv3x3_wgrad(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t 
                       int32_t dilation, float *dw, void *stream) {
     if (!x || !dz || !dw || N <= 0 || H <= 0 || W <= 0 || Ci <= 0 || Ci % 16 || Co <= 0 || Co % 16 || dilation < 1)
         return MOC_EINVAL;
+    // LDS-staged kernel for Co in {16, 32, 64}, Ci in {32, 64} when its staging fits;
+    // otherwise the gather kernel
+    const int nco = Co / 16, nci = Ci / 16;
+    const size_t stage = sizeof(uint16_t) * ((size_t)Co * wg_dz_stride() + (size_t)Ci * wg_x_stride(dilation));
+    const size_t lds = std::max(stage, sizeof(float) * 3 * (size_t)Co * Ci);
+    const bool fits = (nco == 1 || nco == 2 || nco == 4) && (nci == 2 || nci == 4) && lds <= 64 * 1024 &&
+                      wg_x_units(Ci, dilation) <= 256 * kWgXU;
+    if (fits) {
+        const int64_t nrows = (int64_t)N * H;
+        const int rows = (int)std::max<int64_t>(1, std::min<int64_t>(16, (nrows * 3 + 191) / 192));
+        const dim3 grid((unsigned)((nrows + rows - 1) / rows), 3);
+        const hipStream_t s = (hipStream_t)stream;
+#define WG_LAUNCH(A, B) hipLaunchKernelGGL((k_conv_wgrad_lds<A, B>), grid, dim3(256), lds, s, x, dz, N, H, W, dilation, dw, rows)
+        switch (nco * 8 + nci) {
+        case 10: WG_LAUNCH(1, 2); break;
+        case 12: WG_LAUNCH(1, 4); break;
+        case 18: WG_LAUNCH(2, 2); break;
+        case 20: WG_LAUNCH(2, 4); break;
+        case 34: WG_LAUNCH(4, 2); break;
+        default: WG_LAUNCH(4, 4); break;
+        }
+#undef WG_LAUNCH
+        return launched();
+    }
     const int rows = 4;
     const dim3 grid((unsigned)(((int64_t)N * H + rows - 1) / rows), 9);
     hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, (hipStream_t)stream, x, dz, N, H, W, Ci, Co, dilation, dw, rows);
@@ -419,7 +801,11 @@ int cnn_conv3x3_wgrad(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t 
 
 int cnn_bias_grad(const float *dz, int64_t npix, int32_t Co, float *db, void *stream) {
     if (!dz || !db || npix <= 0 || Co <= 0) return MOC_EINVAL;
-    hipLaunchKernelGGL(k_bias_grad, dim3(grid_for(npix, 256, 64), Co), dim3(256), 0, (hipStream_t)stream, dz, npix, Co, db);
+    if (Co <= 256 && 256 % Co == 0)
+        hipLaunchKernelGGL(k_bias_grad, dim3(grid_for(npix * Co, 256 * 16, 256)), dim3(256), 0, (hipStream_t)stream, dz, npix, Co, db);
+    else
+        hipLaunchKernelGGL(k_bias_grad_col, dim3(grid_for(npix, 256, 64), Co), dim3(256), 0, (hipStream_t)stream, dz, npix, Co,
+                           db);
     return launched();
 }
 

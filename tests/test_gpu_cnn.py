@@ -76,6 +76,43 @@ def test_wgrad_and_dgrad_exact(d, cuda):
     np.testing.assert_allclose(_np(dx), dx_ref, rtol=1e-5, atol=1e-5 * np.abs(dx_ref).max())
 
 
+@pytest.mark.parametrize("N,H,W,Ci,Co,d", [(1, 6, 128, 64, 64, 1), (1, 5, 200, 64, 32, 3), (2, 4, 70, 32, 64, 2),
+                                            (1, 40, 33, 64, 16, 32), (1, 9, 131, 32, 32, 8), (1, 3, 20, 96, 32, 1),
+                                            (1, 4, 16, 32, 48, 1)])
+def test_wgrad_shapes(N, H, W, Ci, Co, d, cuda):
+    """Weight gradient against the oracle over the staged kernel's cases (one and several
+    128-pixel segments with a ragged last one, shifts at every alignment, dilation 32 with
+    rows whose x row leaves the image) and two shapes it hands to the gather kernel
+    (Ci = 96, Co = 48). dW is accumulated into a non-zero start."""
+    import torch
+    from paper_2607_01591_amd import cnn
+    log(f"[cnn wgrad] {N}x{H}x{W} {Ci}->{Co} dilation {d}")
+    rng = np.random.default_rng(7)
+    x = _bf(rng.normal(size=(N, H, W, Ci)), cuda)
+    dz = _bf(rng.normal(size=(N, H, W, Co)), cuda)
+    w0 = rng.normal(size=(Co, 9, Ci)).astype(np.float32)
+    _, dW_ref, _ = CO.conv_backward(_np(x), np.zeros((Co, 3, 3, Ci)), _np(dz), d)
+    dW = torch.as_tensor(w0, device=cuda)
+    cnn.wgrad(x, dz, dW, dilation=d)
+    ref = dW_ref.reshape(Co, 9, Ci) + w0
+    np.testing.assert_allclose(_np(dW), ref, rtol=1e-5, atol=1e-5 * np.abs(dW_ref).max())
+
+
+@pytest.mark.parametrize("npix,Co", [(1000, 16), (70001, 64), (513, 48), (300, 512)])
+def test_bias_grad(npix, Co, cuda):
+    """db += column sums of FP32 dz: the coalesced kernel (Co dividing 256) and the
+    per-channel one (Co = 48, 512)."""
+    import torch
+    from paper_2607_01591_amd import cnn
+    rng = np.random.default_rng(3)
+    dz = rng.normal(size=(npix, Co)).astype(np.float32)
+    db0 = rng.normal(size=Co).astype(np.float32)
+    db = torch.as_tensor(db0, device=cuda)
+    cnn.bias_grad(torch.as_tensor(dz, device=cuda), db)
+    ref = dz.astype(np.float64).sum(axis=0) + db0
+    np.testing.assert_allclose(_np(db), ref, rtol=1e-5, atol=1e-5 * np.sqrt(npix))
+
+
 @pytest.mark.parametrize("dils", [[1, 1, 1], [1, 4, 2]])
 def test_network_gradients_match_oracle(dils, cuda):
     import torch
