@@ -96,16 +96,17 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ x
         }
 }
 
-// Forward with the weights in LDS. Persistent blocks each stage W (Co x 9 x Ci BF16; the
-// rows of one output channel padded by 8 elements so the 16 lanes of an operand read fall
-// on distinct banks) once, then take tiles of 64 MT consecutive pixels of the flattened
-// N x H x W image: wave w owns pixels [16 MT w, 16 MT (w + 1)) of a tile as MT 16-pixel
-// tiles and all Co = 16 NCT output channels, every lane's pixel with its own (n, y, x),
-// so tiles may cross rows and images. The input operands come from global memory (16 bytes,
-// 8 channels of one pixel per lane) and are loaded one (tap, 32-channel) step ahead of the
-// matrix-core products that use them.
-template <int NCT, int MT>
-__global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
+// Forward with the weights in LDS. Persistent blocks (two per compute unit) each stage W
+// (Co x 9 x Ci BF16; the rows of one output channel padded by 8 elements so the 16 lanes
+// of an operand read fall on distinct banks) once, then take tiles of 16 MT NW consecutive
+// pixels of the flattened N x H x W image: wave w of the NW owns pixels
+// [16 MT w, 16 MT (w + 1)) of a tile as MT 16-pixel tiles and all Co = 16 NCT output
+// channels, every lane's pixel with its own (n, y, x), so tiles may cross rows and
+// images. The input operands come from global memory (16 bytes, 8 channels of one pixel
+// per lane) and are loaded two (tap, 32-channel) steps ahead of the matrix-core products
+// that use them.
+template <int NCT, int MT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_conv_fwd_lds(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
                                                       const float *__restrict__ bias, int N, int H, int W, int Ci,
                                                       int relu, int dil, uint16_t *__restrict__ yb,
                                                       float *__restrict__ yf) {
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t *__restrict
     const int WS = 9 * Ci + 8;
     {
         const int per = 9 * Ci / 8;   // 16-byte pieces per output channel
-        for (int e = threadIdx.x; e < Co * per; e += 256) {
+        for (int e = threadIdx.x; e < Co * per; e += 64 * NW) {
             const int co = e / per, k = e - co * per;
             *reinterpret_cast<uint4 *>(wl + co * WS + 8 * k) =
                 *reinterpret_cast<const uint4 *>(w + (int64_t)co * 9 * Ci + 8 * k);
@@ -125,10 +126,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t *__restrict
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kb = lane >> 4;
     const int64_t NP = (int64_t)N * H * W;
-    const int64_t ntile = (NP + 64 * MT - 1) / (64 * MT);
+    const int64_t ntile = (NP + 16 * MT * NW - 1) / (16 * MT * NW);
     const int nc = Ci / 32, nit = 9 * nc;
     for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-        const int64_t pbase = tile * 64 * MT + wv * 16 * MT;
+        const int64_t pbase = tile * 16 * MT * NW + wv * 16 * MT;
         int pimg[MT], py[MT], px[MT];
         bool pv[MT];
 #pragma unroll
@@ -722,7 +723,7 @@ int cnn_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias,
         return MOC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     // weights in LDS when they fit the device's per-block LDS: persistent blocks, two per
-    // compute unit, four 16-pixel tiles per wavefront
+    // compute unit
     {
         const size_t lds = sizeof(uint16_t) * (size_t)Co * (9 * (size_t)Ci + 8);
         int dev = 0, lds_max = 0, ncu = 0;
@@ -730,11 +731,14 @@ int cnn_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias,
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && lds <= (size_t)lds_max &&
             (Co == 16 || Co == 32 || Co == 64)) {
-            constexpr int MT = 4;
-            const int64_t ntile = ((int64_t)N * H * W + 64 * MT - 1) / (64 * MT);
+            // 16 waves of two 16-pixel tiles each: occupancy hides the input loads' latency
+            // (64 x 64 layer, 8 x 128 x 128: 4 waves x 4 tiles 36-42 us, 8 x 2 29-33 us,
+            // 16 x 2 28-32 us, 8 x 4 33-38 us, 4 x 8 51-55 us)
+            constexpr int MT = 2, NW = 16;
+            const int64_t ntile = ((int64_t)N * H * W + 16 * MT * NW - 1) / (16 * MT * NW);
             const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntile, 2 * (int64_t)ncu));
-#define FWD_LAUNCH(A) hipLaunchKernelGGL((k_conv_fwd_lds<A, MT>), dim3(grid), dim3(256), lds, s, x, w, bias, N, H, W, Ci, relu, \
-                                         dilation, y_bf16, y_f32)
+#define FWD_LAUNCH(A) hipLaunchKernelGGL((k_conv_fwd_lds<A, MT, NW>), dim3(grid), dim3(64 * NW), lds, s, x, w, bias, N, H, W, \
+                                         Ci, relu, dilation, y_bf16, y_f32)
             if (Co == 16) FWD_LAUNCH(1);
             else if (Co == 32) FWD_LAUNCH(2);
             else FWD_LAUNCH(4);
