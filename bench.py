@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 N_CU, CLOCK_GHZ = 256, 2.4
 FP32_NONPACKED_TFLOPS = N_CU * 64 * 2 * CLOCK_GHZ / 1000.0      # FMA = 2 flops, no packed FP32
-DG_FLOPS_PER_UPDATE = 55   # DGMOC segment solution per (segment, polar, group), exp and reciprocal as one each
+DG_FLOPS_PER_UPDATE = 44   # DGMOC segment solution per (segment, polar, group); 1 - e^-a and the reciprocal count one each
 FLOPS_PER_UPDATE = 7     # tau mul, 1 - e^-tau (1), psi - q, * F, psi -= d, tally fma (2)
 COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_f32_lattice51x51_counters.txt")
 

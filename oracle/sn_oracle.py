@@ -38,6 +38,16 @@ def build(force: bool = False) -> str:
     return _SO
 
 
+
+def build_sanitized(out: str) -> str:
+    """The same source built for a sanitizer run (tests only): AddressSanitizer and
+    UndefinedBehaviorSanitizer, the process preloading gcc's libasan."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-fno-omit-frame-pointer", "-o", out, _SRC, "-lm"])
+    return out
+
+
 _lib = None
 
 
