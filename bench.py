@@ -221,7 +221,7 @@ def cpu_baseline(workload, full=False):
                 break
         out["lattice17x17_time_to_1e-6_s"] = time.perf_counter() - t0
         out["lattice17x17_iterations"] = its
-        log(f"oracle 17x17 to 1e-6: {out['lattice17x17_time_to_1e-6_s']:.1f} s, {r2['iterations']} iterations")
+        log(f"oracle 17x17 to 1e-6: {out['lattice17x17_time_to_1e-6_s']:.1f} s, {its} iterations")
         del o2
         big = P.config(3)
         o3 = O.Oracle.from_problem(big, threads=threads)
