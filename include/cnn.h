@@ -80,6 +80,16 @@ int cnn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, 
 /* BF16 copy of FP32 data. */
 int cnn_to_bf16(const float *src, int64_t n, uint16_t *dst, void *stream);
 
+/* Input features of the warm-start network per material (device pointers, FP64 inputs
+ * sigma_t [M][G], sigma_s [M][G][G] (from g to g'), nu_sigma_f [M][G], chi [M][G];
+ * output FP32 features [M][4 G]): the log of the material's normalised infinite-medium
+ * spectrum phi, (diag(Sigma_t) - Sigma_s^T) phi = chi (the mean chi of the fissile
+ * materials for one that does not fission, 1/G if none does; |phi| floored at 1e-30),
+ * then Sigma_t, Sigma_a = Sigma_t - sum_g' Sigma_s,g->g' and nuSigma_f. MOC_EINVAL for
+ * null pointers, M <= 0 or G outside 1..32. */
+int cnn_material_features(const double *sigma_t, const double *sigma_s, const double *nu_sigma_f, const double *chi,
+                          int32_t M, int32_t G, float *features, void *stream);
+
 /* Rasterise: out[p][c] = bf16(table[idx[p]][c]) for c < C, 0 for C <= c < Cp
  * (idx [npix] int32 in [0, rows), table FP32 [rows][C]). */
 int cnn_gather_rows(const float *table, const int32_t *idx, int64_t npix, int32_t C, int32_t Cp,

@@ -89,3 +89,27 @@ def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def material_features(sigma_t, sigma_s, nu_sigma_f, chi):
+    """Input features of the warm-start network per material, [M, 4 G] FP64: the log of
+    the normalised infinite-medium spectrum phi, which balances removal by collision
+    against in-scattering and the fission spectrum, Sigma_t,g phi_g - sum_g' Sigma_s,g'->g
+    phi_g' = chi_g (sigma_s[m][g][g'] scatters from g to g'); a material without
+    fission takes the mean chi of the fissile ones (1/G if there are none); |phi| is
+    floored at 1e-30 before normalising to sum 1. Then Sigma_t, Sigma_a = Sigma_t minus
+    the total scattering out of each group, and nuSigma_f."""
+    st, ss, nsf, chi = (np.asarray(a, np.float64) for a in (sigma_t, sigma_s, nu_sigma_f, chi))
+    M, G = st.shape
+    fissile = nsf.sum(axis=1) > 0
+    chi_free = chi[fissile].mean(axis=0) if fissile.any() else np.full(G, 1.0 / G)
+    out = np.zeros((M, 4 * G))
+    for m in range(M):
+        removal = np.diag(st[m]) - ss[m].T            # row g: collisions minus in-scatter
+        phi = np.linalg.solve(removal, chi[m] if fissile[m] else chi_free)
+        phi = np.maximum(np.abs(phi), 1e-30)
+        out[m, :G] = np.log(phi / phi.sum())
+        out[m, G:2 * G] = st[m]
+        out[m, 2 * G:3 * G] = st[m] - ss[m].sum(axis=1)
+        out[m, 3 * G:] = nsf[m]
+    return out

@@ -23,6 +23,7 @@ SIGNATURES = {
     "cnn_mse_grad_noalloc": [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp],
     "cnn_adam": [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i32, _vp, _vp],
     "cnn_to_bf16": [_vp, _i64, _vp, _vp],
+    "cnn_material_features": [_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp],
     "cnn_gather_rows": [_vp, _vp, _i64, _i32, _i32, _vp, _vp],
     "cnn_gather_log": [_vp, _vp, _i64, _i32, _i32, _vp, _vp],
     "cnn_bilinear_sample": [_vp, _i32, _i32, _i32, _i32, _vp, _i64, _i32, _vp, _vp],
@@ -114,6 +115,13 @@ def adam(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, p_bf16=None, str
 
 def to_bf16(src, dst, stream=None):
     _ok(lib().cnn_to_bf16(_p(src), src.numel(), _p(dst), _s(stream)), "cnn_to_bf16")
+
+
+def material_features(sigma_t, sigma_s, nu_sigma_f, chi, out, stream=None):
+    """out [M, 4 G] FP32 from FP64 device cross sections (see cnn_material_features)."""
+    M, G = sigma_t.shape
+    _ok(lib().cnn_material_features(_p(sigma_t), _p(sigma_s), _p(nu_sigma_f), _p(chi), M, G, _p(out), _s(stream)),
+        "cnn_material_features")
 
 
 def gather_rows(table, idx, Cp, out, stream=None):

@@ -670,6 +670,82 @@ inline int grid_for(int64_t n, int block, int cap = 4096) {
 
 inline int launched() { return hipGetLastError() == hipSuccess ? MOC_OK : MOC_EHIP; }
 
+// ---------------------------------------------------------------- input features
+// Input features of the warm-start network, one thread per material m (FP64 arithmetic,
+// FP32 output row [4 G]): the infinite-medium spectrum phi solving
+// (diag(Sigma_t) - Sigma_s^T) phi = chi_m (Gaussian elimination with partial pivoting;
+// a material that does not fission takes the mean chi of the fissile ones, or a flat
+// 1/G if none does), then log(|phi| / sum |phi|) with |phi| floored at 1e-30, Sigma_t,
+// Sigma_a = Sigma_t - sum_g' Sigma_s,g->g' and nuSigma_f.
+constexpr int kFeatMaxG = 32;
+__global__ void k_material_features(const double *__restrict__ st, const double *__restrict__ ss,
+                                    const double *__restrict__ nsf, const double *__restrict__ chi, int M, int G,
+                                    float *__restrict__ out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    double A[kFeatMaxG * kFeatMaxG], b[kFeatMaxG];
+    auto fissile = [&](int mm) {
+        double f = 0.0;
+        for (int g = 0; g < G; ++g) f += nsf[(int64_t)mm * G + g];
+        return f > 0.0;
+    };
+    if (fissile(m)) {
+        for (int g = 0; g < G; ++g) b[g] = chi[(int64_t)m * G + g];
+    } else {
+        int nf = 0;
+        for (int g = 0; g < G; ++g) b[g] = 0.0;
+        for (int mm = 0; mm < M; ++mm)
+            if (fissile(mm)) {
+                ++nf;
+                for (int g = 0; g < G; ++g) b[g] += chi[(int64_t)mm * G + g];
+            }
+        for (int g = 0; g < G; ++g) b[g] = nf > 0 ? b[g] / nf : 1.0 / G;
+    }
+    // row g: Sigma_t,g phi_g - sum_g' Sigma_s,g'->g phi_g'
+    const double *S = ss + (int64_t)m * G * G;   // S[g][g'] = Sigma_s, g -> g'
+    for (int g = 0; g < G; ++g)
+        for (int gp = 0; gp < G; ++gp) A[g * G + gp] = (g == gp ? st[(int64_t)m * G + g] : 0.0) - S[gp * G + g];
+    for (int c = 0; c < G; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < G; ++r)
+            if (fabs(A[r * G + c]) > fabs(A[piv * G + c])) piv = r;
+        if (piv != c) {
+            for (int j = 0; j < G; ++j) {
+                const double t = A[c * G + j];
+                A[c * G + j] = A[piv * G + j];
+                A[piv * G + j] = t;
+            }
+            const double t = b[c];
+            b[c] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = c + 1; r < G; ++r) {
+            const double f = A[r * G + c] / A[c * G + c];
+            for (int j = c; j < G; ++j) A[r * G + j] -= f * A[c * G + j];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = G - 1; r >= 0; --r) {
+        double v = b[r];
+        for (int j = r + 1; j < G; ++j) v -= A[r * G + j] * b[j];
+        b[r] = v / A[r * G + r];
+    }
+    double tot = 0.0;
+    for (int g = 0; g < G; ++g) {
+        b[g] = fmax(fabs(b[g]), 1e-30);
+        tot += b[g];
+    }
+    float *o = out + (int64_t)m * 4 * G;
+    for (int g = 0; g < G; ++g) {
+        double sa = 0.0;
+        for (int gp = 0; gp < G; ++gp) sa += S[g * G + gp];
+        o[g] = (float)log(b[g] / tot);
+        o[G + g] = (float)st[(int64_t)m * G + g];
+        o[2 * G + g] = (float)(st[(int64_t)m * G + g] - sa);
+        o[3 * G + g] = (float)nsf[(int64_t)m * G + g];
+    }
+}
+
 // ---------------------------------------------------------------- allocation-free loss
 // Blocks of the loss kernel: the partial sums of squares have exactly this many entries.
 constexpr int kMseBlocks = 256;
@@ -853,6 +929,14 @@ int cnn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, 
 int cnn_to_bf16(const float *src, int64_t n, uint16_t *dst, void *stream) {
     if (!src || !dst || n <= 0) return MOC_EINVAL;
     hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, src, n, dst);
+    return launched();
+}
+
+int cnn_material_features(const double *sigma_t, const double *sigma_s, const double *nu_sigma_f, const double *chi,
+                          int32_t M, int32_t G, float *features, void *stream) {
+    if (!sigma_t || !sigma_s || !nu_sigma_f || !chi || !features || M <= 0 || G <= 0 || G > kFeatMaxG) return MOC_EINVAL;
+    hipLaunchKernelGGL(k_material_features, dim3((M + 63) / 64), dim3(64), 0, (hipStream_t)stream, sigma_t, sigma_s,
+                       nu_sigma_f, chi, M, G, features);
     return launched();
 }
 

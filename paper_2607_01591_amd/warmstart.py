@@ -40,24 +40,20 @@ def load_net(path, device, n_groups) -> cnn.ConvNet:
     return net
 
 
-def material_features(prob) -> np.ndarray:
-    """Per-material input features [M, 4 G] (float32): the log of the material's
-    infinite-medium spectrum (the solution of (Sigma_t - Sigma_s^T) phi = chi, with the
-    lattice's mean fission spectrum for materials that do not fission; normalised to sum
-    1), then Sigma_t, Sigma_a = Sigma_t - sum_g' Sigma_s,g->g' and nuSigma_f. The
-    spectrum is the part of the flux a few pixels of context cannot infer from raw cross
-    sections."""
-    G = prob.n_groups
-    st, ss, nsf, chi = prob.sigma_t, prob.sigma_s, prob.nu_sigma_f, prob.chi
-    fiss = nsf.sum(axis=1) > 0
-    chi_mean = chi[fiss].mean(axis=0) if fiss.any() else np.full(G, 1.0 / G)
-    feats = []
-    for m in range(prob.n_materials):
-        src = chi[m] if fiss[m] else chi_mean
-        spec = np.linalg.solve(np.diag(st[m]) - ss[m].T, src)
-        spec = np.maximum(np.abs(spec), 1e-30)
-        feats.append(np.concatenate([np.log(spec / spec.sum()), st[m], st[m] - ss[m].sum(axis=1), nsf[m]]))
-    return np.asarray(feats, dtype=np.float32)
+def material_features(prob, device):
+    """Per-material input features [M, 4 G] (device FP32, computed by the
+    cnn_material_features kernel): the log of the material's infinite-medium spectrum
+    (the solution of (Sigma_t - Sigma_s^T) phi = chi, with the lattice's mean fission
+    spectrum for materials that do not fission; normalised to sum 1), then Sigma_t,
+    Sigma_a = Sigma_t - sum_g' Sigma_s,g->g' and nuSigma_f. The spectrum is the part of
+    the flux a few pixels of context cannot infer from raw cross sections."""
+    import torch
+    def dev(a):
+        return torch.as_tensor(np.ascontiguousarray(a, np.float64), device=device)
+    M, G = prob.sigma_t.shape
+    out = torch.empty((M, 4 * G), dtype=torch.float32, device=device)
+    cnn.material_features(dev(prob.sigma_t), dev(prob.sigma_s), dev(prob.nu_sigma_f), dev(prob.chi), out)
+    return out
 
 
 class WarmStart:
@@ -88,7 +84,7 @@ class WarmStart:
     def rasterize(self, prob, out=None):
         """BF16 input image [1, IMG, IMG, 32] of a problem on this mesh."""
         import torch
-        table = torch.as_tensor(material_features(prob), device=self.dev)
+        table = material_features(prob, self.dev)
         idx = torch.as_tensor(prob.region_material[self.pix_region_host].astype(np.int32), device=self.dev)
         if out is None:
             out = torch.empty((1, IMG, IMG, C_IN_PAD), dtype=torch.bfloat16, device=self.dev)

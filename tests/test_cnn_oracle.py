@@ -1,6 +1,7 @@
 """Pins for the numpy CNN oracle: central finite differences of the loss, a 1x1
 special case against a plain matrix product, shifted taps, and for dilated
-convolutions the polyphase identity."""
+convolutions the polyphase identity; the input features' spectrum in closed form for
+two groups without up-scatter and one group."""
 import numpy as np
 
 from oracle import cnn_oracle as C
@@ -138,3 +139,29 @@ def test_dilated_gradients_match_central_differences():
         lm = np.sum(C.conv_forward(x, W, np.zeros(3), 2) * dz)
         xf[idx] = old
         assert abs((lp - lm) / (2 * h) - dx.reshape(-1)[idx]) < 1e-6
+
+
+def test_material_features_closed_forms():
+    """Two groups, no up-scatter: the spectrum is phi_1 = chi_1 / (St_1 - S_11),
+    phi_2 = (chi_2 + S_12 phi_1) / (St_2 - S_22) in closed form; one group: phi = 1 (log
+    0); a non-fissile material takes the mean fission spectrum of the fissile ones;
+    Sigma_a is Sigma_t minus the scattering out of the group (not into it)."""
+    st = np.array([[0.5, 1.2], [0.4, 0.9]])
+    ss = np.array([[[0.30, 0.15], [0.0, 1.0]], [[0.35, 0.04], [0.0, 0.85]]])
+    nsf = np.array([[0.01, 0.2], [0.0, 0.0]])
+    chi = np.array([[0.9, 0.1], [0.0, 0.0]])
+    f = C.material_features(st, ss, nsf, chi)
+    for m, c in ((0, chi[0]), (1, chi[0])):          # material 1 takes material 0's chi
+        p1 = c[0] / (st[m, 0] - ss[m, 0, 0])
+        p2 = (c[1] + ss[m, 0, 1] * p1) / (st[m, 1] - ss[m, 1, 1])
+        tot = p1 + p2
+        np.testing.assert_allclose(f[m, :2], np.log([p1 / tot, p2 / tot]), rtol=1e-13)
+        np.testing.assert_allclose(f[m, 2:4], st[m])
+        np.testing.assert_allclose(f[m, 4:6], [st[m, 0] - ss[m, 0, 0] - ss[m, 0, 1], st[m, 1] - ss[m, 1, 1]])
+        np.testing.assert_allclose(f[m, 6:], nsf[m])
+    one = C.material_features([[1.0]], [[[0.6]]], [[0.3]], [[1.0]])
+    np.testing.assert_allclose(one, [[0.0, 1.0, 0.4, 0.3]])
+    # no fissile material at all: a flat source
+    flat = C.material_features([[1.0, 2.0]], [[[0.5, 0.0], [0.0, 1.0]]], [[0.0, 0.0]], [[0.0, 0.0]])
+    p = np.array([0.5 / 0.5, 0.5 / 1.0])
+    np.testing.assert_allclose(flat[0, :2], np.log(p / p.sum()), rtol=1e-13)

@@ -252,3 +252,32 @@ def test_d4_transforms(cuda):
         acc = torch.zeros((S, S, Cc), dtype=torch.float32, device=cuda)
         cnn.d4_accumulate(y[0].float().contiguous(), Cc, op, 1.0, acc)
         np.testing.assert_array_equal(_np(acc), xr)
+
+
+def test_material_features_match_oracle(cuda):
+    """The feature kernel against the oracle's numpy solve: the 7-group lattice family's
+    materials (fissile and not), random 2- and 12-group materials with up-scatter, and a
+    set with no fissile material."""
+    import torch
+    from paper_2607_01591_amd import cnn
+    from paper_2607_01591_amd import problems as P
+    rng = np.random.default_rng(11)
+    cases = []
+    p = P.config(5, seed=200004)
+    cases.append((p.sigma_t, p.sigma_s, p.nu_sigma_f, p.chi))
+    for G in (2, 12):
+        M = 5
+        st = rng.uniform(0.3, 2.0, size=(M, G))
+        ss = rng.uniform(0.0, 1.0, size=(M, G, G)) * (0.8 * st[:, :, None] / G)
+        nsf = rng.uniform(0.0, 0.3, size=(M, G)) * (rng.uniform(size=(M, 1)) < 0.6)
+        chi = rng.uniform(size=(M, G))
+        chi /= chi.sum(axis=1, keepdims=True)
+        cases.append((st, ss, nsf, chi))
+    cases.append((cases[1][0], cases[1][1], np.zeros_like(cases[1][2]), cases[1][3]))
+    for st, ss, nsf, chi in cases:
+        M, G = st.shape
+        dev = [torch.as_tensor(np.ascontiguousarray(a, np.float64), device=cuda) for a in (st, ss, nsf, chi)]
+        out = torch.empty((M, 4 * G), dtype=torch.float32, device=cuda)
+        cnn.material_features(*dev, out)
+        ref = CO.material_features(st, ss, nsf, chi).astype(np.float32)
+        np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
