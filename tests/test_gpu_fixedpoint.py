@@ -13,7 +13,7 @@ stated per result:
 * |k_oracle - k_gpu| < 1e-5.
 
 Workloads: the 17 x 17 lattice (three seeds), the 271-pin hexagon with 33 groups (group
-batch 11 in the sweep), the 51 x 51 lattice (solved with CMFD on its pin cells; the
+batches of 8 in the sweep), the 51 x 51 lattice (solved with CMFD on its pin cells; the
 converged answer is the plain iteration's), and one warm-started solve of the
 warm-start family (network guess, then the plain iteration).
 """

@@ -82,8 +82,9 @@ def test_cfg2_full_size_sweep_vs_oracle(cuda):
 
 
 def test_cfg4_full_size_sweep_vs_oracle(cuda):
-    """The 271-pin hexagon with 33 groups in full: the sweep instance the benchmark runs
-    (group batch 11, three batches, P = 3) against one oracle sweep, element by element."""
+    """The 271-pin hexagon with 33 groups in full against one oracle sweep, element by
+    element, for the instance the benchmark runs (group batches of 8: five batches with 7
+    padding groups, P = 3) and for batches of 11 (three batches, no padding)."""
     import os
     import torch
     from oracle.oracle import Oracle
@@ -99,13 +100,20 @@ def test_cfg4_full_size_sweep_vs_oracle(cuda):
     psi = rng.uniform(0, 1, size=s.psi_shape()).astype(np.float32).astype(np.float64)
     o.set_psi(psi)
     ref = o.sweep(src)
-    phi, ex = _sweep(s, _dev(src, cuda), _dev(psi, cuda), cuda)
-    phi = _host(phi)
-    err = np.max(np.abs(phi - ref) / ref)
-    log(f"  max rel err {err:.2e}")
-    assert err < 1e-5
-    np.testing.assert_allclose(_host(ex), o.get_exit_psi(), rtol=1e-5, atol=1e-6)
-    del s, ex
+    ref_ex = o.get_exit_psi()
+    for gb in (0, 11):
+        if gb:
+            del s
+            torch.cuda.empty_cache()
+            s = moc.Solver(prob, precision="f32", group_batch=gb)
+        phi, ex = _sweep(s, _dev(src, cuda), _dev(psi, cuda), cuda)
+        phi = _host(phi)
+        err = np.max(np.abs(phi - ref) / ref)
+        log(f"  group batch {gb or 'default'}: max rel err {err:.2e}")
+        assert err < 1e-5
+        np.testing.assert_allclose(_host(ex), ref_ex, rtol=1e-5, atol=1e-6)
+        del ex
+    del s
     torch.cuda.empty_cache()
 
 
