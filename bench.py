@@ -31,12 +31,13 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_f32_lattice51x51_counters.txt
 
 def kernel_sources_hash():
     """sha256 over the sources that decide what the sweep kernel reads and writes (its code,
-    the segment packing and the launch set-up); measured counters are only reported while
-    this hash matches the one recorded with them."""
+    the segment packing and the launch set-up: every moc_* source but the CMFD kernels,
+    which run between sweeps); measured counters are only reported while this hash matches
+    the one recorded with them."""
     csrc = os.path.join(ROOT, "paper_2607_01591_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
-        if name.startswith("moc_") and name.endswith((".hip", ".h", ".cpp")):
+        if name.startswith("moc_") and name.endswith((".hip", ".h", ".cpp")) and name != "moc_cmfd.hip":
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
