@@ -267,27 +267,41 @@ def dg_leg(args):
 
 
 def sn_leg(args):
-    """DFEM-SN on the 17 x 17 lattice mesh: sweep time and local solves per second."""
+    """DFEM-SN on the 17 x 17 lattice mesh: sweep time and local solves per second, level by
+    level and tile by tile (pin-cell tiles)."""
     import torch
     from paper_2607_01591_amd import dfem
     from paper_2607_01591_amd import problems as P
     prob = P.config(2)
     out = {"workload": f"{prob.name}: {len(prob.tri)} triangles (linear elements), {prob.n_groups} groups, "
                        f"{prob.n_azim} azimuths x {prob.n_polar} polar = {prob.n_azim * prob.n_polar} directions, reflective"}
+    n_tiles, tile = P.grid_tiles(prob, 17, 17)
+    out["tiles"] = f"{n_tiles} pin cells"
     for prec in ("f32",) if args.no_f64 else ("f32", "f64"):
         log(f"DFEM-SN {prec}: creating context")
         s = dfem.SNSolver(prob, precision=prec, check_every=1 << 30)
+        n_solves = s.info["n_tasks"] * prob.n_groups
+        # level by level (one dependent launch per level: bound by the per-level latency)
         ms, prof, r = time_iterations(s, 5, 1)
         sw = prof["sweep_ms"] / max(1, prof["sweeps"])
-        n_solves = s.info["n_tasks"] * prob.n_groups
-        out[prec] = {"local_solves_per_sweep": n_solves, "solves_per_s": n_solves / (sw * 1e-3),
-                     "ms_per_iteration": ms, "sweep_ms": sw, "levels": s.info["n_levels"],
-                     # one dependent launch per level: the sweep is bound by the per-level latency
-                     "bound": "latency", "us_per_level": sw * 1e3 / max(1, s.info["n_levels"]),
-                     "slots": s.info["n_slots"], "tasks": s.info["n_tasks"],
-                     "device_GiB": s.info["device_bytes"] / 2**30, "k_after": r["k"]}
-        log(f"DFEM-SN {prec}: {ms:.2f} ms/iteration, sweep {sw:.2f} ms, {n_solves / (sw * 1e-3):.3e} solves/s, "
-            f"{s.info['n_levels']} levels, {s.info['n_slots']} slots of {s.info['n_tasks']} tasks")
+        lev = {"ms_per_iteration": ms, "sweep_ms": sw, "levels": s.info["n_levels"], "bound": "latency",
+               "us_per_level": sw * 1e3 / max(1, s.info["n_levels"]), "slots": s.info["n_slots"]}
+        log(f"DFEM-SN {prec}, level by level: {ms:.2f} ms/iteration, sweep {sw:.2f} ms, "
+            f"{n_solves / (sw * 1e-3):.3e} solves/s, {s.info['n_levels']} levels, {s.info['n_slots']} slots")
+        # tile by tile (pin cells): one launch per tile level
+        s.set_tiles(tile)
+        ms_t, prof_t, r_t = time_iterations(s, 5, 1)
+        sw_t = prof_t["sweep_ms"] / max(1, prof_t["sweeps"])
+        inf = s.info
+        out[prec] = {"local_solves_per_sweep": n_solves, "solves_per_s": n_solves / (sw_t * 1e-3),
+                     "ms_per_iteration": ms_t, "sweep_ms": sw_t, "schedule": "tiles",
+                     "tile_levels": inf["n_tile_levels"], "max_inner_levels": inf["max_inner_levels"],
+                     "tile_lds_bytes": inf["tile_lds_bytes"], "tile_slots": inf["n_tile_slots"],
+                     "bound": "latency", "levels_schedule": lev, "tasks": inf["n_tasks"],
+                     "device_GiB": inf["device_bytes"] / 2**30, "k_after": r_t["k"]}
+        log(f"DFEM-SN {prec}, pin-cell tiles: {ms_t:.2f} ms/iteration, sweep {sw_t:.2f} ms, "
+            f"{n_solves / (sw_t * 1e-3):.3e} solves/s, {inf['n_tile_levels']} tile levels, "
+            f"{inf['tile_lds_bytes']} B of LDS per block")
         del s
         torch.cuda.empty_cache()
     return out

@@ -12,7 +12,8 @@
  * for every direction, element and group, the element's 3x3 upwind system; all
  * directions advance together, one dependency level after another, and each element's
  * angular flux lives in a storage slot that is reused once every downstream element has
- * read it (Alg. DFEM_SN_sweep's compressed storage).
+ * read it (Alg. DFEM_SN_sweep's compressed storage). With tiles (moc_sn_set_tiles) the
+ * levels are taken tile by tile instead.
  *
  * Conventions are those of moc.h. Arrays of the solver are [T][G][3]: triangle (the
  * caller's triangle numbering), group, modal coefficient; FP64, row-major. Domains are
@@ -41,6 +42,11 @@ typedef struct {
     int32_t tasks_per_thread; /* tasks one thread of a sweep step takes: the polar directions
                                  of one element and azimuth (n_polar), or 1 when a level does
                                  not consist of such runs */
+    int32_t n_tiles;          /* tiles of the tiled schedule, 0 when sweeps run level by level */
+    int32_t n_tile_levels;    /* tile levels (kernel launches per sweep) of the tiled schedule */
+    int32_t max_inner_levels; /* most dependency levels inside one tile for one direction group */
+    int32_t tile_lds_bytes;   /* LDS of one block of the tiled sweep */
+    int64_t n_tile_slots;     /* storage slots of the tiled schedule (fluxes passed between tiles) */
 } moc_sn_info;
 
 /* Create a DFEM-SN context. mesh as for moc_create (box domain only); angles: n_azim (a
@@ -74,6 +80,23 @@ int moc_sn_get_flux(moc_sn_ctx *ctx, double *phi_dev, void *stream);
 int moc_sn_set_external_source(moc_sn_ctx *ctx, const double *q_dev);
 
 int moc_sn_get_info(const moc_sn_ctx *ctx, moc_sn_info *info);
+
+/* Sweep by tiles (same dependency order as Alg. DFEM_SN_sweep, scheduled in two tiers):
+ * element_tile (host [n_elements], copied) assigns every element to one of n_tiles tiles.
+ * For each direction group (the polar directions of one azimuth) the tiles are ordered by
+ * their own dependencies (a tile feeds another through the faces between them) into tile
+ * levels, one kernel launch each; a block takes one tile and direction group and walks
+ * the tile's elements level by level, keeping the fluxes read inside the tile in LDS, and
+ * only fluxes read by another tile go through storage slots. Convex tiles (for example
+ * the pin cells of a lattice) never depend on each other in a cycle. The fluxes are the
+ * same as with level-by-level sweeps bit for bit (the scalar flux is summed in direction
+ * order either way). n_tiles = 0 with element_tile = NULL returns to level-by-level
+ * sweeps. Errors: MOC_EINVAL (tile index out of range, an empty tile, a tile too large for
+ * the LDS of one block (64 KiB: n_elements_in_tile x n_polar x G x 3 x the sweep
+ * precision's size), tiles whose dependencies form a cycle for some direction, n_tiles > 0
+ * with NULL element_tile or the reverse), MOC_ENOMEM, MOC_EHIP. Works on host-only
+ * contexts too (the schedule is built and checked on the host). */
+int moc_sn_set_tiles(moc_sn_ctx *ctx, int32_t n_tiles, const int32_t *element_tile);
 
 /* Sweep timing with HIP events (moc_profile: sweeps, total, min and max ms). */
 int moc_sn_set_profiling(moc_sn_ctx *ctx, int32_t enable);

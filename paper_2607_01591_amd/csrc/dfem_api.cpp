@@ -22,10 +22,31 @@ using namespace moc;
         if (e_ != hipSuccess) throw Error(MOC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// host data the tiled schedule is built from (kept after create)
+struct SnHost {
+    int T = 0, A = 0, P = 0, nd = 0;
+    std::vector<int> nbr;          // [T][3] neighbour element, or -1 - side
+    std::vector<double> nrm;       // [T][3][2] outward unit normals (FP64)
+    std::vector<double> azc, azs;  // azimuths' unit in-plane vectors
+    std::vector<int> bface;        // [3T] boundary face index, or -1
+    std::vector<int> rx, ry;       // mirrored directions
+    int bc[6] = {0, 0, 0, 0, 0, 0};
+    // inflow / outflow by the sign of Omega . n taken with the azimuth's unit vector (as
+    // for the level schedule, so both agree on every face)
+    double onf(int dd, int e, int k) const {
+        const int a = dd / P;
+        return azc[a] * nrm[((size_t)e * 3 + k) * 2] + azs[a] * nrm[((size_t)e * 3 + k) * 2 + 1];
+    }
+};
+
 struct moc_sn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     DevSN d;
+    SnHost h;
+    DevSNTiles tl;
+    bool tiled = false;            // sweeps use the tiled schedule
+    std::vector<void *> tile_allocs;
     int max_iter = 10000, check_every = 1, n_threads = 1;
     bool fissile = false, fixed_source = false;
     bool host_only = false;   // negative device ordinal: host setup and its checks only
@@ -53,6 +74,15 @@ struct moc_sn_ctx {
         T *p = dalloc<T>(v.size());
         if (!v.empty()) SN_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
         return p;
+    }
+    void dfree(void *p) {
+        for (size_t i = 0; i < allocs.size(); ++i)
+            if (allocs[i].first == p) {
+                (void)hipFree(p);
+                device_bytes -= (int64_t)allocs[i].second;
+                allocs.erase(allocs.begin() + (long)i);
+                return;
+            }
     }
     ~moc_sn_ctx() {
         if (stream) (void)hipStreamSynchronize(stream);
@@ -357,6 +387,23 @@ static void sn_create_impl(const moc_mesh *mesh_in, const moc_tracks *angles, co
         }
     }
 
+    {
+        SnHost &h = c->h;
+        h.T = T;
+        h.A = A;
+        h.P = P;
+        h.nd = nd;
+        h.nbr = nbr;
+        h.nrm = nrm;
+        h.azc = azc;
+        h.azs = azs;
+        h.bface = bface;
+        h.rx = rx;
+        h.ry = ry;
+        for (int i = 0; i < 6; ++i) h.bc[i] = m.bc[i];
+    }
+    d.ndg = nd / d.tgroup;
+
     // ---- check the schedule on the host before any kernel can use it: replay the sweep
     // order and require every upstream read to find its task's flux in the slot, and every
     // index to be in range
@@ -430,18 +477,8 @@ static void sn_create_impl(const moc_mesh *mesh_in, const moc_tracks *angles, co
     d.bnd[1] = c->dalloc<char>((size_t)std::max<int64_t>(d.nbnd, 1) * G * 3 * rs);
     d.q = c->dalloc<char>((size_t)T * G * 3 * rs);
     d.phi_acc = c->dalloc<double>((size_t)T * G * 3);
-    // runs of tgroup tasks and, per element, its runs (the scalar flux is gathered from them)
-    d.nrun = ntask / d.tgroup;
-    {
-        std::vector<int> off((size_t)T + 1, 0), runs((size_t)d.nrun);
-        for (int64_t r = 0; r < d.nrun; ++r) ++off[(size_t)task_e[(size_t)(r * d.tgroup)] + 1];
-        for (int e = 0; e < T; ++e) off[(size_t)e + 1] += off[(size_t)e];
-        std::vector<int> fill(off.begin(), off.end() - 1);
-        for (int64_t r = 0; r < d.nrun; ++r) runs[(size_t)fill[(size_t)task_e[(size_t)(r * d.tgroup)]]++] = (int)r;
-        d.elem_off = c->upload(off);
-        d.elem_runs = c->upload(runs);
-    }
-    d.run_acc = f64 ? (void *)c->dalloc<double>((size_t)d.nrun * G * 3) : (void *)c->dalloc<float>((size_t)d.nrun * G * 3);
+    // scalar-flux contribution of each (element, direction group), gathered in direction order
+    d.run_acc = f64 ? (void *)c->dalloc<double>((size_t)T * d.ndg * G * 3) : (void *)c->dalloc<float>((size_t)T * d.ndg * G * 3);
     d.phi[0] = c->dalloc<double>((size_t)T * G * 3);
     d.phi[1] = c->dalloc<double>((size_t)T * G * 3);
     d.partials = c->dalloc<double>(2 * kSnReduceBlocks);
@@ -470,8 +507,9 @@ static std::pair<hipEvent_t, hipEvent_t> sn_prof_events(moc_sn_ctx *c) {
 }
 
 // The launches of one sweep with the emission in d.q: one launch per dependency level
-// (every direction's elements of that level, all groups), then the gather of the scalar
-// flux; reflective inflow reads boundary buffer `parity`, outflow writes the other.
+// (every direction's elements of that level, all groups), or with tiles one launch per
+// tile level, then the gather of the scalar flux; reflective inflow reads boundary buffer
+// `parity`, outflow writes the other.
 static void sn_enqueue_sweep(moc_sn_ctx *c, int parity, hipStream_t s) {
     DevSN &d = c->d;
     SnStepArgs a{};
@@ -495,10 +533,33 @@ static void sn_enqueue_sweep(moc_sn_ctx *c, int parity, hipStream_t s) {
     a.run_acc = d.run_acc;
     a.G = d.G;
     a.tgroup = d.tgroup;
-    for (int st = 0; st < d.nsteps; ++st) {
-        a.k0 = d.step_off[st];
-        a.k1 = d.step_off[st + 1];
-        launch_sn_step(a, d.precision, s);
+    a.ndg = d.ndg;
+    a.T = d.T;
+    if (c->tiled) {
+        const DevSNTiles &t = c->tl;
+        a.psi = t.psi;
+        SnTileArgs ta{};
+        ta.tt_task = t.tt_task;
+        ta.tt_fine = t.tt_fine;
+        ta.fine_off = t.fine_off;
+        ta.tt_tile = t.tt_tile;
+        ta.tt_dg = t.tt_dg;
+        ta.tile_off = t.tile_off;
+        ta.tile_elems = t.tile_elems;
+        ta.ext_off = t.ext_off;
+        ta.ext_src = t.ext_src;
+        ta.rec = t.rec;
+        for (int r = 0; r < kSnLdsCount; ++r) ta.lds_off[r] = t.lds_off[r];
+        for (int L = 0; L < t.n_levels; ++L) {
+            ta.tt0 = t.lev_off[L];
+            launch_sn_tile(a, ta, (int)(t.lev_off[L + 1] - t.lev_off[L]), t.lds_bytes, d.precision, s);
+        }
+    } else {
+        for (int st = 0; st < d.nsteps; ++st) {
+            a.k0 = d.step_off[st];
+            a.k1 = d.step_off[st + 1];
+            launch_sn_step(a, d.precision, s);
+        }
     }
     launch_sn_gather(d, s);
 }
@@ -534,6 +595,455 @@ static void sn_sweep_impl(moc_sn_ctx *c, hipStream_t s) {
         SN_HIP(hipEventRecord(ev.second, s));
         c->prof_pending.push_back(ev);
     }
+}
+
+// LDS of one block of the tiled sweep when no device is there to ask (host-only contexts):
+// gfx950's 160 KiB
+constexpr size_t kSnHostLdsLimit = 160 * 1024;
+
+static void sn_drop_graphs(moc_sn_ctx *c) {
+    if (c->stream) SN_HIP(hipStreamSynchronize(c->stream));
+    for (auto &g : c->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+static void sn_clear_tiles(moc_sn_ctx *c) {
+    sn_drop_graphs(c);
+    for (void *p : c->tile_allocs) c->dfree(p);
+    c->tile_allocs.clear();
+    c->tl = DevSNTiles{};
+    c->tiled = false;
+}
+
+// The tiled schedule (an MI355X layout of the same dependency order, Alg. DFEM_SN_sweep):
+// per direction group, the tiles' own dependency graph (a tile feeds another through the
+// faces between them) ordered by Kahn's algorithm into tile levels, and inside each tile
+// the elements' levels restricted to the tile. One tile level is one launch; a tile task
+// (tile, direction group) is one block that walks its inner levels. Fluxes read inside a
+// tile stay in LDS; fluxes read by another tile get a storage slot, allocated over tile
+// levels as the level schedule allocates them over levels. Everything is checked by a
+// host replay before any upload.
+static void sn_set_tiles_impl(moc_sn_ctx *c, int n_tiles, const int32_t *tile_of) {
+    if (n_tiles <= 0 || !tile_of) {
+        if (n_tiles > 0 || tile_of) throw Error(MOC_EINVAL, "sn tiles: n_tiles > 0 needs element_tile and back");
+        sn_clear_tiles(c);
+        return;
+    }
+    const SnHost &h = c->h;
+    const DevSN &d = c->d;
+    const int T = h.T, nd = h.nd, TG = d.tgroup, ndg = d.ndg, G = d.G;
+    const bool f64 = d.precision == MOC_PREC_F64;
+    // tiles and each element's index within its tile
+    std::vector<int> tsize(n_tiles, 0), local(T);
+    for (int e = 0; e < T; ++e) {
+        const int t = tile_of[e];
+        if (t < 0 || t >= n_tiles) throw Error(MOC_EINVAL, "sn tiles: tile index out of range");
+        local[e] = tsize[t]++;
+    }
+    int max_tile = 0;
+    for (int t = 0; t < n_tiles; ++t) {
+        if (tsize[t] == 0) throw Error(MOC_EINVAL, "sn tiles: empty tile " + std::to_string(t));
+        max_tile = std::max(max_tile, tsize[t]);
+    }
+    size_t lds_limit = kSnHostLdsLimit;
+    if (!c->host_only) {
+        int v = 0;
+        SN_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+        lds_limit = (size_t)v;
+    }
+    const size_t rs = f64 ? sizeof(double) : sizeof(float);
+    std::vector<int> toff(n_tiles + 1, 0), telem(T);
+    for (int t = 0; t < n_tiles; ++t) toff[t + 1] = toff[t] + tsize[t];
+    {
+        std::vector<int> fill(toff.begin(), toff.end() - 1);
+        for (int e = 0; e < T; ++e) telem[fill[tile_of[e]]++] = e;   // ascending element order
+    }
+    // per direction group: tile levels and the elements' levels inside their tile
+    std::vector<int> tlev((size_t)ndg * n_tiles), flev((size_t)ndg * T);
+    std::vector<int> ntlev(ndg, 0);
+    parallel_for(ndg, c->n_threads, 1, [&](int64_t g0, int64_t g1, int) {
+        std::vector<int> indeg(std::max(T, n_tiles)), queue(std::max(T, n_tiles));
+        for (int64_t dg = g0; dg < g1; ++dg) {
+            const int dd = (int)dg * TG;
+            int *tl = &tlev[(size_t)dg * n_tiles];
+            // tile graph: one edge per face from one tile into another
+            std::fill(indeg.begin(), indeg.begin() + n_tiles, 0);
+            for (int e = 0; e < T; ++e)
+                for (int k = 0; k < 3; ++k) {
+                    const int nb = h.nbr[(size_t)e * 3 + k];
+                    if (nb >= 0 && tile_of[nb] != tile_of[e] && h.onf(dd, e, k) > 0) ++indeg[tile_of[nb]];
+                }
+            int head = 0, tail = 0;
+            for (int t = 0; t < n_tiles; ++t) {
+                tl[t] = 0;
+                if (indeg[t] == 0) queue[tail++] = t;
+            }
+            while (head < tail) {
+                const int t = queue[head++];
+                for (int i = toff[t]; i < toff[t + 1]; ++i) {
+                    const int e = telem[i];
+                    for (int k = 0; k < 3; ++k) {
+                        const int nb = h.nbr[(size_t)e * 3 + k];
+                        if (nb >= 0 && tile_of[nb] != t && h.onf(dd, e, k) > 0) {
+                            const int tn = tile_of[nb];
+                            tl[tn] = std::max(tl[tn], tl[t] + 1);
+                            if (--indeg[tn] == 0) queue[tail++] = tn;
+                        }
+                    }
+                }
+            }
+            if (tail != n_tiles)
+                throw Error(MOC_EINVAL, "sn tiles: the tiles' sweep dependencies are cyclic for direction " +
+                                            std::to_string(dd) + " (use convex tiles)");
+            int mx = 0;
+            for (int t = 0; t < n_tiles; ++t) mx = std::max(mx, tl[t]);
+            ntlev[dg] = mx + 1;
+            // levels inside each tile (edges between elements of the same tile)
+            int *fl = &flev[(size_t)dg * T];
+            for (int e = 0; e < T; ++e) {
+                fl[e] = 0;
+                indeg[e] = 0;
+                for (int k = 0; k < 3; ++k) {
+                    const int nb = h.nbr[(size_t)e * 3 + k];
+                    if (nb >= 0 && tile_of[nb] == tile_of[e] && h.onf(dd, e, k) < 0) ++indeg[e];
+                }
+            }
+            head = tail = 0;
+            for (int e = 0; e < T; ++e)
+                if (indeg[e] == 0) queue[tail++] = e;
+            while (head < tail) {
+                const int e = queue[head++];
+                for (int k = 0; k < 3; ++k) {
+                    const int nb = h.nbr[(size_t)e * 3 + k];
+                    if (nb >= 0 && tile_of[nb] == tile_of[e] && h.onf(dd, e, k) > 0) {
+                        fl[nb] = std::max(fl[nb], fl[e] + 1);
+                        if (--indeg[nb] == 0) queue[tail++] = nb;
+                    }
+                }
+            }
+            if (tail != T) throw Error(MOC_EINVAL, "sn tiles: cyclic dependencies inside a tile");
+        }
+    });
+    int nlev = 0;
+    for (int v : ntlev) nlev = std::max(nlev, v);
+
+    // tile tasks ordered by (tile level, direction group, tile); inside a tile task the
+    // tasks by (inner level, element, direction)
+    DevSNTiles tl;
+    tl.n_tiles = n_tiles;
+    tl.n_levels = nlev;
+    tl.max_tile = max_tile;
+    const int64_t ntt = (int64_t)ndg * n_tiles, ntask = (int64_t)T * nd;
+    tl.lev_off.assign(nlev + 1, 0);
+    for (int64_t dg = 0; dg < ndg; ++dg)
+        for (int t = 0; t < n_tiles; ++t) ++tl.lev_off[tlev[(size_t)dg * n_tiles + t] + 1];
+    for (int L = 0; L < nlev; ++L) tl.lev_off[L + 1] += tl.lev_off[L];
+    std::vector<int64_t> tt_order(ntt);
+    {
+        std::vector<int64_t> fill(tl.lev_off.begin(), tl.lev_off.end() - 1);
+        for (int64_t dg = 0; dg < ndg; ++dg)
+            for (int t = 0; t < n_tiles; ++t) tt_order[fill[tlev[(size_t)dg * n_tiles + t]]++] = dg * n_tiles + t;
+    }
+    std::vector<int> task_e(ntask), task_d(ntask), task_loc(ntask), tt_fine(ntt + 1), tt_tile(ntt), tt_dg(ntt);
+    std::vector<int64_t> tt_task(ntt + 1), task_of(ntask), task_tt(ntask);
+    std::vector<int> task_fl(ntask), fine_off;
+    fine_off.reserve((size_t)ntt * 8);
+    int64_t k = 0;
+    std::vector<int> order;
+    for (int64_t i = 0; i < ntt; ++i) {
+        const int64_t dg = tt_order[i] / n_tiles;
+        const int t = (int)(tt_order[i] % n_tiles);
+        const int *fl = &flev[(size_t)dg * T];
+        order.assign(telem.begin() + toff[t], telem.begin() + toff[t + 1]);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return fl[x] < fl[y]; });
+        tt_task[i] = k;
+        tt_fine[i] = (int)fine_off.size();
+        tt_tile[i] = t;
+        tt_dg[i] = (int)dg;
+        int cur = -1;
+        for (int e : order) {
+            if (fl[e] != cur) {
+                cur = fl[e];
+                fine_off.push_back((int)(k - tt_task[i]));
+            }
+            for (int p = 0; p < TG; ++p) {
+                const int dd = (int)dg * TG + p;
+                task_e[k] = e;
+                task_d[k] = dd;
+                task_loc[k] = local[e];
+                task_of[(size_t)dd * T + e] = k;
+                task_tt[k] = i;
+                task_fl[k] = cur;
+                ++k;
+            }
+        }
+        fine_off.push_back((int)(k - tt_task[i]));
+    }
+    tt_task[ntt] = k;
+    tt_fine[ntt] = (int)fine_off.size();
+    if (k != ntask) throw Error(MOC_EINVAL, "sn tiles: task count mismatch");
+    std::vector<int> tt_level(ntt);
+    for (int L = 0; L < nlev; ++L)
+        for (int64_t i = tl.lev_off[L]; i < tl.lev_off[L + 1]; ++i) tt_level[i] = L;
+
+    // items: (tile task, element); task k belongs to item k / TG as polar direction k % TG
+    const int64_t nitem = ntask / TG;
+    auto bad = [](const char *what) { throw Error(MOC_EINVAL, std::string("sn tiles: inconsistent schedule (") + what + ")"); };
+    // storage slots for fluxes read by another tile, TG consecutive slots per item (one per
+    // polar direction): held from the producing tile level to the last reading one, then
+    // reused
+    std::vector<int> last_use(nitem, -1);
+    for (int64_t it = 0; it < nitem; ++it) {
+        const int e = task_e[it * TG], dd = task_d[it * TG];
+        for (int f = 0; f < 3; ++f) {
+            const int nb = h.nbr[(size_t)e * 3 + f];
+            if (nb >= 0 && tile_of[nb] != tile_of[e] && h.onf(dd, e, f) > 0)
+                last_use[it] = std::max(last_use[it], tt_level[task_tt[task_of[(size_t)dd * T + nb]]]);
+        }
+    }
+    std::vector<int> sgrp(nitem, -1), free_slots;
+    {
+        std::vector<std::vector<int>> release(nlev);
+        int next = 0;
+        for (int L = 0; L < nlev; ++L) {
+            if (L > 0)
+                for (int sl : release[L - 1]) free_slots.push_back(sl);
+            for (int64_t it = tt_task[tl.lev_off[L]] / TG; it < tt_task[tl.lev_off[L + 1]] / TG; ++it) {
+                if (last_use[it] < 0) continue;
+                int sl;
+                if (!free_slots.empty()) {
+                    sl = free_slots.back();
+                    free_slots.pop_back();
+                } else {
+                    sl = next++;
+                }
+                sgrp[it] = sl;
+                release[last_use[it]].push_back(sl);
+            }
+        }
+        tl.nslot = (int64_t)next * TG;
+    }
+    if (tl.nslot >= kSnExtFlag) throw Error(MOC_EINVAL, "sn tiles: too many storage slots");
+    auto slot_of = [&](int64_t kk) { return sgrp[kk / TG] >= 0 ? sgrp[kk / TG] * TG + (int)(kk % TG) : -1; };
+    // LDS slots inside each tile task (Alg. DFEM_SN_sweep's compressed storage within the
+    // tile): an element's fluxes are held from its inner level to the last inner level that
+    // reads them
+    std::vector<int> lslot(nitem, -1);
+    int max_live = 1;
+    {
+        std::vector<int> lu(nitem, -1), freel;
+        std::vector<std::vector<int>> rel;
+        for (int64_t i = 0; i < ntt; ++i) {
+            const int nf = tt_fine[i + 1] - tt_fine[i] - 1;
+            for (int64_t it = tt_task[i] / TG; it < tt_task[i + 1] / TG; ++it) {
+                const int e = task_e[it * TG], dd = task_d[it * TG];
+                for (int f = 0; f < 3; ++f) {
+                    const int nb = h.nbr[(size_t)e * 3 + f];
+                    if (nb >= 0 && tile_of[nb] == tile_of[e] && h.onf(dd, e, f) > 0)
+                        lu[it] = std::max(lu[it], task_fl[task_of[(size_t)dd * T + nb]]);
+                }
+            }
+            rel.assign(nf + 1, {});
+            freel.clear();
+            int next = 0;
+            for (int j = 0; j < nf; ++j) {
+                if (j > 0)
+                    for (int sl : rel[j - 1]) freel.push_back(sl);
+                const int64_t ia = (tt_task[i] + fine_off[tt_fine[i] + j]) / TG, ib = (tt_task[i] + fine_off[tt_fine[i] + j + 1]) / TG;
+                for (int64_t it = ia; it < ib; ++it) {
+                    if (lu[it] < 0) continue;
+                    if (lu[it] <= j || lu[it] >= nf) bad("inner reader level");
+                    int sl;
+                    if (!freel.empty()) {
+                        sl = freel.back();
+                        freel.pop_back();
+                    } else {
+                        sl = next++;
+                    }
+                    lslot[it] = sl;
+                    rel[lu[it]].push_back(sl);
+                }
+            }
+            max_live = std::max(max_live, next);
+        }
+    }
+
+    // inflow codes and boundary writes of every task
+    std::vector<int> inflow(3 * (size_t)ntask), bwrite(3 * (size_t)ntask, -1);
+    for (int64_t kk = 0; kk < ntask; ++kk) {
+        const int e = task_e[kk], dd = task_d[kk];
+        for (int f = 0; f < 3; ++f) {
+            const int nb = h.nbr[(size_t)e * 3 + f];
+            const double on = h.onf(dd, e, f);
+            int code = kSnOutflow;
+            if (nb >= 0) {
+                if (on < 0) {
+                    const int64_t kp = task_of[(size_t)dd * T + nb];
+                    code = tile_of[nb] == tile_of[e] ? (kSnLocalFlag | lslot[kp / TG]) : slot_of(kp);
+                }
+            } else {
+                const int side = -1 - nb;
+                const bool refl = h.bc[side] == MOC_BC_REFLECTIVE;
+                const int bf = h.bface[3 * e + f];
+                if (on < 0) {
+                    code = refl ? -4 - (bf * nd + (side < 2 ? h.rx[dd] : h.ry[dd])) : kSnVacuum;
+                } else if (refl) {
+                    bwrite[3 * kk + f] = bf * nd + dd;
+                }
+            }
+            inflow[3 * kk + f] = code;
+        }
+    }
+
+    // replay: every read finds its producer's flux (a storage slot written at an earlier
+    // tile level and not rewritten since; an LDS slot of the same tile task written at an
+    // earlier inner level and not rewritten since), no storage slot is written at the tile
+    // level that reads its previous value, and every index is in range
+    {
+        std::vector<int64_t> owner(std::max<int64_t>(tl.nslot, 1), -1);
+        std::vector<int> last_read(std::max<int64_t>(tl.nslot, 1), -1), written(std::max<int64_t>(tl.nslot, 1), -1);
+        std::vector<int64_t> lowner(max_live, -1);
+        for (int L = 0; L < nlev; ++L) {
+            for (int64_t i = tl.lev_off[L]; i < tl.lev_off[L + 1]; ++i) {
+                std::fill(lowner.begin(), lowner.end(), -1);
+                for (int j = tt_fine[i]; j < tt_fine[i + 1] - 1; ++j) {
+                    const int64_t ka = tt_task[i] + fine_off[j], kb = tt_task[i] + fine_off[j + 1];
+                    for (int64_t kk = ka; kk < kb; ++kk) {
+                        const int e = task_e[kk], dd = task_d[kk];
+                        if (task_loc[kk] < 0 || task_loc[kk] >= max_tile) bad("tile index");
+                        for (int f = 0; f < 3; ++f) {
+                            const int code = inflow[3 * kk + f];
+                            const int nb = h.nbr[(size_t)e * 3 + f];
+                            if (code >= 0 && (code & kSnLocalFlag)) {
+                                const int ls = code & ~kSnLocalFlag;
+                                if (nb < 0 || tile_of[nb] != tile_of[e] || ls >= max_live) bad("local read");
+                                const int64_t kp = task_of[(size_t)dd * T + nb];
+                                if (lowner[ls] != kp / TG || task_tt[kp] != i || task_fl[kp] >= task_fl[kk]) bad("local read order");
+                            } else if (code >= 0) {
+                                if (code >= tl.nslot || nb < 0 || owner[code] != task_of[(size_t)dd * T + nb]) bad("slot read");
+                                last_read[code] = L;
+                            } else if (code <= -4) {
+                                if (-4 - (int64_t)code >= d.nbnd) bad("boundary index");
+                            } else if (code != kSnOutflow && code != kSnVacuum) {
+                                bad("inflow code");
+                            }
+                            if (bwrite[3 * kk + f] >= d.nbnd) bad("boundary index");
+                        }
+                    }
+                    for (int64_t it = ka / TG; it < kb / TG; ++it)
+                        if (lslot[it] >= 0) lowner[lslot[it]] = it;
+                }
+            }
+            for (int64_t kk = tt_task[tl.lev_off[L]]; kk < tt_task[tl.lev_off[L + 1]]; ++kk) {
+                const int sl = slot_of(kk);
+                if (sl < 0) continue;
+                if (sl >= tl.nslot || written[sl] == L || last_read[sl] >= L) bad("slot write");
+                written[sl] = L;
+                owner[sl] = kk;
+            }
+        }
+        for (int64_t i = 0; i < ntt; ++i) {
+            const int n_fine = tt_fine[i + 1] - tt_fine[i] - 1;
+            if (n_fine < 1) bad("empty tile task");
+            if (tt_task[i] + fine_off[tt_fine[i + 1] - 1] != tt_task[i + 1] || tt_task[i] % TG) bad("tile task extent");
+            for (int j = tt_fine[i]; j < tt_fine[i + 1] - 1; ++j)
+                if (fine_off[j + 1] <= fine_off[j] || (fine_off[j + 1] - fine_off[j]) % TG) bad("inner level");
+        }
+    }
+
+    // item records [tile element, LDS slot, three inflow codes, three boundary writes,
+    // storage slot], written for polar direction 0; direction p of the item adds p to a
+    // staged entry (kSnExtFlag | j), subtracts it from a reflective code (-4 - j), and adds
+    // it to a boundary write and to the storage slot. Every flux a tile task reads from a
+    // storage slot or the boundary buffer becomes a staged entry, TG consecutive ones per
+    // (item, face).
+    std::vector<int> rec((size_t)nitem * kSnRecInts), ext_off(ntt + 1, 0), ext_src;
+    int max_ext = 0, max_fine = 0, max_items = 0;
+    for (int64_t i = 0; i < ntt; ++i) {
+        ext_off[i] = (int)ext_src.size();
+        for (int64_t it = tt_task[i] / TG; it < tt_task[i + 1] / TG; ++it) {
+            int *r = &rec[(size_t)it * kSnRecInts];
+            const int64_t k0 = it * TG;
+            r[0] = task_loc[k0];
+            r[1] = lslot[it];
+            for (int f = 0; f < 3; ++f) {
+                const int c0 = inflow[3 * k0 + f];
+                const bool staged = (c0 >= 0 && !(c0 & kSnLocalFlag)) || c0 <= -4;
+                int code = c0;
+                if (staged) {
+                    const int j = (int)ext_src.size() - ext_off[i];
+                    if (j + TG >= kSnExtFlag) throw Error(MOC_EINVAL, "sn tiles: too many inflow entries in one tile");
+                    for (int p = 0; p < TG; ++p) ext_src.push_back(inflow[3 * (k0 + p) + f]);
+                    code = c0 >= 0 ? (kSnExtFlag | j) : -4 - j;
+                }
+                r[2 + f] = code;
+                r[5 + f] = bwrite[3 * k0 + f];
+                // every polar direction of the item must follow from direction 0's record
+                for (int p = 0; p < TG; ++p) {
+                    const int cp = inflow[3 * (k0 + p) + f], bw = bwrite[3 * (k0 + p) + f];
+                    if (staged) {
+                        const int jp = (c0 >= 0 ? (code & ~kSnExtFlag) : -4 - code) + p;
+                        if (((cp >= 0) != (c0 >= 0)) || ext_src[ext_off[i] + jp] != cp) bad("staged entry");
+                    } else if (cp != c0) {
+                        bad("polar inflow code");
+                    }
+                    if ((bw >= 0) != (r[5 + f] >= 0) || (bw >= 0 && bw != r[5 + f] + p)) bad("polar boundary write");
+                }
+            }
+            r[8] = slot_of(k0);
+            for (int p = 0; p < TG; ++p)
+                if (slot_of(k0 + p) != (r[8] >= 0 ? r[8] + p : -1) || task_loc[k0 + p] != r[0]) bad("polar slot");
+        }
+        max_ext = std::max(max_ext, (int)ext_src.size() - ext_off[i]);
+        max_fine = std::max(max_fine, tt_fine[i + 1] - tt_fine[i]);
+        max_items = std::max(max_items, (int)((tt_task[i + 1] - tt_task[i]) / TG));
+        tl.max_inner = std::max(tl.max_inner, tt_fine[i + 1] - tt_fine[i] - 1);
+    }
+    ext_off[ntt] = (int)ext_src.size();
+    tl.max_live = max_live;
+    // LDS layout of one block (16-byte aligned regions)
+    {
+        const size_t sz[kSnLdsCount] = {(size_t)max_live * TG * G * 3 * rs, (size_t)max_tile * kSnElemReals * rs,
+                                        (size_t)max_tile * G * 4 * rs,      (size_t)max_ext * G * 3 * rs,
+                                        (size_t)TG * 3 * rs,                (size_t)max_items * kSnRecInts * sizeof(int),
+                                        (size_t)max_tile * sizeof(int),     (size_t)max_fine * sizeof(int)};
+        size_t off = 0;
+        for (int r = 0; r < kSnLdsCount; ++r) {
+            tl.lds_off[r] = (unsigned)off;
+            off += (sz[r] + 15) & ~(size_t)15;
+        }
+        tl.lds_bytes = off;
+        if (off > lds_limit)
+            throw Error(MOC_EINVAL, "sn tiles: a tile of " + std::to_string(max_tile) + " elements needs " + std::to_string(off) +
+                                        " bytes of LDS (the device allows " + std::to_string(lds_limit) + ")");
+    }
+
+    sn_clear_tiles(c);
+    if (!c->host_only) {
+        SN_HIP(hipSetDevice(c->device));
+        auto up = [&](const auto &v) {
+            auto *p = c->upload(v);
+            c->tile_allocs.push_back(p);
+            return p;
+        };
+        tl.rec = up(rec);
+        tl.tt_task = up(tt_task);
+        tl.tt_fine = up(tt_fine);
+        tl.fine_off = up(fine_off);
+        tl.tt_tile = up(tt_tile);
+        tl.tt_dg = up(tt_dg);
+        tl.tile_off = up(toff);
+        tl.tile_elems = up(telem);
+        tl.ext_off = up(ext_off);
+        tl.ext_src = up(ext_src.empty() ? std::vector<int>(1, 0) : ext_src);
+        tl.psi = c->dalloc<char>((size_t)std::max<int64_t>(tl.nslot, 1) * G * 3 * rs);
+        c->tile_allocs.push_back(tl.psi);
+    }
+    c->tl = std::move(tl);
+    c->tiled = true;
 }
 
 static void sn_drain_profile(moc_sn_ctx *c) {
@@ -711,7 +1221,17 @@ int moc_sn_get_info(const moc_sn_ctx *c, moc_sn_info *info) {
     info->device_bytes = c->device_bytes;
     info->setup_ms = c->setup_ms;
     info->tasks_per_thread = c->d.tgroup;
+    info->n_tiles = c->tiled ? c->tl.n_tiles : 0;
+    info->n_tile_levels = c->tiled ? c->tl.n_levels : 0;
+    info->max_inner_levels = c->tiled ? c->tl.max_inner : 0;
+    info->tile_lds_bytes = c->tiled ? (int32_t)c->tl.lds_bytes : 0;
+    info->n_tile_slots = c->tiled ? c->tl.nslot : 0;
     return MOC_OK;
+}
+
+int moc_sn_set_tiles(moc_sn_ctx *c, int32_t n_tiles, const int32_t *element_tile) {
+    if (!c) return MOC_EINVAL;
+    return sn_guarded(c, [&] { sn_set_tiles_impl(c, n_tiles, element_tile); });
 }
 
 int moc_sn_set_profiling(moc_sn_ctx *c, int32_t enable) {

@@ -11,6 +11,18 @@ namespace moc {
 // inflow codes per (task, face), decided on the host in FP64
 constexpr int kSnOutflow = -1;   // Omega . n >= 0: the face adds to the local matrix
 constexpr int kSnVacuum = -3;    // inflow through a vacuum side: nothing enters
+// tiled schedule (codes of its own task records): kSnLocalFlag | l = interior inflow from
+// the tile's LDS flux of its element l; kSnExtFlag | j = interior inflow from staged entry
+// j (another tile's storage slot); -4 - j = reflective inflow from staged entry j (the
+// boundary buffer)
+constexpr int kSnLocalFlag = 1 << 30;
+constexpr int kSnExtFlag = 1 << 29;
+constexpr int kSnRecInts = 9;           // item record: tile element, LDS slot, 3 inflow codes,
+                                        // 3 boundary writes, storage slot (polar direction 0)
+constexpr int kSnElemReals = 58;        // staged element data: mass 6, gradw 1, normals 6,
+                                        // face matrices 18, coupling matrices 27
+// regions of a tile block's LDS (byte offsets in SnTileArgs::lds_off)
+enum { kSnLdsPsi = 0, kSnLdsElem, kSnLdsSq, kSnLdsExt, kSnLdsDir, kSnLdsTask, kSnLdsElemId, kSnLdsFine, kSnLdsCount };
 // >= 0: inflow from the upstream element's storage slot; <= -4: reflective inflow read
 // from boundary entry (-4 - code)
 
@@ -40,10 +52,8 @@ struct DevSN {
     void *bnd[2] = {nullptr, nullptr};  // [nbnd][G][3], entry = boundary face * nd + direction
     void *q = nullptr;       // [T][G][3] per steradian
     double *phi_acc = nullptr;          // [T][G][3]
-    int64_t nrun = 0;        // runs of tgroup tasks per sweep (run r = tasks r tgroup ...)
-    void *run_acc = nullptr; // [nrun][G][3] scalar-flux contribution of each run (sweep precision)
-    int *elem_off = nullptr; // [T + 1] runs of element e: elem_runs[elem_off[e] .. elem_off[e+1])
-    int *elem_runs = nullptr;
+    int ndg = 0;             // direction groups (runs of tgroup directions of one azimuth)
+    void *run_acc = nullptr; // [ndg][T][G][3] scalar-flux contribution of each run (sweep precision)
     double *phi[2] = {nullptr, nullptr};
     double *qext = nullptr;
     double *partials = nullptr, *scal = nullptr;
@@ -59,10 +69,47 @@ struct SnStepArgs {
     int64_t k0, k1;
     int G;
     int tgroup;
+    int ndg;
+    int T;
+};
+
+// one launch of the tiled schedule: blocks take the tile tasks tt0, tt0 + 1, ...; the
+// tasks of level j inside tile task tt are tt_task[tt] + [fine_off[j], fine_off[j + 1]) for
+// j in [tt_fine[tt], tt_fine[tt + 1] - 1) (each tile task stores its levels' starts and the
+// end of its last level)
+struct SnTileArgs {
+    const int64_t *tt_task;
+    const int *tt_fine;
+    const int *fine_off;
+    const int *tt_tile, *tt_dg;        // tile and direction group of each tile task
+    const int *tile_off, *tile_elems;  // elements of each tile (ascending)
+    const int *ext_off, *ext_src;      // staged inflow entries of each tile task: a storage
+                                       // slot (>= 0) or a boundary code (<= -4)
+    const int *rec;                    // item records (item = tile task element, task / tgroup)
+    int64_t tt0;
+    unsigned lds_off[kSnLdsCount];
+};
+
+// device arrays of the tiled schedule (own task order, slots and codes)
+struct DevSNTiles {
+    int n_tiles = 0, n_levels = 0;      // tiles; tile levels (launches per sweep)
+    int max_tile = 0;                   // elements of the largest tile
+    int max_inner = 0;                  // most dependency levels inside one tile task
+    size_t lds_bytes = 0;               // LDS of one block
+    int64_t nslot = 0;
+    std::vector<int64_t> lev_off;       // host [n_levels + 1]: tile tasks of each tile level
+    unsigned lds_off[kSnLdsCount] = {};
+    int max_live = 0;                   // LDS flux slots of one tile task
+    int *rec = nullptr;                 // item records [item][kSnRecInts]
+    int64_t *tt_task = nullptr;
+    int *tt_fine = nullptr, *fine_off = nullptr, *tt_tile = nullptr, *tt_dg = nullptr;
+    int *tile_off = nullptr, *tile_elems = nullptr, *ext_off = nullptr, *ext_src = nullptr;
+    void *psi = nullptr;                // [nslot][G][3]
 };
 
 void launch_sn_step(const SnStepArgs &a, int precision, hipStream_t s);
 void launch_sn_gather(const DevSN &d, hipStream_t s);
+void launch_sn_tile(const SnStepArgs &a, const SnTileArgs &t, int nblocks, size_t lds_bytes, int precision, hipStream_t s);
 void launch_sn_prep_user(const DevSN &d, const double *src, hipStream_t s);
 void launch_sn_source(const DevSN &d, const double *phi, hipStream_t s);
 void launch_sn_finalize(const DevSN &d, double *phi_internal, double *phi_user, double *partials, hipStream_t s);

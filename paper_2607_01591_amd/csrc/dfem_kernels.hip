@@ -19,127 +19,197 @@ namespace moc {
 
 static constexpr double kFourPiSn = 12.566370614359172953850573533118;
 
-// One sweep step: every (element, direction) task of one dependency level, for every
-// group, one thread per (task, group). A run of tgroup consecutive tasks (the polar
-// directions of one element and azimuth) sits on adjacent lanes of one wavefront for each
-// group (64 / tgroup runs per wavefront, the remaining lanes idle), so the lanes of a run
-// read the same element data and their contributions to the element's scalar-flux moments
-// are summed across the run with wavefront shuffles and stored once per run (no atomics;
-// k_sn_gather adds the runs of each element after the last level). The upstream elements
-// of a task belong to earlier levels, whose angular fluxes sit in their storage slots.
-template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStepArgs a) {
-    const int G = a.G, TG = a.tgroup;
-    const int runs_per_wave = 64 / TG;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int pp = lane % TG;
-    const int64_t run = wave * runs_per_wave + lane / TG;
-    const int64_t nrun = (a.k1 - a.k0) / TG * G;
-    const bool valid = lane < runs_per_wave * TG && run < nrun;
-    const Real *__restrict__ mass = reinterpret_cast<const Real *>(a.mass);
-    const Real *__restrict__ fmass = reinterpret_cast<const Real *>(a.fmass);
-    const Real *__restrict__ fcpl = reinterpret_cast<const Real *>(a.fcpl);
-    const Real *__restrict__ nrm = reinterpret_cast<const Real *>(a.nrm);
-    const Real *__restrict__ gradw = reinterpret_cast<const Real *>(a.gradw);
-    const Real *__restrict__ sigt = reinterpret_cast<const Real *>(a.sigt);
-    const Real *__restrict__ dirs = reinterpret_cast<const Real *>(a.dirs);
-    const Real *__restrict__ q = reinterpret_cast<const Real *>(a.q);
+
+// Where the local solve reads its data: straight from the global arrays (level schedule)
+// or from a tile task's copy in LDS (tiled schedule). Both present the same values, so the
+// solve below does the same arithmetic in the same order for either.
+template <typename Real> struct SnGlobalSrc {
+    const SnStepArgs &a;
+    int64_t k;
+    int e, d;
+    __device__ SnGlobalSrc(const SnStepArgs &a_, int64_t k_) : a(a_), k(k_), e(a_.task_e[k_]), d(a_.task_d[k_]) {}
+    __device__ const Real *mass() const { return reinterpret_cast<const Real *>(a.mass) + (int64_t)e * 6; }
+    __device__ Real gradw() const { return reinterpret_cast<const Real *>(a.gradw)[e]; }
+    __device__ const Real *nrm(int f) const { return reinterpret_cast<const Real *>(a.nrm) + ((int64_t)e * 3 + f) * 2; }
+    __device__ const Real *fmass(int f) const { return reinterpret_cast<const Real *>(a.fmass) + ((int64_t)e * 3 + f) * 6; }
+    __device__ const Real *fcpl(int f) const { return reinterpret_cast<const Real *>(a.fcpl) + ((int64_t)e * 3 + f) * 9; }
+    __device__ Real sigt(int g) const { return reinterpret_cast<const Real *>(a.sigt)[(int64_t)e * a.G + g]; }
+    __device__ const Real *q(int g) const { return reinterpret_cast<const Real *>(a.q) + ((int64_t)e * a.G + g) * 3; }
+    __device__ const Real *dir() const { return reinterpret_cast<const Real *>(a.dirs) + 3 * d; }
+    __device__ int code(int f) const { return a.inflow[3 * k + f]; }
+    __device__ int bwrite(int f) const { return a.bwrite[3 * k + f]; }
+    __device__ int slot() const { return a.task_slot[k]; }
+    // upstream flux of inflow code c >= 0 (a storage slot) or c <= -4 (boundary entry)
+    __device__ const Real *upstream(int c, int g) const {
+        return c >= 0 ? reinterpret_cast<const Real *>(a.psi) + ((int64_t)c * a.G + g) * 3
+                      : reinterpret_cast<const Real *>(a.bnd_in) + ((int64_t)(-4 - c) * a.G + g) * 3;
+    }
+    __device__ void store_local(int, int, const Real *) const {}
+};
+
+// LDS copy of one tile task: element data [tile element][kSnElemReals], (Sigma_t, q)
+// [tile element][G][4], item records [item][kSnRecInts], the fluxes entering from other
+// tiles or the boundary [entry][G][3], the direction group's directions, and the tile's
+// own fluxes in compressed slots [slot][tgroup][G][3]. Polar direction pp of an item reads
+// its record with the offsets of the record's layout (entries, boundary writes and storage
+// slots of the item's directions are consecutive).
+template <typename Real> struct SnLdsSrc {
+    const SnStepArgs &a;
+    const Real *el, *sq, *ext, *dirs;
+    Real *psi_l;
+    const int *tk;
+    int it, loc, pp;
+    __device__ const Real *mass() const { return el + loc * kSnElemReals; }
+    __device__ Real gradw() const { return el[loc * kSnElemReals + 6]; }
+    __device__ const Real *nrm(int f) const { return el + loc * kSnElemReals + 7 + 2 * f; }
+    __device__ const Real *fmass(int f) const { return el + loc * kSnElemReals + 13 + 6 * f; }
+    __device__ const Real *fcpl(int f) const { return el + loc * kSnElemReals + 31 + 9 * f; }
+    __device__ Real sigt(int g) const { return sq[(loc * a.G + g) * 4]; }
+    __device__ const Real *q(int g) const { return sq + (loc * a.G + g) * 4 + 1; }
+    __device__ const Real *dir() const { return dirs + 3 * pp; }
+    __device__ int code(int f) const {
+        const int c = tk[it * kSnRecInts + 2 + f];
+        if (c <= -4) return c - pp;
+        return (c >= 0 && !(c & kSnLocalFlag)) ? c + pp : c;
+    }
+    __device__ int bwrite(int f) const {
+        const int w = tk[it * kSnRecInts + 5 + f];
+        return w >= 0 ? w + pp : -1;
+    }
+    __device__ int slot() const {
+        const int sl = tk[it * kSnRecInts + 8];
+        return sl >= 0 ? sl + pp : -1;
+    }
+    // c >= 0 with kSnLocalFlag: the tile's own flux of that element; c >= 0 with
+    // kSnExtFlag: staged entry (another tile's slot); c <= -4: staged entry -4 - c (the
+    // boundary buffer)
+    __device__ const Real *upstream(int c, int g) const {
+        if (c < 0) return ext + ((-4 - c) * a.G + g) * 3;
+        return (c & kSnLocalFlag) ? psi_l + (((c & ~kSnLocalFlag) * a.tgroup + pp) * a.G + g) * 3
+                                  : ext + ((c & ~kSnExtFlag) * a.G + g) * 3;
+    }
+    __device__ void store_local(int g, int, const Real *x) const {
+        const int ls = tk[it * kSnRecInts + 1];
+        if (ls < 0) return;   // read by no element of the tile
+        Real *pl = psi_l + ((ls * a.tgroup + pp) * a.G + g) * 3;
+        pl[0] = x[0];
+        pl[1] = x[1];
+        pl[2] = x[2];
+    }
+};
+
+// The local solve of one task (element, direction) for group g, shared by both
+// schedules: A = Sigma_t M - (Omega . grad u) int u + outflow face terms, b = M q -
+// inflow face terms, Gaussian elimination with partial pivoting. Writes psi to the task's
+// storage slot (slot >= 0), to the boundary buffer on reflective outflow faces and, tiled,
+// to the tile's LDS copy; returns w psi in contrib.
+template <typename Real, typename Src>
+__device__ __forceinline__ void sn_task(const SnStepArgs &a, const Src &S, int g, double (&contrib)[3]) {
+    const int G = a.G;
     Real *__restrict__ psi = reinterpret_cast<Real *>(a.psi);
-    const Real *__restrict__ bnd_in = reinterpret_cast<const Real *>(a.bnd_in);
     Real *__restrict__ bnd_out = reinterpret_cast<Real *>(a.bnd_out);
-    double contrib[3] = {0.0, 0.0, 0.0};
-    const int64_t kg = run / G;
-    const int g = int(run - kg * G);
-    if (valid) {
-        const int64_t k = a.k0 + kg * TG + pp;
-        const int e = a.task_e[k];
-        const int d = a.task_d[k];
-        const Real ox = dirs[3 * d], oy = dirs[3 * d + 1], wd = dirs[3 * d + 2];
-        const Real st = sigt[(int64_t)e * G + g];
-        const Real *m = mass + (int64_t)e * 6;
-        const Real M[9] = {m[0], m[1], m[2], m[1], m[3], m[4], m[2], m[4], m[5]};
-        Real A[9], b[3];
+    const Real *dr = S.dir();
+    const Real ox = dr[0], oy = dr[1], wd = dr[2];
+    const Real st = S.sigt(g);
+    const Real *m = S.mass();
+    const Real M[9] = {m[0], m[1], m[2], m[1], m[3], m[4], m[2], m[4], m[5]};
+    Real A[9], b[3];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) A[i] = st * M[i];
-        const Real gw = gradw[e];
-        A[3] -= ox * gw;
-        A[6] -= oy * gw;
-        const Real *qe = q + ((int64_t)e * G + g) * 3;
+    for (int i = 0; i < 9; ++i) A[i] = st * M[i];
+    const Real gw = S.gradw();
+    A[3] -= ox * gw;
+    A[6] -= oy * gw;
+    const Real *qe = S.q(g);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) b[j] = M[3 * j] * qe[0] + M[3 * j + 1] * qe[1] + M[3 * j + 2] * qe[2];
+    for (int j = 0; j < 3; ++j) b[j] = M[3 * j] * qe[0] + M[3 * j + 1] * qe[1] + M[3 * j + 2] * qe[2];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const int code = a.inflow[3 * k + f];
-            if (code == kSnVacuum) continue;
-            const Real on = ox * nrm[((int64_t)e * 3 + f) * 2] + oy * nrm[((int64_t)e * 3 + f) * 2 + 1];
-            const Real *E = fmass + ((int64_t)e * 3 + f) * 6;
-            if (code == kSnOutflow) {
-                const Real Ef[9] = {E[0], E[1], E[2], E[1], E[3], E[4], E[2], E[4], E[5]};
+    for (int f = 0; f < 3; ++f) {
+        const int code = S.code(f);
+        if (code == kSnVacuum) continue;
+        const Real *nf = S.nrm(f);
+        const Real on = ox * nf[0] + oy * nf[1];
+        const Real *E = S.fmass(f);
+        if (code == kSnOutflow) {
+            const Real Ef[9] = {E[0], E[1], E[2], E[1], E[3], E[4], E[2], E[4], E[5]};
 #pragma unroll
-                for (int i = 0; i < 9; ++i) A[i] += on * Ef[i];
-            } else if (code >= 0) {
-                const Real *pu = psi + ((int64_t)code * G + g) * 3;
-                const Real u0 = pu[0], u1 = pu[1], u2 = pu[2];
-                const Real *C = fcpl + ((int64_t)e * 3 + f) * 9;
+            for (int i = 0; i < 9; ++i) A[i] += on * Ef[i];
+        } else if (code >= 0) {
+            // interior inflow: upstream flux through the coupling matrix
+            const Real *pu = S.upstream(code, g);
+            const Real u0 = pu[0], u1 = pu[1], u2 = pu[2];
+            const Real *C = S.fcpl(f);
 #pragma unroll
-                for (int j = 0; j < 3; ++j) b[j] -= on * (C[3 * j] * u0 + C[3 * j + 1] * u1 + C[3 * j + 2] * u2);
-            } else {
-                const Real *pb = bnd_in + ((int64_t)(-4 - code) * G + g) * 3;
-                const Real u0 = pb[0], u1 = pb[1], u2 = pb[2];
-                const Real Ef[9] = {E[0], E[1], E[2], E[1], E[3], E[4], E[2], E[4], E[5]};
+            for (int j = 0; j < 3; ++j) b[j] -= on * (C[3 * j] * u0 + C[3 * j + 1] * u1 + C[3 * j + 2] * u2);
+        } else {
+            // reflective boundary inflow (code <= -4) through the element's own face matrix
+            const Real *pb = S.upstream(code, g);
+            const Real u0 = pb[0], u1 = pb[1], u2 = pb[2];
+            const Real Ef[9] = {E[0], E[1], E[2], E[1], E[3], E[4], E[2], E[4], E[5]};
 #pragma unroll
-                for (int j = 0; j < 3; ++j) b[j] -= on * (Ef[3 * j] * u0 + Ef[3 * j + 1] * u1 + Ef[3 * j + 2] * u2);
-            }
-        }
-        // Gaussian elimination with partial pivoting
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            int piv = c;
-#pragma unroll
-            for (int r = c + 1; r < 3; ++r)
-                if (fabs(A[3 * r + c]) > fabs(A[3 * piv + c])) piv = r;
-            if (piv != c) {
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const Real tmp = A[3 * c + j];
-                    A[3 * c + j] = A[3 * piv + j];
-                    A[3 * piv + j] = tmp;
-                }
-                const Real tb = b[c];
-                b[c] = b[piv];
-                b[piv] = tb;
-            }
-#pragma unroll
-            for (int r = c + 1; r < 3; ++r) {
-                const Real f = A[3 * r + c] / A[3 * c + c];
-#pragma unroll
-                for (int j = c; j < 3; ++j) A[3 * r + j] -= f * A[3 * c + j];
-                b[r] -= f * b[c];
-            }
-        }
-        Real x[3];
-        x[2] = b[2] / A[8];
-        x[1] = (b[1] - A[5] * x[2]) / A[4];
-        x[0] = (b[0] - A[1] * x[1] - A[2] * x[2]) / A[0];
-        Real *ps = psi + ((int64_t)a.task_slot[k] * G + g) * 3;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            ps[i] = x[i];
-            contrib[i] = (double)(wd * x[i]);
-        }
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const int wi = a.bwrite[3 * k + f];
-            if (wi >= 0) {
-                Real *o = bnd_out + ((int64_t)wi * G + g) * 3;
-                o[0] = x[0];
-                o[1] = x[1];
-                o[2] = x[2];
-            }
+            for (int j = 0; j < 3; ++j) b[j] -= on * (Ef[3 * j] * u0 + Ef[3 * j + 1] * u1 + Ef[3 * j + 2] * u2);
         }
     }
-    // sum each run onto its first lane; every lane of the wavefront takes part in the
-    // shuffles (idle lanes carry zeros, and a run never crosses a wavefront)
+    // Gaussian elimination with partial pivoting; one correctly rounded reciprocal per
+    // pivot (three divisions instead of six; the hardware's approximate FP32 reciprocal
+    // biased the eigenvalue by 2e-7 after a dozen iterations and is not used)
+    Real rp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+#pragma unroll
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(A[3 * r + c]) > fabs(A[3 * piv + c])) piv = r;
+        if (piv != c) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const Real tmp = A[3 * c + j];
+                A[3 * c + j] = A[3 * piv + j];
+                A[3 * piv + j] = tmp;
+            }
+            const Real tb = b[c];
+            b[c] = b[piv];
+            b[piv] = tb;
+        }
+        rp[c] = Real(1) / A[3 * c + c];
+#pragma unroll
+        for (int r = c + 1; r < 3; ++r) {
+            const Real f = A[3 * r + c] * rp[c];
+#pragma unroll
+            for (int j = c; j < 3; ++j) A[3 * r + j] -= f * A[3 * c + j];
+            b[r] -= f * b[c];
+        }
+    }
+    Real x[3];
+    x[2] = b[2] * rp[2];
+    x[1] = (b[1] - A[5] * x[2]) * rp[1];
+    x[0] = (b[0] - A[1] * x[1] - A[2] * x[2]) * rp[0];
+    const int sl = S.slot();
+    if (sl >= 0) {
+        Real *ps = psi + ((int64_t)sl * G + g) * 3;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ps[i] = x[i];
+    }
+    S.store_local(g, 0, x);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) contrib[i] = (double)(wd * x[i]);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int wi = S.bwrite(f);
+        if (wi >= 0) {
+            Real *o = bnd_out + ((int64_t)wi * G + g) * 3;
+            o[0] = x[0];
+            o[1] = x[1];
+            o[2] = x[2];
+        }
+    }
+}
+
+// sums each run of TG lanes onto its first lane, which stores it at run_acc row r
+// (direction group, element); every lane of the wavefront takes part in the shuffles (idle
+// lanes carry zeros, and a run never crosses a wavefront)
+template <typename Real>
+__device__ __forceinline__ void sn_store_run(const SnStepArgs &a, int pp, bool valid, int64_t r, int g, double (&contrib)[3]) {
+    const int TG = a.tgroup;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         double sum = contrib[i];
@@ -150,23 +220,146 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStep
         contrib[i] = sum;
     }
     if (valid && pp == 0) {
-        Real *ra = reinterpret_cast<Real *>(a.run_acc) + ((a.k0 / TG + kg) * G + g) * 3;
+        Real *ra = reinterpret_cast<Real *>(a.run_acc) + (r * a.G + g) * 3;
 #pragma unroll
         for (int i = 0; i < 3; ++i) ra[i] = (Real)contrib[i];
     }
 }
 
-// Scalar-flux moments of every element: the sum of its runs' contributions, in a fixed
-// order (run index), one thread per (element, group, moment).
+// One sweep step of the level schedule: every (element, direction) task of one dependency
+// level, for every group, one thread per (task, group). A run of tgroup consecutive tasks
+// (the polar directions of one element and azimuth) sits on adjacent lanes of one
+// wavefront for each group (64 / tgroup runs per wavefront, the remaining lanes idle), so
+// the lanes of a run read the same element data and their contributions to the element's
+// scalar-flux moments are summed across the run with wavefront shuffles and stored once
+// per run (no atomics; k_sn_gather adds them after the last level). The upstream elements
+// of a task belong to earlier levels, whose angular fluxes sit in their storage slots.
+template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStepArgs a) {
+    const int G = a.G, TG = a.tgroup;
+    const int runs_per_wave = 64 / TG;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int pp = lane % TG;
+    const int64_t run = wave * runs_per_wave + lane / TG;
+    const int64_t nrun = (a.k1 - a.k0) / TG * G;
+    const bool valid = lane < runs_per_wave * TG && run < nrun;
+    double contrib[3] = {0.0, 0.0, 0.0};
+    const int64_t kg = run / G;
+    const int g = int(run - kg * G);
+    const int64_t k = a.k0 + kg * TG + pp;
+    int64_t r = 0;
+    if (valid) {
+        const SnGlobalSrc<Real> S(a, k);
+        sn_task<Real>(a, S, g, contrib);
+        r = (int64_t)(S.d / TG) * a.T + S.e;
+    }
+    sn_store_run<Real>(a, pp, valid, r, g, contrib);
+}
+
+// Tiled schedule: one block per (tile, direction group) of one tile level. The block first
+// copies everything its tasks read into LDS in one round of independent loads (element
+// data, Sigma_t and q of the tile's elements, the item records, the fluxes entering from
+// earlier tiles and from the boundary, the directions), then walks the tile's own
+// dependency levels with a workgroup barrier between two of them, reading only LDS: the
+// tile's own fluxes stay there in slots reused once their last reader in the tile is done,
+// fluxes read by a later tile go to storage slots.
+template <typename Real> __global__ void __launch_bounds__(256) k_sn_tile(SnStepArgs a, SnTileArgs t) {
+    extern __shared__ __align__(16) unsigned char sn_lds[];
+    Real *psi_l = reinterpret_cast<Real *>(sn_lds + t.lds_off[kSnLdsPsi]);
+    Real *el = reinterpret_cast<Real *>(sn_lds + t.lds_off[kSnLdsElem]);
+    Real *sq = reinterpret_cast<Real *>(sn_lds + t.lds_off[kSnLdsSq]);
+    Real *ext = reinterpret_cast<Real *>(sn_lds + t.lds_off[kSnLdsExt]);
+    Real *dl = reinterpret_cast<Real *>(sn_lds + t.lds_off[kSnLdsDir]);
+    int *tk = reinterpret_cast<int *>(sn_lds + t.lds_off[kSnLdsTask]);
+    int *eg = reinterpret_cast<int *>(sn_lds + t.lds_off[kSnLdsElemId]);
+    int *fo = reinterpret_cast<int *>(sn_lds + t.lds_off[kSnLdsFine]);
+    const int G = a.G, TG = a.tgroup;
+    const int64_t tt = t.tt0 + blockIdx.x;
+    const int64_t ibase = t.tt_task[tt] / TG;
+    const int nit = int(t.tt_task[tt + 1] / TG - ibase);
+    const int tile = t.tt_tile[tt], dg = t.tt_dg[tt];
+    const int toff = t.tile_off[tile], nel = t.tile_off[tile + 1] - toff;
+    const int x0 = t.ext_off[tt], nx = t.ext_off[tt + 1] - x0;
+    const int f0 = t.tt_fine[tt], nf = t.tt_fine[tt + 1] - f0;   // nf - 1 levels
+    const Real *__restrict__ gmass = reinterpret_cast<const Real *>(a.mass);
+    const Real *__restrict__ ggw = reinterpret_cast<const Real *>(a.gradw);
+    const Real *__restrict__ gnrm = reinterpret_cast<const Real *>(a.nrm);
+    const Real *__restrict__ gfm = reinterpret_cast<const Real *>(a.fmass);
+    const Real *__restrict__ gfc = reinterpret_cast<const Real *>(a.fcpl);
+    const Real *__restrict__ gst = reinterpret_cast<const Real *>(a.sigt);
+    const Real *__restrict__ gq = reinterpret_cast<const Real *>(a.q);
+    const Real *__restrict__ gpsi = reinterpret_cast<const Real *>(a.psi);
+    const Real *__restrict__ gbnd = reinterpret_cast<const Real *>(a.bnd_in);
+    const Real *__restrict__ gdir = reinterpret_cast<const Real *>(a.dirs);
+    // ---- stage
+    for (int i = threadIdx.x; i < nel * kSnElemReals; i += blockDim.x) {
+        const int l = i / kSnElemReals, c = i - l * kSnElemReals;
+        const int64_t e = t.tile_elems[toff + l];
+        Real v;
+        if (c < 6) v = gmass[e * 6 + c];
+        else if (c == 6) v = ggw[e];
+        else if (c < 13) v = gnrm[e * 6 + (c - 7)];
+        else if (c < 31) v = gfm[e * 18 + (c - 13)];
+        else v = gfc[e * 27 + (c - 31)];
+        el[i] = v;
+    }
+    for (int i = threadIdx.x; i < nel * G; i += blockDim.x) {
+        const int l = i / G, g = i - l * G;
+        const int64_t e = t.tile_elems[toff + l];
+        sq[i * 4] = gst[e * G + g];
+        sq[i * 4 + 1] = gq[(e * G + g) * 3];
+        sq[i * 4 + 2] = gq[(e * G + g) * 3 + 1];
+        sq[i * 4 + 3] = gq[(e * G + g) * 3 + 2];
+    }
+    for (int i = threadIdx.x; i < nit * kSnRecInts; i += blockDim.x) tk[i] = t.rec[ibase * kSnRecInts + i];
+    for (int i = threadIdx.x; i < nx * G; i += blockDim.x) {
+        const int j = i / G, g = i - j * G;
+        const int src = t.ext_src[x0 + j];
+        const Real *p = src >= 0 ? gpsi + ((int64_t)src * G + g) * 3 : gbnd + ((int64_t)(-4 - src) * G + g) * 3;
+        ext[i * 3] = p[0];
+        ext[i * 3 + 1] = p[1];
+        ext[i * 3 + 2] = p[2];
+    }
+    for (int i = threadIdx.x; i < TG * 3; i += blockDim.x) dl[i] = gdir[(int64_t)dg * TG * 3 + i];
+    for (int i = threadIdx.x; i < nel; i += blockDim.x) eg[i] = t.tile_elems[toff + i];
+    for (int i = threadIdx.x; i < nf; i += blockDim.x) fo[i] = t.fine_off[f0 + i];
+    __syncthreads();
+    // ---- the tile's levels
+    const int runs_per_wave = 64 / TG;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int pp = lane % TG;
+    SnLdsSrc<Real> S{a, el, sq, ext, dl, psi_l, tk, 0, 0, pp};
+    for (int fl = 0; fl + 1 < nf; ++fl) {
+        const int k0 = fo[fl], nrun = (fo[fl + 1] - k0) / TG * G;
+        for (int r0 = wave * runs_per_wave; r0 < nrun; r0 += nwave * runs_per_wave) {
+            const int run = r0 + lane / TG;
+            const bool valid = lane < runs_per_wave * TG && run < nrun;
+            double contrib[3] = {0.0, 0.0, 0.0};
+            const int kg = run / G;
+            const int g = run - kg * G;
+            int64_t r = 0;
+            if (valid) {
+                S.it = k0 / TG + kg;
+                S.loc = tk[S.it * kSnRecInts];
+                sn_task<Real>(a, S, g, contrib);
+                r = (int64_t)dg * a.T + eg[S.loc];
+            }
+            sn_store_run<Real>(a, pp, valid, r, g, contrib);
+        }
+        __syncthreads();   // this level's LDS fluxes before the next level reads them
+    }
+}
+
+// Scalar-flux moments of every element: the sum over the direction groups, in direction
+// order (the same order for both schedules), one thread per (element, group, moment);
+// run_acc is [direction group][T][G][3], so each term of the sum is a coalesced read.
 template <typename Real>
-__global__ void k_sn_gather(const Real *__restrict__ run_acc, const int *__restrict__ elem_off,
-                            const int *__restrict__ elem_runs, double *__restrict__ phi_acc, int T, int G) {
+__global__ void k_sn_gather(const Real *__restrict__ run_acc, double *__restrict__ phi_acc, int T, int G, int ndg) {
     const int64_t n = (int64_t)T * G * 3;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int e = int(t / (3 * G));
-        const int gi = int(t - (int64_t)e * 3 * G);
         double acc = 0.0;
-        for (int j = elem_off[e]; j < elem_off[e + 1]; ++j) acc += (double)run_acc[(int64_t)elem_runs[j] * G * 3 + gi];
+        for (int j = 0; j < ndg; ++j) acc += (double)run_acc[(int64_t)j * n + t];
         phi_acc[t] = acc;
     }
 }
@@ -373,11 +566,18 @@ void launch_sn_step(const SnStepArgs &a, int precision, hipStream_t s) {
 void launch_sn_gather(const DevSN &d, hipStream_t s) {
     const int64_t n = (int64_t)d.T * d.G * 3;
     if (d.precision == MOC_PREC_F64)
-        k_sn_gather<double><<<sn_grid(n), 256, 0, s>>>((const double *)d.run_acc, d.elem_off, d.elem_runs, d.phi_acc,
-                                                        d.T, d.G);
+        k_sn_gather<double><<<sn_grid(n), 256, 0, s>>>((const double *)d.run_acc, d.phi_acc, d.T, d.G, d.ndg);
     else
-        k_sn_gather<float><<<sn_grid(n), 256, 0, s>>>((const float *)d.run_acc, d.elem_off, d.elem_runs, d.phi_acc,
-                                                       d.T, d.G);
+        k_sn_gather<float><<<sn_grid(n), 256, 0, s>>>((const float *)d.run_acc, d.phi_acc, d.T, d.G, d.ndg);
+    sn_check_launch();
+}
+
+void launch_sn_tile(const SnStepArgs &a, const SnTileArgs &t, int nblocks, size_t lds_bytes, int precision, hipStream_t s) {
+    if (nblocks <= 0) return;
+    if (precision == MOC_PREC_F64)
+        k_sn_tile<double><<<(unsigned)nblocks, 256, lds_bytes, s>>>(a, t);
+    else
+        k_sn_tile<float><<<(unsigned)nblocks, 256, lds_bytes, s>>>(a, t);
     sn_check_launch();
 }
 

@@ -18,7 +18,8 @@ from .moc import (MOC_ENOCONV, MOC_OK, PREC, MocError, MocMesh, MocOptions, MocP
 class MocSnInfo(C.Structure):
     _fields_ = [("n_elements", _i32), ("n_directions", _i32), ("n_groups", _i32), ("n_levels", _i32),
                 ("n_tasks", _i64), ("n_slots", _i64), ("n_boundary_faces", _i64), ("device_bytes", _i64),
-                ("setup_ms", _f64), ("tasks_per_thread", _i32)]
+                ("setup_ms", _f64), ("tasks_per_thread", _i32), ("n_tiles", _i32), ("n_tile_levels", _i32),
+                ("max_inner_levels", _i32), ("tile_lds_bytes", _i32), ("n_tile_slots", _i64)]
 
 
 SIGNATURES = {
@@ -30,6 +31,7 @@ SIGNATURES = {
     "moc_sn_get_flux": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "moc_sn_set_external_source": (C.c_int, [C.c_void_p, C.c_void_p]),
     "moc_sn_get_info": (C.c_int, [C.c_void_p, _P(MocSnInfo)]),
+    "moc_sn_set_tiles": (C.c_int, [C.c_void_p, _i32, C.c_void_p]),
     "moc_sn_set_profiling": (C.c_int, [C.c_void_p, _i32]),
     "moc_sn_get_profile": (C.c_int, [C.c_void_p, _P(MocProfile)]),
     "moc_sn_last_error": (C.c_char_p, [C.c_void_p]),
@@ -90,9 +92,7 @@ class SNSolver:
             raise MocError(rc, L.moc_sn_last_error(None).decode())
         self._h = h
         self.device = device
-        inf = MocSnInfo()
-        L.moc_sn_get_info(self._h, C.byref(inf))
-        self.info = {f: getattr(inf, f) for f, _ in MocSnInfo._fields_}
+        self._refresh_info()
         self.T, self.G = int(len(tri)), int(st.shape[1])
 
     def close(self):
@@ -147,6 +147,23 @@ class SNSolver:
             return
         torch.cuda.current_stream().synchronize()
         self._check(lib().moc_sn_set_external_source(self._h, _dptr(q.contiguous())))
+
+    def _refresh_info(self):
+        inf = MocSnInfo()
+        self._check(lib().moc_sn_get_info(self._h, C.byref(inf)))
+        self.info = {f: getattr(inf, f) for f, _ in MocSnInfo._fields_}
+
+    def set_tiles(self, element_tile=None):
+        """Sweep tile by tile: element_tile[e] = tile of triangle e (e.g. its pin cell), or
+        None for level-by-level sweeps."""
+        if element_tile is None:
+            self._check(lib().moc_sn_set_tiles(self._h, 0, None))
+        else:
+            t = np.ascontiguousarray(element_tile, dtype=np.int32)
+            if t.shape != (self.T,):
+                raise ValueError(f"element_tile must have shape ({self.T},)")
+            self._check(lib().moc_sn_set_tiles(self._h, int(t.max()) + 1 if t.size else 0, t.ctypes.data))
+        self._refresh_info()
 
     def set_profiling(self, enable: bool = True):
         self._check(lib().moc_sn_set_profiling(self._h, int(enable)))

@@ -590,6 +590,19 @@ def coarse_cells(p: Problem, nx: int, ny: int):
     return int(len(used)), region_cell.astype(np.int32)
 
 
+def grid_tiles(p: Problem, nx: int, ny: int):
+    """Tiles for the tiled DFEM-SN sweep: an nx x ny Cartesian grid over the bounding box;
+    each triangle goes to the cell holding its centroid, and cells holding no triangle are
+    dropped. On meshes whose edges follow the grid lines (the square lattices with nx, ny =
+    pins per side) every tile is a convex cell. Returns (n_tiles, triangle_tile int32 [T])."""
+    cen = p.xy[p.tri].mean(axis=1)
+    x0, y0, x1, y1 = p.box
+    ix = np.clip(((cen[:, 0] - x0) / (x1 - x0) * nx).astype(np.int64), 0, nx - 1)
+    iy = np.clip(((cen[:, 1] - y0) / (y1 - y0) * ny).astype(np.int64), 0, ny - 1)
+    used, tile = np.unique(iy * nx + ix, return_inverse=True)
+    return int(len(used)), tile.astype(np.int32)
+
+
 # ----------------------------------------------------------------------------------
 # coarse brick grids (diffusion HFEM)
 # ----------------------------------------------------------------------------------

@@ -95,6 +95,38 @@ def test_dfem_host_schedule(case):
     import ctypes
     r = moc.MocResult()
     assert dfem.lib().moc_sn_solve(s._h, 1e-6, ctypes.byref(r)) == moc.MOC_ESTATE
+    # the tiled schedule is built and replay-checked on the host: one tile per element
+    # reproduces the element levels (every tile convex)
+    s.set_tiles(np.arange(info["n_elements"], dtype=np.int32))
+    assert s.info["n_tiles"] == info["n_elements"] and s.info["n_tile_levels"] == info["n_levels"]
+    s.set_tiles(None)
+    assert s.info["n_tiles"] == 0
+
+
+def test_dfem_tiles_host():
+    """Pin-cell tiles of the 17 x 17 lattice mesh: 33 tile levels (a diagonal direction
+    crosses 17 + 17 - 1 pins) instead of 797 element levels; tiles that cut pins in four
+    follow no mesh line and depend on each other in a cycle; oversized tiles and bad
+    indices are refused."""
+    from paper_2607_01591_amd import dfem
+    prob = P.config(2)
+    s = dfem.SNSolver(prob, device=-1)
+    n, tile = P.grid_tiles(prob, 17, 17)
+    s.set_tiles(tile)
+    assert (s.info["n_tiles"], s.info["n_tile_levels"], s.info["n_levels"]) == (289, 33, 797)
+    assert 0 < s.info["n_tile_slots"] < s.info["n_slots"]
+    for bad in (P.grid_tiles(prob, 34, 34)[1], P.grid_tiles(prob, 8, 8)[1]):
+        with pytest.raises(dfem.MocError):
+            s.set_tiles(bad)
+    assert s.info["n_tiles"] == 289      # a refused tiling leaves the previous one
+    t2 = tile.copy()
+    t2[0] = -1
+    with pytest.raises(dfem.MocError):
+        s.set_tiles(t2)
+    t3 = tile.copy()
+    t3[t3 == 5] = 4                      # tile 5 left empty
+    with pytest.raises(dfem.MocError):
+        s.set_tiles(t3)
 
 
 def test_library_exports_every_hfem_symbol():
