@@ -550,6 +550,7 @@ static void sn_enqueue_sweep(moc_sn_ctx *c, int parity, hipStream_t s) {
         ta.ext_src = t.ext_src;
         ta.rec = t.rec;
         for (int r = 0; r < kSnLdsCount; ++r) ta.lds_off[r] = t.lds_off[r];
+        ta.el_stride = t.el_stride;
         for (int L = 0; L < t.n_levels; ++L) {
             ta.tt0 = t.lev_off[L];
             launch_sn_tile(a, ta, (int)(t.lev_off[L + 1] - t.lev_off[L]), t.lds_bytes, d.precision, s);
@@ -1004,9 +1005,22 @@ static void sn_set_tiles_impl(moc_sn_ctx *c, int n_tiles, const int32_t *tile_of
     }
     ext_off[ntt] = (int)ext_src.size();
     tl.max_live = max_live;
+    // staged element data per item: the head and, per face, the matrix its direction group
+    // uses (coupling matrix for an interior inflow, face matrix for an outflow or a
+    // reflective inflow, nothing for a vacuum inflow)
+    int el_stride = kSnElemHead;
+    for (int64_t it = 0; it < nitem; ++it) {
+        int n = kSnElemHead;
+        for (int f = 0; f < 3; ++f) {
+            const int c = rec[(size_t)it * kSnRecInts + 2 + f];
+            n += c == kSnVacuum ? 0 : (c >= 0 ? 9 : 6);
+        }
+        el_stride = std::max(el_stride, n);
+    }
+    tl.el_stride = el_stride;
     // LDS layout of one block (16-byte aligned regions)
     {
-        const size_t sz[kSnLdsCount] = {(size_t)max_live * TG * G * 3 * rs, (size_t)max_tile * kSnElemReals * rs,
+        const size_t sz[kSnLdsCount] = {(size_t)max_live * TG * G * 3 * rs, (size_t)max_items * el_stride * rs,
                                         (size_t)max_tile * G * 4 * rs,      (size_t)max_ext * G * 3 * rs,
                                         (size_t)TG * 3 * rs,                (size_t)max_items * kSnRecInts * sizeof(int),
                                         (size_t)max_tile * sizeof(int),     (size_t)max_fine * sizeof(int)};

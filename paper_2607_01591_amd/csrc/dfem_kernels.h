@@ -19,8 +19,8 @@ constexpr int kSnLocalFlag = 1 << 30;
 constexpr int kSnExtFlag = 1 << 29;
 constexpr int kSnRecInts = 9;           // item record: tile element, LDS slot, 3 inflow codes,
                                         // 3 boundary writes, storage slot (polar direction 0)
-constexpr int kSnElemReals = 58;        // staged element data: mass 6, gradw 1, normals 6,
-                                        // face matrices 18, coupling matrices 27
+constexpr int kSnElemHead = 13;         // staged element data: mass 6, gradw 1, normals 6,
+                                        // then one face block per face (9, 6 or 0 reals)
 // regions of a tile block's LDS (byte offsets in SnTileArgs::lds_off)
 enum { kSnLdsPsi = 0, kSnLdsElem, kSnLdsSq, kSnLdsExt, kSnLdsDir, kSnLdsTask, kSnLdsElemId, kSnLdsFine, kSnLdsCount };
 // >= 0: inflow from the upstream element's storage slot; <= -4: reflective inflow read
@@ -87,6 +87,7 @@ struct SnTileArgs {
                                        // slot (>= 0) or a boundary code (<= -4)
     const int *rec;                    // item records (item = tile task element, task / tgroup)
     int64_t tt0;
+    int el_stride;                     // reals of one item's staged element data
     unsigned lds_off[kSnLdsCount];
 };
 
@@ -100,6 +101,7 @@ struct DevSNTiles {
     std::vector<int64_t> lev_off;       // host [n_levels + 1]: tile tasks of each tile level
     unsigned lds_off[kSnLdsCount] = {};
     int max_live = 0;                   // LDS flux slots of one tile task
+    int el_stride = 0;                  // reals of one item's staged element data
     int *rec = nullptr;                 // item records [item][kSnRecInts]
     int64_t *tt_task = nullptr;
     int *tt_fine = nullptr, *fine_off = nullptr, *tt_tile = nullptr, *tt_dg = nullptr;

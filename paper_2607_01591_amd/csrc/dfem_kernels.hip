@@ -47,7 +47,13 @@ template <typename Real> struct SnGlobalSrc {
     __device__ void store_local(int, int, const Real *) const {}
 };
 
-// LDS copy of one tile task: element data [tile element][kSnElemReals], (Sigma_t, q)
+// Size of the face block a direction group needs for inflow code c: the coupling matrix
+// (9) for an interior inflow, the face matrix (6) for an outflow or a reflective inflow,
+// nothing for a vacuum inflow.
+__device__ __forceinline__ int sn_face_reals(int c) { return c == kSnVacuum ? 0 : (c >= 0 ? 9 : 6); }
+
+// LDS copy of one tile task: element data per item [item][el_stride] (mass 6, gradw 1,
+// normals 6, then per face only the matrix the item's direction group uses), (Sigma_t, q)
 // [tile element][G][4], item records [item][kSnRecInts], the fluxes entering from other
 // tiles or the boundary [entry][G][3], the direction group's directions, and the tile's
 // own fluxes in compressed slots [slot][tgroup][G][3]. Polar direction pp of an item reads
@@ -59,11 +65,13 @@ template <typename Real> struct SnLdsSrc {
     Real *psi_l;
     const int *tk;
     int it, loc, pp;
-    __device__ const Real *mass() const { return el + loc * kSnElemReals; }
-    __device__ Real gradw() const { return el[loc * kSnElemReals + 6]; }
-    __device__ const Real *nrm(int f) const { return el + loc * kSnElemReals + 7 + 2 * f; }
-    __device__ const Real *fmass(int f) const { return el + loc * kSnElemReals + 13 + 6 * f; }
-    __device__ const Real *fcpl(int f) const { return el + loc * kSnElemReals + 31 + 9 * f; }
+    int eo, fo1, fo2;    // the item's element block and the offsets of its face 1 and 2 blocks
+    __device__ const Real *mass() const { return el + eo; }
+    __device__ Real gradw() const { return el[eo + 6]; }
+    __device__ const Real *nrm(int f) const { return el + eo + 7 + 2 * f; }
+    __device__ const Real *face(int f) const { return el + eo + 13 + (f == 0 ? 0 : f == 1 ? fo1 : fo2); }
+    __device__ const Real *fmass(int f) const { return face(f); }
+    __device__ const Real *fcpl(int f) const { return face(f); }
     __device__ Real sigt(int g) const { return sq[(loc * a.G + g) * 4]; }
     __device__ const Real *q(int g) const { return sq + (loc * a.G + g) * 4 + 1; }
     __device__ const Real *dir() const { return dirs + 3 * pp; }
@@ -292,16 +300,31 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_tile(SnStep
     const Real *__restrict__ gbnd = reinterpret_cast<const Real *>(a.bnd_in);
     const Real *__restrict__ gdir = reinterpret_cast<const Real *>(a.dirs);
     // ---- stage
-    for (int i = threadIdx.x; i < nel * kSnElemReals; i += blockDim.x) {
-        const int l = i / kSnElemReals, c = i - l * kSnElemReals;
-        const int64_t e = t.tile_elems[toff + l];
-        Real v;
-        if (c < 6) v = gmass[e * 6 + c];
-        else if (c == 6) v = ggw[e];
-        else if (c < 13) v = gnrm[e * 6 + (c - 7)];
-        else if (c < 31) v = gfm[e * 18 + (c - 13)];
-        else v = gfc[e * 27 + (c - 31)];
-        el[i] = v;
+    const int els = t.el_stride;
+    for (int i = threadIdx.x; i < nit; i += blockDim.x) {   // one thread per item's element block
+        const int *r = t.rec + (ibase + i) * kSnRecInts;
+        const int64_t e = t.tile_elems[toff + r[0]];
+        Real *o = el + i * els;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = gmass[e * 6 + c];
+        o[6] = ggw[e];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[7 + c] = gnrm[e * 6 + c];
+        int off = 13;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const int code = r[2 + f];
+            if (code == kSnVacuum) continue;
+            if (code >= 0) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) o[off + c] = gfc[e * 27 + f * 9 + c];
+                off += 9;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) o[off + c] = gfm[e * 18 + f * 6 + c];
+                off += 6;
+            }
+        }
     }
     for (int i = threadIdx.x; i < nel * G; i += blockDim.x) {
         const int l = i / G, g = i - l * G;
@@ -329,7 +352,7 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_tile(SnStep
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     const int pp = lane % TG;
-    SnLdsSrc<Real> S{a, el, sq, ext, dl, psi_l, tk, 0, 0, pp};
+    SnLdsSrc<Real> S{a, el, sq, ext, dl, psi_l, tk, 0, 0, pp, 0, 0, 0};
     for (int fl = 0; fl + 1 < nf; ++fl) {
         const int k0 = fo[fl], nrun = (fo[fl + 1] - k0) / TG * G;
         for (int r0 = wave * runs_per_wave; r0 < nrun; r0 += nwave * runs_per_wave) {
@@ -342,6 +365,9 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_tile(SnStep
             if (valid) {
                 S.it = k0 / TG + kg;
                 S.loc = tk[S.it * kSnRecInts];
+                S.eo = S.it * els;
+                S.fo1 = sn_face_reals(tk[S.it * kSnRecInts + 2]);
+                S.fo2 = S.fo1 + sn_face_reals(tk[S.it * kSnRecInts + 3]);
                 sn_task<Real>(a, S, g, contrib);
                 r = (int64_t)dg * a.T + eg[S.loc];
             }
