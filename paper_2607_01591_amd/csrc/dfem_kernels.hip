@@ -45,6 +45,7 @@ template <typename Real> struct SnGlobalSrc {
                       : reinterpret_cast<const Real *>(a.bnd_in) + ((int64_t)(-4 - c) * a.G + g) * 3;
     }
     __device__ void store_local(int, int, const Real *) const {}
+    __device__ int ng() const { return a.G; }
 };
 
 // Size of the face block a direction group needs for inflow code c: the coupling matrix
@@ -59,21 +60,23 @@ __device__ __forceinline__ int sn_face_reals(int c) { return c == kSnVacuum ? 0 
 // own fluxes in compressed slots [slot][tgroup][G][3]. Polar direction pp of an item reads
 // its record with the offsets of the record's layout (entries, boundary writes and storage
 // slots of the item's directions are consecutive).
-template <typename Real> struct SnLdsSrc {
+template <typename Real, int kG, int kTG> struct SnLdsSrc {
     const SnStepArgs &a;
     const Real *el, *sq, *ext, *dirs;
     Real *psi_l;
     const int *tk;
     int it, loc, pp;
     int eo, fo1, fo2;    // the item's element block and the offsets of its face 1 and 2 blocks
+    __device__ int ng() const { return kG > 0 ? kG : a.G; }
+    __device__ int ntg() const { return kTG > 0 ? kTG : a.tgroup; }
     __device__ const Real *mass() const { return el + eo; }
     __device__ Real gradw() const { return el[eo + 6]; }
     __device__ const Real *nrm(int f) const { return el + eo + 7 + 2 * f; }
     __device__ const Real *face(int f) const { return el + eo + 13 + (f == 0 ? 0 : f == 1 ? fo1 : fo2); }
     __device__ const Real *fmass(int f) const { return face(f); }
     __device__ const Real *fcpl(int f) const { return face(f); }
-    __device__ Real sigt(int g) const { return sq[(loc * a.G + g) * 4]; }
-    __device__ const Real *q(int g) const { return sq + (loc * a.G + g) * 4 + 1; }
+    __device__ Real sigt(int g) const { return sq[(loc * ng() + g) * 4]; }
+    __device__ const Real *q(int g) const { return sq + (loc * ng() + g) * 4 + 1; }
     __device__ const Real *dir() const { return dirs + 3 * pp; }
     __device__ int code(int f) const {
         const int c = tk[it * kSnRecInts + 2 + f];
@@ -92,14 +95,14 @@ template <typename Real> struct SnLdsSrc {
     // kSnExtFlag: staged entry (another tile's slot); c <= -4: staged entry -4 - c (the
     // boundary buffer)
     __device__ const Real *upstream(int c, int g) const {
-        if (c < 0) return ext + ((-4 - c) * a.G + g) * 3;
-        return (c & kSnLocalFlag) ? psi_l + (((c & ~kSnLocalFlag) * a.tgroup + pp) * a.G + g) * 3
-                                  : ext + ((c & ~kSnExtFlag) * a.G + g) * 3;
+        if (c < 0) return ext + ((-4 - c) * ng() + g) * 3;
+        return (c & kSnLocalFlag) ? psi_l + (((c & ~kSnLocalFlag) * ntg() + pp) * ng() + g) * 3
+                                  : ext + ((c & ~kSnExtFlag) * ng() + g) * 3;
     }
     __device__ void store_local(int g, int, const Real *x) const {
         const int ls = tk[it * kSnRecInts + 1];
         if (ls < 0) return;   // read by no element of the tile
-        Real *pl = psi_l + ((ls * a.tgroup + pp) * a.G + g) * 3;
+        Real *pl = psi_l + ((ls * ntg() + pp) * ng() + g) * 3;
         pl[0] = x[0];
         pl[1] = x[1];
         pl[2] = x[2];
@@ -113,7 +116,7 @@ template <typename Real> struct SnLdsSrc {
 // to the tile's LDS copy; returns w psi in contrib.
 template <typename Real, typename Src>
 __device__ __forceinline__ void sn_task(const SnStepArgs &a, const Src &S, int g, double (&contrib)[3]) {
-    const int G = a.G;
+    const int G = S.ng();
     Real *__restrict__ psi = reinterpret_cast<Real *>(a.psi);
     Real *__restrict__ bnd_out = reinterpret_cast<Real *>(a.bnd_out);
     const Real *dr = S.dir();
@@ -215,9 +218,10 @@ __device__ __forceinline__ void sn_task(const SnStepArgs &a, const Src &S, int g
 // sums each run of TG lanes onto its first lane, which stores it at run_acc row r
 // (direction group, element); every lane of the wavefront takes part in the shuffles (idle
 // lanes carry zeros, and a run never crosses a wavefront)
-template <typename Real>
+template <typename Real, int kG = 0, int kTG = 0>
 __device__ __forceinline__ void sn_store_run(const SnStepArgs &a, int pp, bool valid, int64_t r, int g, double (&contrib)[3]) {
-    const int TG = a.tgroup;
+    const int TG = kTG > 0 ? kTG : a.tgroup;
+    const int G = kG > 0 ? kG : a.G;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         double sum = contrib[i];
@@ -228,7 +232,7 @@ __device__ __forceinline__ void sn_store_run(const SnStepArgs &a, int pp, bool v
         contrib[i] = sum;
     }
     if (valid && pp == 0) {
-        Real *ra = reinterpret_cast<Real *>(a.run_acc) + (r * a.G + g) * 3;
+        Real *ra = reinterpret_cast<Real *>(a.run_acc) + (r * G + g) * 3;
 #pragma unroll
         for (int i = 0; i < 3; ++i) ra[i] = (Real)contrib[i];
     }
@@ -271,7 +275,8 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStep
 // dependency levels with a workgroup barrier between two of them, reading only LDS: the
 // tile's own fluxes stay there in slots reused once their last reader in the tile is done,
 // fluxes read by a later tile go to storage slots.
-template <typename Real> __global__ void __launch_bounds__(256) k_sn_tile(SnStepArgs a, SnTileArgs t) {
+template <typename Real, int kG, int kTG>
+__global__ void __launch_bounds__(256) k_sn_tile(SnStepArgs a, SnTileArgs t) {
     extern __shared__ __align__(16) unsigned char sn_lds[];
     Real *psi_l = reinterpret_cast<Real *>(sn_lds + t.lds_off[kSnLdsPsi]);
     Real *el = reinterpret_cast<Real *>(sn_lds + t.lds_off[kSnLdsElem]);
@@ -281,7 +286,7 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_tile(SnStep
     int *tk = reinterpret_cast<int *>(sn_lds + t.lds_off[kSnLdsTask]);
     int *eg = reinterpret_cast<int *>(sn_lds + t.lds_off[kSnLdsElemId]);
     int *fo = reinterpret_cast<int *>(sn_lds + t.lds_off[kSnLdsFine]);
-    const int G = a.G, TG = a.tgroup;
+    const int G = kG > 0 ? kG : a.G, TG = kTG > 0 ? kTG : a.tgroup;
     const int64_t tt = t.tt0 + blockIdx.x;
     const int64_t ibase = t.tt_task[tt] / TG;
     const int nit = int(t.tt_task[tt + 1] / TG - ibase);
@@ -352,7 +357,7 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_tile(SnStep
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     const int pp = lane % TG;
-    SnLdsSrc<Real> S{a, el, sq, ext, dl, psi_l, tk, 0, 0, pp, 0, 0, 0};
+    SnLdsSrc<Real, kG, kTG> S{a, el, sq, ext, dl, psi_l, tk, 0, 0, pp, 0, 0, 0};
     for (int fl = 0; fl + 1 < nf; ++fl) {
         const int k0 = fo[fl], nrun = (fo[fl + 1] - k0) / TG * G;
         for (int r0 = wave * runs_per_wave; r0 < nrun; r0 += nwave * runs_per_wave) {
@@ -371,7 +376,7 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_tile(SnStep
                 sn_task<Real>(a, S, g, contrib);
                 r = (int64_t)dg * a.T + eg[S.loc];
             }
-            sn_store_run<Real>(a, pp, valid, r, g, contrib);
+            sn_store_run<Real, kG, kTG>(a, pp, valid, r, g, contrib);
         }
         __syncthreads();   // this level's LDS fluxes before the next level reads them
     }
@@ -600,10 +605,16 @@ void launch_sn_gather(const DevSN &d, hipStream_t s) {
 
 void launch_sn_tile(const SnStepArgs &a, const SnTileArgs &t, int nblocks, size_t lds_bytes, int precision, hipStream_t s) {
     if (nblocks <= 0) return;
-    if (precision == MOC_PREC_F64)
-        k_sn_tile<double><<<(unsigned)nblocks, 256, lds_bytes, s>>>(a, t);
-    else
-        k_sn_tile<float><<<(unsigned)nblocks, 256, lds_bytes, s>>>(a, t);
+    // the usual shape (7 groups, 3 polar directions per azimuth) with its sizes known to the
+    // compiler, every other shape through the general instance
+    const bool g7p3 = a.G == 7 && a.tgroup == 3;
+    if (precision == MOC_PREC_F64) {
+        if (g7p3) k_sn_tile<double, 7, 3><<<(unsigned)nblocks, 256, lds_bytes, s>>>(a, t);
+        else k_sn_tile<double, 0, 0><<<(unsigned)nblocks, 256, lds_bytes, s>>>(a, t);
+    } else {
+        if (g7p3) k_sn_tile<float, 7, 3><<<(unsigned)nblocks, 256, lds_bytes, s>>>(a, t);
+        else k_sn_tile<float, 0, 0><<<(unsigned)nblocks, 256, lds_bytes, s>>>(a, t);
+    }
     sn_check_launch();
 }
 
