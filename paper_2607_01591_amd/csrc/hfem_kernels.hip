@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
 // s = V Q (from the previous flux, or V times a caller's emission moments), then
 // a = A^-1 s, then h = C s / 4 = Lambda^-1 M a / 4 (face factor lists per face DoF).
 // Emission: Q_g,i = chi_g F_i / k + sum_{g' != g} Sigma_s,g'->g phi_g',i (+ external).
-template <typename MT>
+template <int NP, int KG, typename MT>
 __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ phi, const double *__restrict__ user,
                                                     const double *__restrict__ scal, const int *__restrict__ mat,
                                                     const int *__restrict__ perm, const double *__restrict__ vol,
@@ -206,7 +206,12 @@ __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ p
                                                     const MT *__restrict__ Ainv, const int *__restrict__ rlist,
                                                     const double *__restrict__ rval, double *__restrict__ s,
                                                     double *__restrict__ h, int64_t red_pg, int64_t all_pg,
-                                                    int64_t nblk0, int G, int Np, int Nft, int nr) {
+                                                    int64_t nblk0, int G_, int Np_, int Nft, int nr) {
+    // NP moments and KG groups known at compile time (KG = 0: G from the argument), so the
+    // loops over groups and moments unroll and their loads issue together
+    const int G = KG > 0 ? KG : G_;
+    constexpr int Np = NP;
+    (void)Np_;
     extern __shared__ double sh[];
     const int npg_blk = 256 / Nft;
     double *sv = sh;                    // [npg_blk][Np]
@@ -231,6 +236,7 @@ __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ p
             const double cg = chi[m * G + g] * inv_k;
             const double *sg = sigs + (int64_t)m * G * G + g;
             q = qext ? qext[src] : 0.0;
+#pragma unroll
             for (int gp = 0; gp < G; ++gp) q += (cg * nsf[m * G + gp] + (gp != g ? sg[gp * G] : 0.0)) * ph[gp * Np];
         }
         const double v = vol[e] * q;
@@ -244,6 +250,7 @@ __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ p
         const MT *Ab = Ainv + blk * Np * npg_blk * Np + t;
         const double *x = sv + pl * Np;
         double acc = 0.0;
+#pragma unroll
         for (int k = 0; k < Np; ++k) acc += (double)Ab[(int64_t)k * npg_blk * Np] * x[k];
         av[t] = acc;
     }
@@ -555,22 +562,38 @@ void launch_hf_assemble(const DevHF &d, hipStream_t s) {
     hf_check_launch();
 }
 
-template <typename MT>
+template <int NP, int KG, typename MT>
 static void hf_prepare_t(const DevHF &d, const double *phi, const double *user, int64_t nb, size_t lds, hipStream_t s) {
-    k_hf_prepare<MT><<<(unsigned)nb, 256, lds, s>>>(phi, user, d.scal, d.mat, d.perm, d.vol, d.sigs, d.nsf, d.chi, d.qext,
+    k_hf_prepare<NP, KG, MT><<<(unsigned)nb, 256, lds, s>>>(phi, user, d.scal, d.mat, d.perm, d.vol, d.sigs, d.nsf, d.chi, d.qext,
                                                     (const MT *)d.Ainv, d.rlist, d.rval, d.s, d.bq,
                                                     (int64_t)d.n_red * d.G, (int64_t)d.N * d.G, d.nblk[0], d.G, d.Np,
                                                     d.Nft, d.nr);
+}
+
+// the 7-group shape with the group count known at compile time, other counts general
+template <int NP>
+static void hf_prepare_np(const DevHF &d, const double *phi, const double *user, int64_t nb, size_t lds, hipStream_t s) {
+    if (d.G == 7) {
+        if (d.mat32) hf_prepare_t<NP, 7, float>(d, phi, user, nb, lds, s);
+        else hf_prepare_t<NP, 7, double>(d, phi, user, nb, lds, s);
+    } else {
+        if (d.mat32) hf_prepare_t<NP, 0, float>(d, phi, user, nb, lds, s);
+        else hf_prepare_t<NP, 0, double>(d, phi, user, nb, lds, s);
+    }
 }
 
 void launch_hf_prepare(const DevHF &d, const double *phi, const double *user, hipStream_t s) {
     const int64_t nb = d.nblk[0] + d.nblk[1];
     if (nb <= 0) return;
     const size_t lds = sizeof(double) * (size_t)d.npg_blk * 2 * d.Np;
-    if (d.mat32)
-        hf_prepare_t<float>(d, phi, user, nb, lds, s);
-    else
-        hf_prepare_t<double>(d, phi, user, nb, lds, s);
+    switch (d.Np) {
+    case 1: hf_prepare_np<1>(d, phi, user, nb, lds, s); break;
+    case 4: hf_prepare_np<4>(d, phi, user, nb, lds, s); break;
+    case 10: hf_prepare_np<10>(d, phi, user, nb, lds, s); break;
+    case 20: hf_prepare_np<20>(d, phi, user, nb, lds, s); break;
+    case 35: hf_prepare_np<35>(d, phi, user, nb, lds, s); break;
+    default: throw Error(MOC_EINVAL, "hfem: unsupported number of moments");
+    }
     hf_check_launch();
 }
 
