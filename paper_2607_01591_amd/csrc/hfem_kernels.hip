@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(64) k_hf_assemble(HfAsmArgs a) {
 // s = V Q (from the previous flux, or V times a caller's emission moments), then
 // a = A^-1 s, then h = C s / 4 = Lambda^-1 M a / 4 (face factor lists per face DoF).
 // Emission: Q_g,i = chi_g F_i / k + sum_{g' != g} Sigma_s,g'->g phi_g',i (+ external).
-template <int NP, int KG, typename MT>
+template <int NP, int NFT, int KG, typename MT>
 __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ phi, const double *__restrict__ user,
                                                     const double *__restrict__ scal, const int *__restrict__ mat,
                                                     const int *__restrict__ perm, const double *__restrict__ vol,
@@ -206,10 +206,11 @@ __global__ void __launch_bounds__(256) k_hf_prepare(const double *__restrict__ p
                                                     const MT *__restrict__ Ainv, const int *__restrict__ rlist,
                                                     const double *__restrict__ rval, double *__restrict__ s,
                                                     double *__restrict__ h, int64_t red_pg, int64_t all_pg,
-                                                    int64_t nblk0, int G_, int Np_, int Nft, int nr) {
-    // NP moments and KG groups known at compile time (KG = 0: G from the argument), so the
-    // loops over groups and moments unroll and their loads issue together
+                                                    int64_t nblk0, int G_, int Np_, int Nft_, int nr) {
+    // NP moments, and KG groups and NFT face DoFs when non-zero, known at compile time, so
+    // the loops over groups and moments unroll and their loads issue together
     const int G = KG > 0 ? KG : G_;
+    const int Nft = NFT > 0 ? NFT : Nft_;
     constexpr int Np = NP;
     (void)Np_;
     extern __shared__ double sh[];
@@ -331,13 +332,17 @@ __global__ void __launch_bounds__(256) k_hf_rb(const MT *__restrict__ R, const d
 // node-groups. Thread (slot, i) loads row i of A^-1 for its node-group while the net
 // currents are gathered into LDS; then u = s - M^T j (M = face area x face factor, from
 // the compact per-moment lists of non-zero face factors), then phi_i = sum_k Ainv_ik u_k.
-template <int NP, typename MT>
+template <int NP, int NFT, int KG, typename MT>
 __global__ void __launch_bounds__(256) k_hf_reconstruct(const MT *__restrict__ Ainv, const int *__restrict__ flist,
                                                         const double *__restrict__ fval, const double *__restrict__ hdim,
                                                         const double *__restrict__ s, const double *__restrict__ jp,
                                                         const int *__restrict__ nbr, const int *__restrict__ perm,
                                                         double *__restrict__ phi, int64_t red_pg, int64_t all_pg,
-                                                        int64_t nblk0, int G, int Nfb, int Nft) {
+                                                        int64_t nblk0, int G_, int Nfb_, int Nft_) {
+    // face DoFs (NFT) and groups (KG) known at compile time when non-zero: the divisions and
+    // index products of the gathers fold
+    const int G = KG > 0 ? KG : G_;
+    const int Nft = NFT > 0 ? NFT : Nft_, Nfb = NFT > 0 ? NFT / 6 : Nfb_;
     extern __shared__ double sh[];
     const int npg_blk = 256 / Nft;
     double *net = sh;                   // [npg_blk][Nft]
@@ -562,23 +567,27 @@ void launch_hf_assemble(const DevHF &d, hipStream_t s) {
     hf_check_launch();
 }
 
-template <int NP, int KG, typename MT>
+template <int NP, int NFT, int KG, typename MT>
 static void hf_prepare_t(const DevHF &d, const double *phi, const double *user, int64_t nb, size_t lds, hipStream_t s) {
-    k_hf_prepare<NP, KG, MT><<<(unsigned)nb, 256, lds, s>>>(phi, user, d.scal, d.mat, d.perm, d.vol, d.sigs, d.nsf, d.chi, d.qext,
+    k_hf_prepare<NP, NFT, KG, MT><<<(unsigned)nb, 256, lds, s>>>(phi, user, d.scal, d.mat, d.perm, d.vol, d.sigs, d.nsf, d.chi, d.qext,
                                                     (const MT *)d.Ainv, d.rlist, d.rval, d.s, d.bq,
                                                     (int64_t)d.n_red * d.G, (int64_t)d.N * d.G, d.nblk[0], d.G, d.Np,
                                                     d.Nft, d.nr);
 }
 
-// the 7-group shape with the group count known at compile time, other counts general
+// the 7-group shapes with the group count (and for face order 1 the face DoFs) known at
+// compile time, other counts general
 template <int NP>
 static void hf_prepare_np(const DevHF &d, const double *phi, const double *user, int64_t nb, size_t lds, hipStream_t s) {
-    if (d.G == 7) {
-        if (d.mat32) hf_prepare_t<NP, 7, float>(d, phi, user, nb, lds, s);
-        else hf_prepare_t<NP, 7, double>(d, phi, user, nb, lds, s);
+    if (NP == 10 && d.G == 7 && d.Nft == 18) {   // volume order 2, face order 1, 7 groups
+        if (d.mat32) hf_prepare_t<NP, 18, 7, float>(d, phi, user, nb, lds, s);
+        else hf_prepare_t<NP, 18, 7, double>(d, phi, user, nb, lds, s);
+    } else if (d.G == 7) {
+        if (d.mat32) hf_prepare_t<NP, 0, 7, float>(d, phi, user, nb, lds, s);
+        else hf_prepare_t<NP, 0, 7, double>(d, phi, user, nb, lds, s);
     } else {
-        if (d.mat32) hf_prepare_t<NP, 0, float>(d, phi, user, nb, lds, s);
-        else hf_prepare_t<NP, 0, double>(d, phi, user, nb, lds, s);
+        if (d.mat32) hf_prepare_t<NP, 0, 0, float>(d, phi, user, nb, lds, s);
+        else hf_prepare_t<NP, 0, 0, double>(d, phi, user, nb, lds, s);
     }
 }
 
@@ -619,24 +628,30 @@ void launch_hf_rb(const DevHF &d, int colour, hipStream_t s) {
     hf_check_launch();
 }
 
-template <int NP, typename MT>
+template <int NP, int NFT, int KG, typename MT>
 static void hf_reconstruct_t(const DevHF &d, double *phi_out, int64_t nb, size_t lds, hipStream_t s) {
-    k_hf_reconstruct<NP, MT><<<(unsigned)nb, 256, lds, s>>>((const MT *)d.Ainv, d.flist, d.fval, d.hdim, d.s, d.jp, d.nbr,
+    k_hf_reconstruct<NP, NFT, KG, MT><<<(unsigned)nb, 256, lds, s>>>((const MT *)d.Ainv, d.flist, d.fval, d.hdim, d.s, d.jp, d.nbr,
                                                             d.perm, phi_out, (int64_t)d.n_red * d.G, (int64_t)d.N * d.G,
                                                             d.nblk[0], d.G, d.Nfb, d.Nft);
 }
 
 template <int NP> static void hf_reconstruct_np(const DevHF &d, double *phi_out, int64_t nb, size_t lds, hipStream_t s) {
     if (d.mat32)
-        hf_reconstruct_t<NP, float>(d, phi_out, nb, lds, s);
+        hf_reconstruct_t<NP, 0, 0, float>(d, phi_out, nb, lds, s);
     else
-        hf_reconstruct_t<NP, double>(d, phi_out, nb, lds, s);
+        hf_reconstruct_t<NP, 0, 0, double>(d, phi_out, nb, lds, s);
 }
 
 void launch_hf_reconstruct(const DevHF &d, double *phi_out, hipStream_t s) {
     const int64_t nb = d.nblk[0] + d.nblk[1];
     if (nb <= 0) return;
     const size_t lds = sizeof(double) * (size_t)d.npg_blk * (d.Nft + d.Np);
+    if (d.Np == 10 && d.Nft == 18 && d.G == 7) {   // volume order 2, face order 1, 7 groups
+        if (d.mat32) hf_reconstruct_t<10, 18, 7, float>(d, phi_out, nb, lds, s);
+        else hf_reconstruct_t<10, 18, 7, double>(d, phi_out, nb, lds, s);
+        hf_check_launch();
+        return;
+    }
     switch (d.Np) {
     case 1: hf_reconstruct_np<1>(d, phi_out, nb, lds, s); break;
     case 4: hf_reconstruct_np<4>(d, phi_out, nb, lds, s); break;
