@@ -85,17 +85,20 @@ int moc_sn_get_info(const moc_sn_ctx *ctx, moc_sn_info *info);
  * element_tile (host [n_elements], copied) assigns every element to one of n_tiles tiles.
  * For each direction group (the polar directions of one azimuth) the tiles are ordered by
  * their own dependencies (a tile feeds another through the faces between them) into tile
- * levels, one kernel launch each; a block takes one tile and direction group and walks
- * the tile's elements level by level, keeping the fluxes read inside the tile in LDS, and
- * only fluxes read by another tile go through storage slots. Convex tiles (for example
- * the pin cells of a lattice) never depend on each other in a cycle. The fluxes are the
- * same as with level-by-level sweeps bit for bit (the scalar flux is summed in direction
- * order either way). n_tiles = 0 with element_tile = NULL returns to level-by-level
- * sweeps. Errors: MOC_EINVAL (tile index out of range, an empty tile, a tile too large for
- * the LDS of one block (64 KiB: n_elements_in_tile x n_polar x G x 3 x the sweep
- * precision's size), tiles whose dependencies form a cycle for some direction, n_tiles > 0
- * with NULL element_tile or the reverse), MOC_ENOMEM, MOC_EHIP. Works on host-only
- * contexts too (the schedule is built and checked on the host). */
+ * levels, one kernel launch each; a block takes one tile and direction group, copies what
+ * its elements read into LDS and walks the tile's elements level by level, keeping the
+ * fluxes read inside the tile in LDS; only fluxes read by another tile go through storage
+ * slots. Convex tiles (for example the pin cells of a lattice) never depend on each other
+ * in a cycle. The fluxes are the same as with level-by-level sweeps bit for bit (the
+ * scalar flux is summed in direction order either way). n_tiles = 0 with element_tile =
+ * NULL returns to level-by-level sweeps; a refused tiling leaves the previous schedule in
+ * place. The LDS one block needs (moc_sn_info.tile_lds_bytes) grows with the tile's
+ * elements and the groups: on the order of 370 bytes per element at 7 groups in FP32,
+ * twice that in FP64. Errors: MOC_EINVAL (tile index out of range, an empty tile, tiles
+ * whose dependencies form a cycle for some direction, a tile whose block needs more LDS
+ * than the device gives one block (host-only contexts assume 160 KiB), n_tiles > 0 with
+ * NULL element_tile or the reverse), MOC_ENOMEM, MOC_EHIP. Works on host-only contexts
+ * too (the schedule is built and checked on the host). */
 int moc_sn_set_tiles(moc_sn_ctx *ctx, int32_t n_tiles, const int32_t *element_tile);
 
 /* Sweep timing with HIP events (moc_profile: sweeps, total, min and max ms). */
