@@ -23,7 +23,7 @@ static constexpr double kFourPiSn = 12.566370614359172953850573533118;
 // Where the local solve reads its data: straight from the global arrays (level schedule)
 // or from a tile task's copy in LDS (tiled schedule). Both present the same values, so the
 // solve below does the same arithmetic in the same order for either.
-template <typename Real> struct SnGlobalSrc {
+template <typename Real, int kG = 0> struct SnGlobalSrc {
     const SnStepArgs &a;
     int64_t k;
     int e, d;
@@ -33,19 +33,19 @@ template <typename Real> struct SnGlobalSrc {
     __device__ const Real *nrm(int f) const { return reinterpret_cast<const Real *>(a.nrm) + ((int64_t)e * 3 + f) * 2; }
     __device__ const Real *fmass(int f) const { return reinterpret_cast<const Real *>(a.fmass) + ((int64_t)e * 3 + f) * 6; }
     __device__ const Real *fcpl(int f) const { return reinterpret_cast<const Real *>(a.fcpl) + ((int64_t)e * 3 + f) * 9; }
-    __device__ Real sigt(int g) const { return reinterpret_cast<const Real *>(a.sigt)[(int64_t)e * a.G + g]; }
-    __device__ const Real *q(int g) const { return reinterpret_cast<const Real *>(a.q) + ((int64_t)e * a.G + g) * 3; }
+    __device__ Real sigt(int g) const { return reinterpret_cast<const Real *>(a.sigt)[(int64_t)e * ng() + g]; }
+    __device__ const Real *q(int g) const { return reinterpret_cast<const Real *>(a.q) + ((int64_t)e * ng() + g) * 3; }
     __device__ const Real *dir() const { return reinterpret_cast<const Real *>(a.dirs) + 3 * d; }
     __device__ int code(int f) const { return a.inflow[3 * k + f]; }
     __device__ int bwrite(int f) const { return a.bwrite[3 * k + f]; }
     __device__ int slot() const { return a.task_slot[k]; }
     // upstream flux of inflow code c >= 0 (a storage slot) or c <= -4 (boundary entry)
     __device__ const Real *upstream(int c, int g) const {
-        return c >= 0 ? reinterpret_cast<const Real *>(a.psi) + ((int64_t)c * a.G + g) * 3
-                      : reinterpret_cast<const Real *>(a.bnd_in) + ((int64_t)(-4 - c) * a.G + g) * 3;
+        return c >= 0 ? reinterpret_cast<const Real *>(a.psi) + ((int64_t)c * ng() + g) * 3
+                      : reinterpret_cast<const Real *>(a.bnd_in) + ((int64_t)(-4 - c) * ng() + g) * 3;
     }
     __device__ void store_local(int, int, const Real *) const {}
-    __device__ int ng() const { return a.G; }
+    __device__ int ng() const { return kG > 0 ? kG : a.G; }
 };
 
 // Size of the face block a direction group needs for inflow code c: the coupling matrix
@@ -246,8 +246,8 @@ __device__ __forceinline__ void sn_store_run(const SnStepArgs &a, int pp, bool v
 // scalar-flux moments are summed across the run with wavefront shuffles and stored once
 // per run (no atomics; k_sn_gather adds them after the last level). The upstream elements
 // of a task belong to earlier levels, whose angular fluxes sit in their storage slots.
-template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStepArgs a) {
-    const int G = a.G, TG = a.tgroup;
+template <typename Real, int kG, int kTG> __global__ void __launch_bounds__(256) k_sn_step(SnStepArgs a) {
+    const int G = kG > 0 ? kG : a.G, TG = kTG > 0 ? kTG : a.tgroup;
     const int runs_per_wave = 64 / TG;
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -261,11 +261,11 @@ template <typename Real> __global__ void __launch_bounds__(256) k_sn_step(SnStep
     const int64_t k = a.k0 + kg * TG + pp;
     int64_t r = 0;
     if (valid) {
-        const SnGlobalSrc<Real> S(a, k);
+        const SnGlobalSrc<Real, kG> S(a, k);
         sn_task<Real>(a, S, g, contrib);
         r = (int64_t)(S.d / TG) * a.T + S.e;
     }
-    sn_store_run<Real>(a, pp, valid, r, g, contrib);
+    sn_store_run<Real, kG, kTG>(a, pp, valid, r, g, contrib);
 }
 
 // Tiled schedule: one block per (tile, direction group) of one tile level. The block first
@@ -587,10 +587,14 @@ void launch_sn_step(const SnStepArgs &a, int precision, hipStream_t s) {
     const int64_t runs_per_wave = 64 / a.tgroup;
     const int64_t waves = (nrun + runs_per_wave - 1) / runs_per_wave;
     const int64_t blocks = (waves + 3) / 4;
-    if (precision == MOC_PREC_F64)
-        k_sn_step<double><<<(unsigned)blocks, 256, 0, s>>>(a);
-    else
-        k_sn_step<float><<<(unsigned)blocks, 256, 0, s>>>(a);
+    const bool g7p3 = a.G == 7 && a.tgroup == 3;   // the usual shape, sizes known to the compiler
+    if (precision == MOC_PREC_F64) {
+        if (g7p3) k_sn_step<double, 7, 3><<<(unsigned)blocks, 256, 0, s>>>(a);
+        else k_sn_step<double, 0, 0><<<(unsigned)blocks, 256, 0, s>>>(a);
+    } else {
+        if (g7p3) k_sn_step<float, 7, 3><<<(unsigned)blocks, 256, 0, s>>>(a);
+        else k_sn_step<float, 0, 0><<<(unsigned)blocks, 256, 0, s>>>(a);
+    }
     sn_check_launch();
 }
 
