@@ -111,7 +111,7 @@ template <typename Real, int kG, int kTG> struct SnLdsSrc {
 
 // The local solve of one task (element, direction) for group g, shared by both
 // schedules: A = Sigma_t M - (Omega . grad u) int u + outflow face terms, b = M q -
-// inflow face terms, Gaussian elimination with partial pivoting. Writes psi to the task's
+// inflow face terms, solved in closed form. Writes psi to the task's
 // storage slot (slot >= 0), to the boundary buffer on reflective outflow faces and, tiled,
 // to the tile's LDS copy; returns w psi in contrib.
 template <typename Real, typename Src>
@@ -160,40 +160,18 @@ __device__ __forceinline__ void sn_task(const SnStepArgs &a, const Src &S, int g
             for (int j = 0; j < 3; ++j) b[j] -= on * (Ef[3 * j] * u0 + Ef[3 * j + 1] * u1 + Ef[3 * j + 2] * u2);
         }
     }
-    // Gaussian elimination with partial pivoting; one correctly rounded reciprocal per
-    // pivot (three divisions instead of six; the hardware's approximate FP32 reciprocal
-    // biased the eigenvalue by 2e-7 after a dozen iterations and is not used)
-    Real rp[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        int piv = c;
-#pragma unroll
-        for (int r = c + 1; r < 3; ++r)
-            if (fabs(A[3 * r + c]) > fabs(A[3 * piv + c])) piv = r;
-        if (piv != c) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const Real tmp = A[3 * c + j];
-                A[3 * c + j] = A[3 * piv + j];
-                A[3 * piv + j] = tmp;
-            }
-            const Real tb = b[c];
-            b[c] = b[piv];
-            b[piv] = tb;
-        }
-        rp[c] = Real(1) / A[3 * c + c];
-#pragma unroll
-        for (int r = c + 1; r < 3; ++r) {
-            const Real f = A[3 * r + c] * rp[c];
-#pragma unroll
-            for (int j = c; j < 3; ++j) A[3 * r + j] -= f * A[3 * c + j];
-            b[r] -= f * b[c];
-        }
-    }
+    // x = adj(A) b / det(A): the cofactors C_ij of A, det along the first row, one
+    // division. No pivoting is needed: integrating the streaming term by parts gives
+    // u^T A u = Sigma_t |u|^2 + 1/2 sum over faces of int |Omega . n| u^2 > 0, so the
+    // symmetric part of A is positive definite and det(A) > 0.
+    const Real c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+    const Real c10 = A[2] * A[7] - A[1] * A[8], c11 = A[0] * A[8] - A[2] * A[6], c12 = A[1] * A[6] - A[0] * A[7];
+    const Real c20 = A[1] * A[5] - A[2] * A[4], c21 = A[2] * A[3] - A[0] * A[5], c22 = A[0] * A[4] - A[1] * A[3];
+    const Real rdet = Real(1) / (A[0] * c00 + A[1] * c01 + A[2] * c02);
     Real x[3];
-    x[2] = b[2] * rp[2];
-    x[1] = (b[1] - A[5] * x[2]) * rp[1];
-    x[0] = (b[0] - A[1] * x[1] - A[2] * x[2]) * rp[0];
+    x[0] = (c00 * b[0] + c10 * b[1] + c20 * b[2]) * rdet;
+    x[1] = (c01 * b[0] + c11 * b[1] + c21 * b[2]) * rdet;
+    x[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * rdet;
     const int sl = S.slot();
     if (sl >= 0) {
         Real *ps = psi + ((int64_t)sl * G + g) * 3;
