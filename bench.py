@@ -304,6 +304,16 @@ def sn_leg(args):
             f"{inf['tile_lds_bytes']} B of LDS per block")
         del s
         torch.cuda.empty_cache()
+    # time to a 1e-6 residual, tile by tile, FP32 (convergence checked every 10 iterations)
+    s = dfem.SNSolver(prob, precision="f32", max_iter=20000, check_every=10)
+    s.set_tiles(tile)
+    s.run_iterations(1)
+    r = s.solve(1e-6)
+    out["f32_solve"] = {"tol": 1e-6, "converged": r["converged"], "iterations": r["iterations"],
+                        "wall_ms": r["wall_ms"], "k": r["k"]}
+    log(f"DFEM-SN f32 tiles, solve to 1e-6: k = {r['k']:.6f}, {r['iterations']} iterations, {r['wall_ms']:.0f} ms")
+    del s
+    torch.cuda.empty_cache()
     return out
 
 
